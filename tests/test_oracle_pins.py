@@ -1,0 +1,444 @@
+"""Pins for the FP64 oracle: checks against things other than itself.
+
+Each test names the passage of the paper it follows.  Together they are chosen
+so that a plausible mistake in the oracle -- a dropped term, a wrong sign or
+axis, a transposed table, a wrong normalisation, a misplaced footprint -- fails
+at least one of them.
+"""
+import cmath
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from oracle import fx
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def small_case(seed, n_ant=5, N=16, C=2, T=3, kernels=None, gains=True, fmt=synth.IN_C64, cell_m=1.0):
+    rng = np.random.default_rng(1000 + seed)
+    if kernels is None:
+        kernels = [synth.random_kernel(rng, 2), synth.random_kernel(rng, 3)]
+    return synth.random_case(seed, n_ant, N, C, T, kernels, fmt=fmt, with_gains=gains,
+                             extent_m=3.0, cell_m=cell_m)
+
+
+# ---------------------------------------------------------------------------
+# Pin 1: brute-force pair sum (Sec. 5 / App. B, eq. wt-dirty-image-EPIC: the
+# image is the sum over antenna pairs a != b of weighted fringes).
+# ---------------------------------------------------------------------------
+
+def brute_force_pairs(geom, E, gains, c):
+    P = oracle.plan(geom)
+    N = P["N"]
+    T, _, na = E.shape
+    e = [[complex(E[t, c, a]) * (complex(gains[c, a]) if gains is not None else 1.0)
+          for a in range(na)] for t in range(T)]
+    G = []
+    for a in range(na):
+        K = geom.ktype_vals[geom.ant_ktype[a]]
+        k = K.shape[0]
+        Ga = [[0j] * N for _ in range(N)]
+        for r in range(N):
+            for q in range(N):
+                s = 0j
+                for u in range(k):
+                    for v in range(k):
+                        ph = ((P["iy0"][a] + u) * (r - N // 2) + (P["ix0"][a] + v) * (q - N // 2)) / N
+                        s += complex(K[u, v]) * cmath.exp(2j * math.pi * ph)
+                Ga[r][q] = s
+        G.append(Ga)
+    img = np.zeros((N, N))
+    for r in range(N):
+        for q in range(N):
+            acc = 0j
+            for t in range(T):
+                for a in range(na):
+                    for b in range(na):
+                        if a != b:
+                            acc += e[t][a] * e[t][b].conjugate() * G[a][r][q] * G[b][r][q].conjugate()
+            img[r, q] = acc.real / T
+    return img
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_brute_force_pair_sum(seed):
+    w = small_case(seed)
+    for c in range(w.geom.n_chan):
+        ref = brute_force_pairs(w.geom, w.E, w.gains, c)
+        got = oracle.moff_channel(w.geom, w.E, w.gains, c)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref)) + 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Pin 2: library special case -- the direct DFT is N^2 * ifft2 of the padded
+# grid, shifted so that index N/2 is the origin (Sec. 3, spatial transform).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [8, 32, 64])
+def test_direct_dft_is_library_ifft(N):
+    rng = np.random.default_rng(N)
+    L = N // 2
+    Eg = rng.standard_normal((3, L, L)) + 1j * rng.standard_normal((3, L, L))
+    pad = np.zeros((3, N, N), complex)
+    pad[:, :L, :L] = Eg
+    lib = np.fft.fftshift(np.fft.ifft2(pad) * N * N, axes=(-2, -1))
+    got = oracle.image_field(Eg, N)
+    assert np.max(np.abs(got - lib)) < 1e-11 * np.max(np.abs(lib))
+
+
+def test_literal_sum_matches_matrix_form():
+    rng = np.random.default_rng(7)
+    Eg = rng.standard_normal((2, 8, 8)) + 1j * rng.standard_normal((2, 8, 8))
+    a = oracle.image_field(Eg, 16)
+    b = oracle.image_field_literal(Eg, 16)
+    assert np.max(np.abs(a - b)) < 1e-11 * np.max(np.abs(b))
+
+
+# ---------------------------------------------------------------------------
+# Pin 3a: the FX route with discrete footprints equals MOFF exactly
+# (Sec. 2: eq. dirty-image-FX == eq. dirty-image-MOFF via eq. e-field-conv).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("case", ["config1", "hetero_gains", "ci4", "autos_kept"])
+def test_fx_discrete_identity(case):
+    if case == "config1":
+        w = synth.make_config(1)
+    elif case == "hetero_gains":
+        w = small_case(3, n_ant=9, N=32, C=2, T=4)
+    elif case == "ci4":
+        w = small_case(4, n_ant=7, N=16, C=1, T=5, fmt=synth.IN_CI4)
+    else:
+        w = small_case(5, n_ant=6, N=16, C=1, T=3)
+        w.geom.flags |= synth.AUTOCORR_NONE
+    for c in range(w.geom.n_chan):
+        moff = oracle.moff_channel(w.geom, w.E, w.gains, c)
+        fxi = fx.fx_discrete_image(w.geom, w.E, w.gains, c)
+        scale = np.max(np.abs(moff))
+        assert np.max(np.abs(moff - fxi)) <= 1e-12 * scale
+
+
+def test_fx_pairs_normalisation():
+    """NORM_PAIRS divides by Na (Na - 1) (eq. wt-dirty-image-EPIC)."""
+    w = small_case(6, n_ant=6, N=16, C=1, T=2)
+    base = oracle.moff_channel(w.geom, w.E, w.gains, 0)
+    w.geom.flags |= synth.NORM_PAIRS
+    normed = oracle.moff_channel(w.geom, w.E, w.gains, 0)
+    fxi = fx.fx_discrete_image(w.geom, w.E, w.gains, 0)
+    assert np.allclose(normed * 30.0, base, rtol=1e-13, atol=1e-12)
+    assert np.allclose(fxi, normed, rtol=1e-12, atol=1e-12 * np.abs(normed).max())
+
+
+# ---------------------------------------------------------------------------
+# Pin 3b: analytic footprints agree to within gridding coarseness and converge
+# as the grid is refined (Sec. 4.3: differences arise from gridding coarseness
+# and vanish in the limit of infinitesimal grid spacing).
+# ---------------------------------------------------------------------------
+
+def test_fx_analytic_converges_with_grid_refinement():
+    side = 4.0            # square top-hat apertures, metres
+    rng = np.random.default_rng(11)
+    xy = rng.uniform(0.0, 24.0, size=(12, 2))
+    lam = 8.0             # wavelength fixed: the image pixel is lam / (N cell)
+    freq = np.array([synth.C_LIGHT / lam])
+    T = 2
+    Es = (rng.standard_normal((T, 1, 12)) + 1j * rng.standard_normal((T, 1, 12))).astype(np.complex64)
+    errs = []
+    for refine in (1, 2, 4):
+        cell = 2.0 / refine
+        k = int(round(side / cell))
+        N = 64 * refine
+        geom = synth.Geometry(ant_xy=xy, ktype_k=[k], ktype_vals=[synth.kernel_tophat(k)],
+                              ant_ktype=np.zeros(12, np.int32), freq_hz=freq, grid_n=N,
+                              cell_m=cell, flags=synth.IN_C64)
+        moff = oracle.moff_channel(geom, Es, None, 0)
+        fxa = fx.fx_analytic_image(geom, Es, None, 0, side)
+        # compare over the pixels common to every refinement (same l, m range)
+        c0 = N // 2
+        sl = slice(c0 - 32, c0 + 32)
+        d = moff[sl, sl] - fxa[sl, sl]
+        errs.append(np.sqrt(np.mean(d ** 2)) / np.sqrt(np.mean(fxa[sl, sl] ** 2)))
+    # first-order convergence in the cell size: each halving at least ~halves the error
+    assert errs[0] < 0.6
+    assert errs[1] < 0.6 * errs[0] and errs[2] < 0.6 * errs[1]
+
+
+def test_fx_analytic_psf_close():
+    """The synthesized beams (a unit point source at the phase centre, so every
+    visibility is 1) of MOFF and the analytic FX route agree to a few per cent
+    of the peak at the configuration-1 gridding (Sec. 4.3 reports < 0.5 % for the
+    paper's finer MWA gridding; this grid is coarser, so the bound is looser)."""
+    w = synth.make_config(1, n_time=1)
+    E = np.ones((1, 1, 16), np.complex64)
+    moff = oracle.moff_channel(w.geom, E, None, 0)
+    P = oracle.plan(w.geom)
+    fxa = fx.fx_analytic_image(w.geom, E, None, 0, 2 * P["cell_m"])
+    peak = np.abs(fxa).max()
+    assert np.max(np.abs(moff - fxa)) / peak < 0.35
+    rel = np.abs(moff - fxa) / peak
+    assert np.mean(rel < 0.05) > 0.5
+
+
+# ---------------------------------------------------------------------------
+# Pin 4: Parseval for the unnormalised transform, before and after removal.
+# ---------------------------------------------------------------------------
+
+def test_parseval():
+    w = small_case(8, n_ant=7, N=32, C=1, T=3)
+    P = oracle.plan(w.geom)
+    img, parts = oracle.moff_channel(w.geom, w.E, w.gains, 0, keep=True)
+    N = P["N"]
+    Y, Eg, e = parts["Y"], parts["Eg"], parts["e"]
+    lhs = np.sum(np.abs(Y) ** 2, axis=(1, 2))
+    rhs = N * N * np.sum(np.abs(Eg) ** 2, axis=(1, 2))
+    assert np.allclose(lhs, rhs, rtol=1e-12)
+    kn = np.array([np.sum(np.abs(P["kernels"][p]) ** 2) for p in P["ant_ktype"]])
+    self_sum = np.sum(np.abs(e) ** 2 * kn[None, :], axis=1)
+    expect = N * N * np.mean(np.sum(np.abs(Eg) ** 2, axis=(1, 2)) - self_sum)
+    assert abs(img.sum() - expect) <= 1e-10 * abs(np.abs(parts["S"]).sum() / 3)
+
+
+# ---------------------------------------------------------------------------
+# Pin 5: a point source on the grid (Sec. 2: measured field of a plane wave;
+# Sec. 5: homogeneous array image |W^G|^2 |W^I|^2 I_D with isotropic W^I).
+# ---------------------------------------------------------------------------
+
+def _point_source_case(kernels, ant_types, k_l, k_m, N=32, cell=2.0, n_ant=10, seed=21):
+    rng = np.random.default_rng(seed)
+    lam = 6.0
+    freq = np.array([synth.C_LIGHT / lam])
+    cells = rng.choice(N // 2 - 8, size=(n_ant, 2), replace=True)
+    xy = cells.astype(np.float64) * cell
+    geom = synth.Geometry(ant_xy=xy, ktype_k=[K.shape[0] for K in kernels], ktype_vals=kernels,
+                          ant_ktype=np.asarray(ant_types, np.int32), freq_hz=freq, grid_n=N,
+                          cell_m=cell, flags=synth.IN_C64)
+    l0 = k_l * lam / (N * cell)
+    m0 = k_m * lam / (N * cell)
+    E = synth.efield_stream(rng, xy, freq, 3, np.array([[l0, m0]]), np.array([1.0]), 0.0,
+                            dtype=np.complex128)
+    return geom, E, cells
+
+
+def _khat(K, N, k_m, k_l):
+    pad = np.zeros((N, N), complex)
+    k = K.shape[0]
+    pad[:k, :k] = K
+    return (np.fft.ifft2(pad) * N * N)[k_m % N, k_l % N]
+
+
+@pytest.mark.parametrize("k_l,k_m", [(0, 0), (3, -5), (-7, 2)])
+def test_point_source_closed_form(k_l, k_m):
+    kernels = [synth.kernel_dipole3().astype(np.complex128), synth.kernel_tophat(2).astype(np.complex128)]
+    types = [0, 1, 0, 1, 1, 0, 0, 1, 0, 0]
+    geom, E, cells = _point_source_case(kernels, types, k_l, k_m)
+    N = geom.grid_n
+    img = oracle.moff_channel(geom, E, None, 0)
+    tot = 0j
+    selfp = 0.0
+    for a, p in enumerate(types):
+        k = kernels[p].shape[0]
+        h = (k - 1) // 2 if k % 2 == 1 else k // 2 - 1
+        kh = _khat(kernels[p], N, k_m, k_l)
+        tot += cmath.exp(-2j * math.pi * h * (k_m + k_l) / N) * kh
+        selfp += abs(kh) ** 2
+    expect = abs(tot) ** 2 - selfp
+    got = img[N // 2 + k_m, N // 2 + k_l]
+    assert abs(got - expect) <= 1e-10 * abs(expect)
+
+
+def test_point_source_peak_position():
+    # 1x1 tables: the image is the array factor minus Na, maximal exactly at the source
+    kernels = [np.ones((1, 1), np.complex128)]
+    geom, E, cells = _point_source_case(kernels, [0] * 10, 5, -3, seed=4)
+    img = oracle.moff_channel(geom, E, None, 0)
+    N = geom.grid_n
+    r, q = np.unravel_index(np.argmax(img), img.shape)
+    assert (r, q) == (N // 2 - 3, N // 2 + 5)
+    assert abs(img[r, q] - (100 - 10)) < 1e-9
+
+
+def test_homogeneous_power_pattern_weighting():
+    """Homogeneous array, single on-grid source: the image at the source pixel
+    equals (Na^2 - Na) |Khat|^2 (eq. wt-dirty-image-homogeneous with W^I = 1)."""
+    kernels = [synth.kernel_airy_like(7).astype(np.complex128)]
+    for k_l, k_m in [(0, 0), (2, 1), (-4, 3)]:
+        geom, E, _ = _point_source_case(kernels, [0] * 10, k_l, k_m, N=64, seed=9)
+        img = oracle.moff_channel(geom, E, None, 0)
+        kh = _khat(kernels[0], 64, k_m, k_l)
+        # all antennas share h, so the array factor at the source is exactly Na
+        assert abs(img[32 + k_m, 32 + k_l] - 90.0 * abs(kh) ** 2) <= 1e-10 * 100 * abs(kh) ** 2
+
+
+# ---------------------------------------------------------------------------
+# Pin 6: invariants.
+# ---------------------------------------------------------------------------
+
+def test_invariants():
+    w = small_case(12, n_ant=8, N=32, C=1, T=4)
+    base = oracle.moff_channel(w.geom, w.E, w.gains, 0)
+    scale = np.abs(base).max()
+    # a global phase, and an independent phase per time sample, change nothing
+    ph = np.exp(1j * np.linspace(0.3, 2.9, 4))[:, None, None]
+    assert np.max(np.abs(oracle.moff_channel(w.geom, (w.E * ph).astype(np.complex64), w.gains, 0) - base)) < 1e-5 * scale
+    # calibration is a pre-multiplication of the field
+    pre = w.E.astype(np.complex128) * w.gains.astype(np.complex128)[None]
+    assert np.max(np.abs(oracle.moff_channel(w.geom, pre, None, 0)
+                         - oracle.moff_channel(w.geom, w.E.astype(np.complex128), w.gains.astype(np.complex128), 0))) < 1e-12 * scale
+    # quadratic in the field
+    assert np.allclose(oracle.moff_channel(w.geom, w.E.astype(np.complex128) * 3.0, w.gains, 0), 9.0 * base, rtol=1e-12, atol=1e-10 * scale)
+    # linear in the per-sample contributions: split integration == whole
+    a = oracle.moff_channel(w.geom, w.E[:1], w.gains, 0)
+    b = oracle.moff_channel(w.geom, w.E[1:], w.gains, 0)
+    assert np.allclose((a * 1 + b * 3) / 4, base, rtol=1e-12, atol=1e-12 * scale)
+
+
+def test_flagged_antenna_equals_deleted():
+    """A flag is a zero weight on the antenna (App. A: flags carried as weights)."""
+    w = small_case(13, n_ant=7, N=32, C=1, T=3)
+    j = 4
+    g = w.gains.copy()
+    g[:, j] = 0
+    flagged = oracle.moff_channel(w.geom, w.E, g, 0)
+    keep = np.array([a for a in range(7) if a != j])
+    geom2 = synth.Geometry(ant_xy=w.geom.ant_xy[keep], ktype_k=w.geom.ktype_k, ktype_vals=w.geom.ktype_vals,
+                           ant_ktype=w.geom.ant_ktype[keep], freq_hz=w.geom.freq_hz, grid_n=32,
+                           cell_m=w.geom.cell_m, flags=w.geom.flags)
+    deleted = oracle.moff_channel(geom2, w.E[:, :, keep], w.gains[:, keep], 0)
+    assert np.max(np.abs(flagged - deleted)) < 1e-12 * np.abs(deleted).max()
+
+
+# ---------------------------------------------------------------------------
+# Pin 7: the self-power table (Sec. 4.2 and its figure: the uv autocorrelation
+# weights of an aperture, normalised to unit sum, give a unit-peak power pattern).
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("which", ["dipole", "airy", "random"])
+def test_power_pattern(which):
+    N = 32
+    if which == "dipole":
+        K = synth.kernel_dipole3().astype(complex)
+    elif which == "airy":
+        K = synth.kernel_airy_like(7).astype(complex)
+    else:
+        K = synth.random_kernel(np.random.default_rng(3), 4).astype(complex)
+    Pp = oracle.power_pattern(K, N)
+    k = K.shape[0]
+    pad = np.zeros((N, N), complex)
+    pad[:k, :k] = K
+    lib = np.abs(np.fft.fftshift(np.fft.ifft2(pad) * N * N)) ** 2
+    assert np.allclose(Pp, lib, rtol=1e-12, atol=1e-12 * lib.max())
+    assert abs(Pp[N // 2, N // 2] - abs(K.sum()) ** 2) < 1e-12 * Pp.max()
+    # Wiener-Khinchin: the transform of the uv autocorrelation weights, normalised to unit sum
+    X = fx.kernel_xcorr(K, K)
+    D = fx.lag_dft_matrix(N, k)
+    pat = (D @ X @ D.T).real / X.sum().real
+    assert np.allclose(pat * X.sum().real, Pp, rtol=1e-10, atol=1e-10 * Pp.max())
+    if which != "random":     # non-negative apertures: unit peak at the phase centre
+        assert abs(pat.max() - 1.0) < 1e-12 and abs(pat[N // 2, N // 2] - 1.0) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Pin 8: the antenna-to-grid mapping.
+# ---------------------------------------------------------------------------
+
+def test_cell_indices_ties_and_negative():
+    cell = 0.5     # exact in binary, so x / cell is exact
+    # antenna centres exactly half way between cells round up; negative coordinates too
+    xy = np.array([[0.25, -0.25], [-1.25, 0.75], [2.0, -3.0], [1.75, 0.0]])
+    ix, iy = oracle.cell_indices(xy, np.array([1, 1, 1, 1]), cell, 64)
+    # floor(x / cell + 0.5): 0.5 -> 1, -2.5 -> -2, 4 -> 4, 3.5 -> 4 ; shift by min (-2)
+    assert list(ix) == [3, 0, 6, 6]
+    # y: -0.5 -> 0, 1.5 -> 2, -6 -> -6, 0 -> 0 ; shift by -6
+    assert list(iy) == [6, 8, 0, 6]
+    # even k: footprint lower-left = floor(x / cell - (k - 1) / 2 + 0.5)
+    ix2, _ = oracle.cell_indices(np.array([[0.0, 0.0], [0.5, 0.0], [0.75, 0.0]]), np.array([2, 2, 2]), cell, 64)
+    assert list(ix2) == [0, 1, 1]
+    ix4, _ = oracle.cell_indices(np.array([[0.0, 0.0], [0.6, 0.0]]), np.array([4, 3]), 1.0, 64)
+    # k=4: floor(0 - 1.5 + 0.5) = -1 ; k=3: floor(0.6 - 1 + 0.5) = 0 ; shifted by -1
+    assert list(ix4) == [0, 1]
+
+
+def test_footprint_overflow():
+    geom = synth.Geometry(ant_xy=np.array([[0.0, 0.0], [20.0, 0.0]]), ktype_k=[3],
+                          ktype_vals=[synth.kernel_dipole3()], ant_ktype=np.zeros(2, np.int32),
+                          freq_hz=np.array([50e6]), grid_n=32, cell_m=1.0)
+    with pytest.raises(oracle.FootprintOverflow):
+        oracle.plan(geom)
+    geom.ant_xy = np.array([[0.0, 0.0], [13.0, 0.0]])     # 13 + 3 = 16 = L: fits exactly
+    oracle.plan(geom)
+
+
+def test_default_cell_size_rule():
+    w1 = synth.make_config(1)
+    assert oracle.plan(w1.geom)["cell_m"] == pytest.approx(synth.C_LIGHT / 60e6 / 2, rel=1e-15)
+    w2 = synth.make_config(2, n_time=1, n_chan=4)
+    lam_min = synth.C_LIGHT / w2.geom.freq_hz.max()
+    assert oracle.plan(w2.geom)["cell_m"] == pytest.approx(lam_min / 2, rel=1e-15)
+    w3 = synth.make_config(3, n_time=1, n_chan=2)
+    P3 = oracle.plan(w3.geom)
+    span = max(np.ptp(w3.geom.ant_xy[:, 0]), np.ptp(w3.geom.ant_xy[:, 1]))
+    assert P3["cell_m"] == pytest.approx(span / (128 - 7 - 1), rel=1e-15)
+    assert int((P3["ix0"] + 7).max()) <= 128 and int((P3["iy0"] + 7).max()) <= 128
+
+
+# ---------------------------------------------------------------------------
+# Golden fixtures derived by hand.
+# ---------------------------------------------------------------------------
+
+def _read_table(path):
+    rows = []
+    with open(path) as f:
+        for line in f:
+            s = line.strip()
+            if not s or s.startswith("#"):
+                continue
+            rows.append(s.split())
+    return rows
+
+
+def _golden_geom(cells_xy, kernel, n):
+    return synth.Geometry(ant_xy=np.asarray(cells_xy, np.float64), ktype_k=[kernel.shape[0]],
+                          ktype_vals=[kernel.astype(np.complex64)], ant_ktype=np.zeros(len(cells_xy), np.int32),
+                          freq_hz=np.array([50e6]), grid_n=n, cell_m=1.0, flags=synth.IN_C64)
+
+
+def test_golden_two_antenna_fringes(golden_dir):
+    one = np.ones((1, 1))
+    cases = {
+        "A": (_golden_geom([[0, 0], [1, 0]], one, 8), [1, 1], 0),
+        "B": (_golden_geom([[0, 0], [1, 0]], one, 8), [1, 1j], 0),
+        "C": (_golden_geom([[0, 0], [0, 1]], one, 8), [1, 1j], 0),
+        "D": (_golden_geom([[0, 0]], np.array([[1, 2], [0, 0]]), 8), [1], synth.AUTOCORR_NONE),
+        "E": (_golden_geom([[0, 0]], np.array([[1, 0], [1j, 0]]), 8), [1], synth.AUTOCORR_NONE),
+        "F": (_golden_geom([[0, 0]], np.array([[1, 2], [0, 0]]), 8), [1], 0),
+    }
+    rows = _read_table(os.path.join(golden_dir, "two_antenna_fringes.txt"))
+    assert len(rows) == len(cases)
+    for name, axis, *vals in rows:
+        geom, e, flags = cases[name]
+        geom.flags = flags
+        E = np.asarray(e, np.complex128).reshape(1, 1, -1)
+        img = oracle.moff_channel(geom, E, None, 0)
+        want = np.asarray([float(v) for v in vals])
+        prof = img if axis == "r" else img.T       # prof[j, other] varies with j
+        for j in range(8):
+            assert np.allclose(prof[j], want[j], atol=1e-12), (name, j, prof[j], want[j])
+
+
+def test_golden_ci4_decode(golden_dir):
+    rows = _read_table(os.path.join(golden_dir, "ci4_decode.txt"))
+    raw = np.array([int(r[0], 16) for r in rows], np.uint8)
+    got = oracle.decode_ci4(raw)
+    for (h, re, im), z in zip(rows, got):
+        assert z == complex(int(re), int(im)), h
+
+
+def test_ci4_roundtrip_all_bytes():
+    raw = np.arange(256, dtype=np.uint8)
+    z = oracle.decode_ci4(raw)
+    again = synth.quantise_ci4(z.astype(np.complex64), rms_levels=float(np.sqrt(np.mean(np.abs(z) ** 2) / 2)))
+    assert np.array_equal(again, raw)
