@@ -1,0 +1,254 @@
+/*
+ * moff.h -- C ABI of the MI355X MOFF direct-imaging library.
+ *
+ * The Modular Optimal Frequency Fourier (MOFF) imager forms, for every time
+ * sample t and frequency channel c (one "frame"), the image-plane field of the
+ * calibrated, gridded antenna E-fields, squares it and averages it over time
+ * (Thyagarajan et al., Sec. 2, MOFF imaging equation, eq. dirty-image-MOFF):
+ *
+ *   e[t,c,a]   = g[c,a] * E[t,c,a]                     calibration (Sec. 3)
+ *   Eg[t,c]    = sum_a K_{p(a)} placed at (iy0_a,ix0_a) * e[t,c,a]
+ *                                                      gridding (Sec. 3, E(r) = M E(a))
+ *   Y[t,c]     = 2-D DFT of Eg zero-padded from N/2 x N/2 to N x N
+ *                (exponent +2 pi i, unnormalised, pixel N/2 = phase centre)
+ *                                                      spatial transform (Sec. 3)
+ *   S[c]       = sum_t |Y[t,c]|^2                      squaring + time average (Sec. 3)
+ *   A[c,p]     = sum_t sum_{a of type p} |e[t,c,a]|^2
+ *   P_p        = |DFT of K_p|^2                        antenna power response (Sec. 4.2)
+ *   I[c]       = (S[c] - sum_p A[c,p] P_p) / T         self-power removal (Sec. 4.2)
+ *
+ * Image pixel (r, q) of channel c is direction m = (r - N/2) lambda_c / (N cell),
+ * l = (q - N/2) lambda_c / (N cell): rows follow y/m, columns follow x/l.
+ *
+ * Conventions for every call:
+ *   - Geometry arrays are HOST pointers, copied at plan creation.
+ *   - Data pointers (E, gains, grids, images, accumulators) are DEVICE pointers
+ *     on the plan's device, owned by the caller, at least 16-byte aligned.
+ *   - Calls enqueue work on `hip_stream` (a hipStream_t, NULL = default stream)
+ *     and return without synchronising; argument validation is synchronous.
+ *   - A plan is immutable after creation; it owns its device tables and a
+ *     workspace, so concurrent calls must use different plans.
+ *   - On any error status the contents of output buffers are unspecified.
+ *   - NaN / Inf inputs propagate; they are not checked.
+ */
+#ifndef MOFF_H
+#define MOFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MOFF_ABI_VERSION 1
+
+typedef struct moff_plan_s* moff_plan;
+
+typedef enum {
+  MOFF_OK = 0,
+  MOFF_ERR_INVALID_ARG = 1,         /* null pointer, non-positive size, bad flag, bad kernel table */
+  MOFF_ERR_GRID_NOT_POW2 = 2,       /* grid_n not a power of two in [8, 256] */
+  MOFF_ERR_FOOTPRINT_OVERFLOW = 3,  /* footprints do not fit in the grid_n/2 aperture region */
+  MOFF_ERR_UNSUPPORTED = 4,         /* valid request this build does not implement (sizes, host-only plan) */
+  MOFF_ERR_NOMEM = 5,               /* host or device allocation failed */
+  MOFF_ERR_HIP = 6                  /* a HIP runtime call or kernel launch failed */
+} moff_status;
+
+/* geometry.flags bits */
+enum {
+  MOFF_IN_C64 = 0,         /* E is complex64: interleaved float32 (re, im) */
+  MOFF_IN_CI4 = 1,         /* E is one byte per sample: re = high nibble, im = low nibble,
+                              two's complement in [-8, 7] */
+  MOFF_AUTOCORR_NONE = 2,  /* keep the antenna self power: I = S / T */
+  MOFF_NORM_PAIRS = 4      /* multiply the image by 1 / (n_ant (n_ant - 1)) (Sec. 5,
+                              eq. wt-dirty-image-EPIC: average over antenna pairs) */
+};
+
+/*
+ * Problem statement (Sec. 3, antenna-to-grid mapping): antenna positions and
+ * illumination kernels, channel frequencies and the grid size.
+ *
+ *   n_ant, ant_xy_m : antenna positions, host float64 [n_ant][2] in metres,
+ *                     (x, y); 2 <= n_ant <= 4000.
+ *   n_ktypes, ktype_k, ktype_vals :
+ *                     illumination tables, one per antenna type; type p is a
+ *                     square ktype_k[p] x ktype_k[p] complex table (1 <= k <= 15),
+ *                     row index u along y, column index v along x. ktype_vals
+ *                     holds all tables back to back as interleaved float32
+ *                     (re, im), row-major. 1 <= n_ktypes <= 4.
+ *   ant_ktype       : host int32 [n_ant], type of each antenna.
+ *   n_chan, freq_hz : channel centre frequencies, host float64 [n_chan] (> 0).
+ *                     They set the pixel scale and the default cell size only;
+ *                     footprints are channel-independent cells.
+ *   grid_n          : FFT side N after two-fold zero padding; a power of two in
+ *                     [8, 256]. Footprints must fit in the N/2 x N/2 aperture region.
+ *   cell_m          : grid spacing in metres; 0 selects the default: half the
+ *                     shortest wavelength, widened if needed so that the layout
+ *                     span plus the widest footprint and one cell of slack fits
+ *                     in N/2 cells.
+ *   flags           : MOFF_IN_* | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS.
+ *
+ * Footprint placement: antenna a with a k x k table covers cells
+ * ix0_a .. ix0_a + k - 1 with ix0_a = floor(x_a / cell - (k - 1) / 2 + 0.5)
+ * (nearest cell, ties round up), the same for y; indices are then shifted so
+ * the smallest ix0 and the smallest iy0 are 0.
+ */
+typedef struct {
+  int32_t n_ant;
+  const double* ant_xy_m;
+  int32_t n_ktypes;
+  const int32_t* ktype_k;
+  const float* ktype_vals;
+  const int32_t* ant_ktype;
+  int32_t n_chan;
+  const double* freq_hz;
+  int32_t grid_n;
+  double cell_m;
+  uint32_t flags;
+} moff_geometry;
+
+/* ABI version of the loaded library (MOFF_ABI_VERSION at build time). */
+int moff_abi_version(void);
+
+/* Static, NUL-terminated description of a status code. Never NULL. */
+const char* moff_status_str(moff_status s);
+
+/*
+ * Build a plan: the footprint cells (FP64 arithmetic), the gather tables keyed
+ * by grid cell, the power patterns P_p (FP64 direct DFT, rounded to float32)
+ * and the transform twiddles, computed once (Sec. 3: the mapping "must only be
+ * determined once").  hip_device >= 0 uploads the tables to that device;
+ * hip_device < 0 builds a host-only plan for moff_plan_query /
+ * moff_plan_power_pattern (compute calls on it return MOFF_ERR_UNSUPPORTED).
+ * *out receives the plan on MOFF_OK and NULL otherwise.
+ */
+moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_plan* out);
+
+/* Release a plan and its device memory. NULL is accepted. Synchronises the device. */
+moff_status moff_plan_destroy(moff_plan plan);
+
+/*
+ * Host copies of the plan's placement results. Any output may be NULL.
+ *   cells        : int32 [n_ant][2] = (ix0_a, iy0_a) lower-left footprint cell
+ *   cell_m       : grid spacing used, metres
+ *   lm_per_pixel : float64 [n_chan], direction-cosine step lambda_c / (N cell)
+ *   grid_n       : N
+ */
+moff_status moff_plan_query(moff_plan plan, int32_t* cells, double* cell_m,
+                            double* lm_per_pixel, int32_t* grid_n);
+
+/*
+ * Host copy of the float64 power pattern P_p of kernel type `ktype`
+ * (Sec. 4.2, the antenna power response), out = float64 [N][N] in image pixel
+ * order.
+ */
+moff_status moff_plan_power_pattern(moff_plan plan, int32_t ktype, double* out);
+
+/*
+ * Diagnostic copy of the fused kernel's cell-keyed gather program for output
+ * column class `w` (0 <= w < *n_classes).  Call with out = NULL to get the
+ * sizes.  out receives uint32 [prog_len][n_threads][2] entries (x, y):
+ *   x bits 0..11 antenna slot (n_ant = the zero slot), bits 12..22 weight
+ *   index, bit 31 "cell complete: store"; y = LDS element index of the cell
+ *   in the folded grid, row pitch *row_pitch.
+ * weights (may be NULL) receives complex64 [n_weights] for class w:
+ *   K[tap] * exp(+2 pi i j w / n_classes) at index j * n_taps + tap.
+ * Used by host-side tests; the data never changes after plan creation.
+ */
+moff_status moff_plan_gather_program(moff_plan plan, int32_t w, uint32_t* out, float* weights,
+                                     int32_t* prog_len, int32_t* n_threads, int32_t* n_classes,
+                                     int32_t* row_pitch, int32_t* n_weights);
+
+/*
+ * Kernel timing.  With timing enabled, every fused call records a pair of HIP
+ * events on its stream around the fused kernel (not the small reduction that
+ * may follow it).  moff_plan_last_kernel_ms waits for the most recent fused
+ * call and returns that kernel's duration in milliseconds (MOFF_ERR_INVALID_ARG
+ * if timing is off or no fused call has been made since it was turned on).
+ */
+moff_status moff_plan_set_timing(moff_plan plan, int enable);
+moff_status moff_plan_last_kernel_ms(moff_plan plan, double* ms);
+
+/* ---------------------------------------------------------------------------
+ * Fused path: one kernel per call runs ingest, calibration, gridding, the
+ * padded 2-D FFT, squaring and accumulation for all frames; the image is
+ * produced without any per-frame HBM round trip.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Time-averaged image with self power removed (or kept, MOFF_AUTOCORR_NONE).
+ *   E_dev     : [n_time][n_chan][n_ant] samples in the plan's input format
+ *   n_time    : number of time samples T >= 1 (the integration)
+ *   gains_dev : complex64 [n_chan][n_ant] calibration gains g, or NULL for g = 1;
+ *               a zero gain flags the antenna (App. A: flags are weights)
+ *   image_dev : float32 [n_chan][N][N], overwritten with I
+ */
+moff_status moff_image(moff_plan plan, const void* E_dev, int64_t n_time,
+                       const float* gains_dev, float* image_dev, void* hip_stream);
+
+/*
+ * Streaming form: add the frames of E to running sums.
+ *   S_dev : float32 [n_chan][N][N], S += sum_t |Y|^2
+ *   A_dev : float64 [n_chan][n_ktypes], A += sum_t sum_{a of type p} |e|^2
+ * accumulate(E1) then accumulate(E2) equals accumulate(E1 ++ E2) up to rounding.
+ */
+moff_status moff_accumulate(moff_plan plan, const void* E_dev, int64_t n_time,
+                            const float* gains_dev, float* S_dev, double* A_dev,
+                            void* hip_stream);
+
+/*
+ * image = (S - sum_p A[:, p] P_p) / n_time_total (times 1/(n_ant(n_ant-1)) with
+ * MOFF_NORM_PAIRS; without the subtraction under MOFF_AUTOCORR_NONE).
+ * S_dev, A_dev as produced by moff_accumulate; image_dev float32 [n_chan][N][N].
+ */
+moff_status moff_finalize(moff_plan plan, const float* S_dev, const double* A_dev,
+                          int64_t n_time_total, float* image_dev, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * Staged path: each step of the method as its own kernel with its result in
+ * HBM.  Used to check each step against the oracle and as the plain baseline.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Calibration + gridding (Sec. 3, E(r) = M(r,a) E(a)):
+ *   eg_dev : complex64 [n_time][n_chan][N/2][N/2], Eg of every frame, overwritten.
+ */
+moff_status moff_grid(moff_plan plan, const void* E_dev, int64_t n_time,
+                      const float* gains_dev, float* eg_dev, void* hip_stream);
+
+/*
+ * Self power of the calibrated fields:
+ *   A_dev : float64 [n_chan][n_ktypes], A += sum_t sum_{a of type p} |g E|^2.
+ */
+moff_status moff_self_power(moff_plan plan, const void* E_dev, int64_t n_time,
+                            const float* gains_dev, double* A_dev, void* hip_stream);
+
+/*
+ * Zero padding + 2-D transform of gridded frames (Sec. 3, spatial transform):
+ *   eg_dev : complex64 [n_frames][N/2][N/2]
+ *   y_dev  : complex64 [n_frames][N][N], Y[r][q] = sum Eg[iy][ix]
+ *            exp(+2 pi i (iy (r - N/2) + ix (q - N/2)) / N), overwritten.
+ */
+moff_status moff_fft2(moff_plan plan, const float* eg_dev, int64_t n_frames,
+                      float* y_dev, void* hip_stream);
+
+/*
+ * Squaring + time accumulation (Sec. 3, time averaging):
+ *   y_dev : complex64 [n_time][n_chan][N][N]
+ *   S_dev : float32 [n_chan][N][N], S += sum_t |Y|^2
+ */
+moff_status moff_detect_accumulate(moff_plan plan, const float* y_dev, int64_t n_time,
+                                   float* S_dev, void* hip_stream);
+
+/*
+ * The staged pipeline end to end (grid -> fft2 -> detect -> finalize), in
+ * time chunks through the plan's workspace; same output as moff_image.
+ */
+moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
+                              const float* gains_dev, float* image_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOFF_H */

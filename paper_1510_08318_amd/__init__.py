@@ -1,0 +1,249 @@
+"""MI355X MOFF direct imager: Python binding of the HIP library (include/moff.h).
+
+`Plan` marshals a geometry and torch device tensors into the C ABI; every step
+of the imaging path (calibration, gridding, the padded 2-D FFT, squaring,
+accumulation and self-power removal) runs in the gfx950 kernels of libmoff.so.
+Shapes, dtypes and devices are checked here before any pointer is passed on,
+since the C side cannot see the extent of a device buffer.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (MOFF_AUTOCORR_NONE, MOFF_IN_C64, MOFF_IN_CI4, MOFF_NORM_PAIRS,  # noqa: F401
+                   MoffError, moff_geometry)
+
+__all__ = ["Plan", "MoffError", "MOFF_IN_C64", "MOFF_IN_CI4", "MOFF_AUTOCORR_NONE", "MOFF_NORM_PAIRS",
+           "library_path"]
+
+
+def library_path():
+    return _lib.LIB_PATH
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class Plan:
+    """A MOFF plan on one device (device < 0: host-only, for queries)."""
+
+    def __init__(self, ant_xy, ktype_k, ktype_vals, ant_ktype, freq_hz, grid_n, cell_m=0.0, flags=0, device=0):
+        self._xy = np.ascontiguousarray(ant_xy, dtype=np.float64).reshape(-1, 2)
+        self._k = np.ascontiguousarray(ktype_k, dtype=np.int32).reshape(-1)
+        tabs = [np.ascontiguousarray(t, dtype=np.complex64) for t in ktype_vals]
+        for k, t in zip(self._k, tabs):
+            if t.shape != (k, k):
+                raise ValueError(f"kernel table shape {t.shape} does not match k={k}")
+        if len(tabs) != len(self._k):
+            raise ValueError("one table per kernel type is required")
+        self._vals = np.ascontiguousarray(np.concatenate([t.reshape(-1) for t in tabs]).view(np.float32))
+        self._types = np.ascontiguousarray(ant_ktype, dtype=np.int32).reshape(-1)
+        self._freq = np.ascontiguousarray(freq_hz, dtype=np.float64).reshape(-1)
+        if self._types.shape[0] != self._xy.shape[0]:
+            raise ValueError("ant_ktype must have one entry per antenna")
+        g = moff_geometry()
+        g.n_ant = self._xy.shape[0]
+        g.ant_xy_m = _ptr(self._xy, ctypes.c_double)
+        g.n_ktypes = self._k.shape[0]
+        g.ktype_k = _ptr(self._k, ctypes.c_int32)
+        g.ktype_vals = _ptr(self._vals, ctypes.c_float)
+        g.ant_ktype = _ptr(self._types, ctypes.c_int32)
+        g.n_chan = self._freq.shape[0]
+        g.freq_hz = _ptr(self._freq, ctypes.c_double)
+        g.grid_n = int(grid_n)
+        g.cell_m = float(cell_m)
+        g.flags = int(flags)
+        self.device = int(device)
+        self.flags = int(flags)
+        self.n_ant = int(g.n_ant)
+        self.n_chan = int(g.n_chan)
+        self.n_ktypes = int(g.n_ktypes)
+        self.N = int(grid_n)
+        self.handle = None
+        self.handle = _lib.moff_plan_create(g, self.device)
+
+    @classmethod
+    def from_geometry(cls, geom, device=0):
+        """Build from any object with the fields of the C geometry (ant_xy, ktype_k,
+        ktype_vals, ant_ktype, freq_hz, grid_n, cell_m, flags)."""
+        return cls(geom.ant_xy, geom.ktype_k, geom.ktype_vals, geom.ant_ktype, geom.freq_hz, geom.grid_n,
+                   geom.cell_m, geom.flags, device)
+
+    # ---- lifetime --------------------------------------------------------
+    def close(self):
+        if self.handle:
+            _lib.moff_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- host queries ----------------------------------------------------
+    @property
+    def ci4(self):
+        return bool(self.flags & MOFF_IN_CI4)
+
+    def cells(self):
+        out = np.zeros((self.n_ant, 2), np.int32)
+        _lib.moff_plan_query(self.handle, _ptr(out, ctypes.c_int32), None, None, None)
+        return out
+
+    def cell_m(self):
+        v = ctypes.c_double()
+        _lib.moff_plan_query(self.handle, None, ctypes.byref(v), None, None)
+        return v.value
+
+    def lm_per_pixel(self):
+        out = np.zeros(self.n_chan, np.float64)
+        _lib.moff_plan_query(self.handle, None, None, _ptr(out, ctypes.c_double), None)
+        return out
+
+    def power_pattern(self, ktype):
+        out = np.zeros((self.N, self.N), np.float64)
+        _lib.moff_plan_power_pattern(self.handle, int(ktype), _ptr(out, ctypes.c_double))
+        return out
+
+    def gather_program(self, w):
+        """(entries uint32 [prog_len, n_threads, 2], weights complex64, row_pitch) of class w."""
+        sizes = [ctypes.c_int32() for _ in range(5)]
+        _lib.moff_plan_gather_program(self.handle, 0, None, None, *[ctypes.byref(s) for s in sizes])
+        plen, nt, ncls, pitch, nw = (s.value for s in sizes)
+        out = np.zeros((plen, nt, 2), np.uint32)
+        wts = np.zeros(2 * nw, np.float32)
+        _lib.moff_plan_gather_program(self.handle, int(w), _ptr(out, ctypes.c_uint32), _ptr(wts, ctypes.c_float),
+                                      *[ctypes.byref(s) for s in sizes])
+        return out, wts.view(np.complex64), dict(prog_len=plen, n_threads=nt, n_classes=ncls, row_pitch=pitch)
+
+    def set_timing(self, enable=True):
+        _lib.moff_plan_set_timing(self.handle, enable)
+
+    def last_kernel_ms(self):
+        return _lib.moff_plan_last_kernel_ms(self.handle)
+
+    # ---- device calls ----------------------------------------------------
+    def _torch(self):
+        import torch
+        return torch
+
+    def _dev(self, t, name, shape, dtype):
+        torch = self._torch()
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.device.type != "cuda" or t.device.index != self.device:
+            raise ValueError(f"{name} must live on cuda:{self.device}")
+        if t.dtype != dtype:
+            raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t.data_ptr()
+
+    def _stream(self, stream):
+        torch = self._torch()
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        return s.cuda_stream
+
+    def _E(self, E):
+        torch = self._torch()
+        if E.dim() != 3:
+            raise ValueError("E must be [n_time, n_chan, n_ant]")
+        T = E.shape[0]
+        dt = torch.uint8 if self.ci4 else torch.complex64
+        return self._dev(E, "E", (T, self.n_chan, self.n_ant), dt), T
+
+    def _gains(self, gains):
+        if gains is None:
+            return None
+        return self._dev(gains, "gains", (self.n_chan, self.n_ant), self._torch().complex64)
+
+    def _new(self, shape, dtype):
+        torch = self._torch()
+        return torch.empty(shape, dtype=dtype, device=f"cuda:{self.device}")
+
+    def image(self, E, gains=None, out=None, stream=None):
+        """Fused path: time-averaged image float32 [n_chan, N, N]."""
+        torch = self._torch()
+        pE, T = self._E(E)
+        if out is None:
+            out = self._new((self.n_chan, self.N, self.N), torch.float32)
+        po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_image(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
+        return out
+
+    def accumulate(self, E, S, A, gains=None, stream=None):
+        torch = self._torch()
+        pE, T = self._E(E)
+        pS = self._dev(S, "S", (self.n_chan, self.N, self.N), torch.float32)
+        pA = self._dev(A, "A", (self.n_chan, self.n_ktypes), torch.float64)
+        _lib.moff_accumulate(self.handle, pE, T, self._gains(gains), pS, pA, self._stream(stream))
+
+    def finalize(self, S, A, n_time_total, out=None, stream=None):
+        torch = self._torch()
+        pS = self._dev(S, "S", (self.n_chan, self.N, self.N), torch.float32)
+        pA = self._dev(A, "A", (self.n_chan, self.n_ktypes), torch.float64)
+        if out is None:
+            out = self._new((self.n_chan, self.N, self.N), torch.float32)
+        po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_finalize(self.handle, pS, pA, int(n_time_total), po, self._stream(stream))
+        return out
+
+    def grid(self, E, gains=None, out=None, stream=None):
+        torch = self._torch()
+        pE, T = self._E(E)
+        L = self.N // 2
+        if out is None:
+            out = self._new((T, self.n_chan, L, L), torch.complex64)
+        po = self._dev(out, "out", (T, self.n_chan, L, L), torch.complex64)
+        _lib.moff_grid(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
+        return out
+
+    def self_power(self, E, A, gains=None, stream=None):
+        torch = self._torch()
+        pE, T = self._E(E)
+        pA = self._dev(A, "A", (self.n_chan, self.n_ktypes), torch.float64)
+        _lib.moff_self_power(self.handle, pE, T, self._gains(gains), pA, self._stream(stream))
+
+    def fft2(self, eg, out=None, stream=None):
+        torch = self._torch()
+        L = self.N // 2
+        lead = tuple(eg.shape[:-2])
+        F = int(np.prod(lead)) if lead else 1
+        if tuple(eg.shape[-2:]) != (L, L):
+            raise ValueError(f"eg must end in ({L}, {L})")
+        pe = self._dev(eg, "eg", tuple(eg.shape), torch.complex64)
+        if out is None:
+            out = self._new(lead + (self.N, self.N), torch.complex64)
+        po = self._dev(out, "out", lead + (self.N, self.N), torch.complex64)
+        _lib.moff_fft2(self.handle, pe, F, po, self._stream(stream))
+        return out
+
+    def detect_accumulate(self, Y, S, stream=None):
+        torch = self._torch()
+        T = Y.shape[0]
+        pY = self._dev(Y, "Y", (T, self.n_chan, self.N, self.N), torch.complex64)
+        pS = self._dev(S, "S", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_detect_accumulate(self.handle, pY, T, pS, self._stream(stream))
+
+    def image_staged(self, E, gains=None, out=None, stream=None):
+        """Staged path (each step through HBM): same result as image()."""
+        torch = self._torch()
+        pE, T = self._E(E)
+        if out is None:
+            out = self._new((self.n_chan, self.N, self.N), torch.float32)
+        po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_image_staged(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
+        return out

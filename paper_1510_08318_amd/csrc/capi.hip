@@ -1,0 +1,495 @@
+// C ABI of the MOFF library (declared in include/moff.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/moff.h"
+#include "kernels.h"
+#include "plan.h"
+
+using moff::GatherEntry;
+using moff::HostPlan;
+
+struct moff_plan_s {
+  HostPlan hp;
+  int device = -1;
+  // device tables
+  GatherEntry* d_prog = nullptr;
+  float2* d_weights = nullptr;
+  float2* d_tw = nullptr;
+  double* d_Pp = nullptr;
+  int* d_ant_type = nullptr;
+  float2* d_ktab = nullptr;
+  int* d_csr_ptr = nullptr;
+  int* d_csr_ant = nullptr;
+  int* d_csr_tap = nullptr;
+  // workspace, grown on demand
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+  // optional kernel timing
+  bool timing = false, timed = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+// Run f with the plan's device current, restoring the caller's device after.
+class DeviceGuard {
+ public:
+  explicit DeviceGuard(int dev) {
+    ok_ = hipGetDevice(&prev_) == hipSuccess;
+    if (ok_ && prev_ != dev) ok_ = hipSetDevice(dev) == hipSuccess;
+    switched_ = ok_ && prev_ != dev;
+  }
+  ~DeviceGuard() {
+    if (switched_) (void)hipSetDevice(prev_);
+  }
+  bool ok() const { return ok_; }
+
+ private:
+  int prev_ = 0;
+  bool ok_ = false, switched_ = false;
+};
+
+template <class T>
+moff_status upload(T** dst, const void* src, size_t bytes) {
+  if (bytes == 0) bytes = sizeof(T);
+  if (hipMalloc(reinterpret_cast<void**>(dst), bytes) != hipSuccess) return MOFF_ERR_NOMEM;
+  if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) return MOFF_ERR_HIP;
+  return MOFF_OK;
+}
+
+void free_device(moff_plan p) {
+  void* ptrs[] = {p->d_prog, p->d_weights, p->d_tw,      p->d_Pp,      p->d_ant_type,
+                  p->d_ktab, p->d_csr_ptr, p->d_csr_ant, p->d_csr_tap, p->d_ws};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+  if (p->ev0) (void)hipEventDestroy(p->ev0);
+  if (p->ev1) (void)hipEventDestroy(p->ev1);
+}
+
+moff_status ensure_workspace(moff_plan p, size_t bytes) {
+  if (bytes <= p->ws_bytes) return MOFF_OK;
+  if (p->d_ws) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_ws);
+    p->d_ws = nullptr;
+    p->ws_bytes = 0;
+  }
+  if (hipMalloc(&p->d_ws, bytes) != hipSuccess) return MOFF_ERR_NOMEM;
+  p->ws_bytes = bytes;
+  return MOFF_OK;
+}
+
+moff_status hip_status(hipError_t e) { return e == hipSuccess ? MOFF_OK : MOFF_ERR_HIP; }
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+moff_status check_compute(moff_plan p, int64_t n_time) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
+  if (n_time < 1) return MOFF_ERR_INVALID_ARG;
+  if (n_time * static_cast<int64_t>(p->hp.n_chan) >= (int64_t(1) << 31)) return MOFF_ERR_UNSUPPORTED;
+  return MOFF_OK;
+}
+
+double image_scale(const HostPlan& hp, int64_t n_time) {
+  double s = 1.0 / static_cast<double>(n_time);
+  if (hp.flags & MOFF_NORM_PAIRS) s /= static_cast<double>(hp.n_ant) * (hp.n_ant - 1);
+  return s;
+}
+
+// Number of time slices of the fused launch: enough workgroups to cover the
+// chip several times over, never more than the frames available.
+int choose_slices(const HostPlan& hp, int64_t n_time) {
+  const int per_slice = hp.shape.SX * hp.n_chan;
+  const int target = 2048;
+  int s = (target + per_slice - 1) / per_slice;
+  s = std::min<int64_t>(s, n_time);
+  s = std::min(s, 64);
+  return std::max(s, 1);
+}
+
+moff::FusedArgs fused_args(moff_plan p, const void* E, int64_t n_time, const float* gains) {
+  const HostPlan& hp = p->hp;
+  moff::FusedArgs a{};
+  a.E = E;
+  a.gains = reinterpret_cast<const float2*>(gains);
+  a.prog = p->d_prog;
+  a.prog_len = hp.prog_len;
+  a.weights = p->d_weights;
+  a.n_weights = hp.NJ * hp.n_taps;
+  a.tw = p->d_tw;
+  a.ant_type = p->d_ant_type;
+  a.n_ant = hp.n_ant;
+  a.n_chan = hp.n_chan;
+  a.n_types = hp.n_ktypes;
+  a.n_time = n_time;
+  a.Pp = p->d_Pp;
+  a.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  return a;
+}
+
+moff_status fused_run(moff_plan p, const void* E, int64_t n_time, const float* gains, float* out,
+                      double* outA, bool final_image, hipStream_t st) {
+  const HostPlan& hp = p->hp;
+  moff::FusedArgs a = fused_args(p, E, n_time, gains);
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  if (moff::fused_lds_bytes(hp.N, a.n_weights, hp.n_ant) > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
+  const int slices = choose_slices(hp, n_time);
+  a.slices = slices;
+  a.scale = image_scale(hp, n_time);
+  if (slices == 1) {
+    a.out = out;
+    a.outA = outA;
+    if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
+    hipError_t e = moff::launch_fused(a, hp.N, final_image ? moff::kModeFinal : moff::kModeAccum, ci4, st);
+    if (e != hipSuccess) return MOFF_ERR_HIP;
+    if (p->timing) {
+      if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
+      p->timed = true;
+    }
+    return MOFF_OK;
+  }
+  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
+  const size_t s_bytes = sizeof(float) * npix * hp.n_chan * slices;
+  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * slices;
+  moff_status ms = ensure_workspace(p, s_bytes + a_bytes);
+  if (ms != MOFF_OK) return ms;
+  a.out = static_cast<float*>(p->d_ws);
+  a.outA = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + s_bytes);
+  if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
+  hipError_t e = moff::launch_fused(a, hp.N, moff::kModePartial, ci4, st);
+  if (e != hipSuccess) return MOFF_ERR_HIP;
+  if (p->timing) {
+    if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
+    p->timed = true;
+  }
+  moff::ReduceArgs r{};
+  r.S_part = a.out;
+  r.A_part = a.outA;
+  r.Pp = p->d_Pp;
+  r.out = out;
+  r.outA = outA;
+  r.N = hp.N;
+  r.n_chan = hp.n_chan;
+  r.n_types = hp.n_ktypes;
+  r.slices = slices;
+  r.final_image = final_image ? 1 : 0;
+  r.subtract = a.subtract;
+  r.scale = a.scale;
+  return hip_status(moff::launch_reduce(r, st));
+}
+
+moff::GridArgs grid_args(moff_plan p, const void* E, int64_t n_time, const float* gains) {
+  const HostPlan& hp = p->hp;
+  moff::GridArgs g{};
+  g.E = E;
+  g.gains = reinterpret_cast<const float2*>(gains);
+  g.ktab = p->d_ktab;
+  g.csr_ptr = p->d_csr_ptr;
+  g.csr_ant = p->d_csr_ant;
+  g.csr_tap = p->d_csr_tap;
+  g.ant_type = p->d_ant_type;
+  g.n_ant = hp.n_ant;
+  g.n_chan = hp.n_chan;
+  g.n_taps = hp.n_taps;
+  g.n_types = hp.n_ktypes;
+  g.L = hp.L;
+  g.n_time = n_time;
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int moff_abi_version(void) { return MOFF_ABI_VERSION; }
+
+const char* moff_status_str(moff_status s) {
+  switch (s) {
+    case MOFF_OK: return "ok";
+    case MOFF_ERR_INVALID_ARG: return "invalid argument";
+    case MOFF_ERR_GRID_NOT_POW2: return "grid_n must be a power of two in [8, 256]";
+    case MOFF_ERR_FOOTPRINT_OVERFLOW: return "antenna footprints do not fit in the grid_n/2 aperture region";
+    case MOFF_ERR_UNSUPPORTED: return "unsupported request";
+    case MOFF_ERR_NOMEM: return "out of memory";
+    case MOFF_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_plan* out) {
+  if (!out) return MOFF_ERR_INVALID_ARG;
+  *out = nullptr;
+  moff_plan p = new (std::nothrow) moff_plan_s;
+  if (!p) return MOFF_ERR_NOMEM;
+  std::string why;
+  moff_status st = moff::build_host_plan(geom, &p->hp, &why);
+  if (st != MOFF_OK) {
+    delete p;
+    return st;
+  }
+  if (hip_device >= 0) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) {
+      delete p;
+      return MOFF_ERR_INVALID_ARG;
+    }
+    DeviceGuard guard(hip_device);
+    if (!guard.ok()) {
+      delete p;
+      return MOFF_ERR_HIP;
+    }
+    p->device = hip_device;
+    const HostPlan& hp = p->hp;
+    std::vector<double> Pp(hp.Pp);
+    moff_status s = MOFF_OK;
+    auto up = [&](moff_status r) {
+      if (s == MOFF_OK) s = r;
+    };
+    up(upload(&p->d_prog, hp.prog.data(), sizeof(GatherEntry) * hp.prog.size()));
+    up(upload(&p->d_weights, hp.weights.data(), sizeof(float) * hp.weights.size()));
+    up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
+    up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
+    up(upload(&p->d_ant_type, hp.ant_ktype.data(), sizeof(int) * hp.ant_ktype.size()));
+    up(upload(&p->d_ktab, hp.kvals.data(), sizeof(float) * hp.kvals.size()));
+    up(upload(&p->d_csr_ptr, hp.csr_ptr.data(), sizeof(int) * hp.csr_ptr.size()));
+    up(upload(&p->d_csr_ant, hp.csr_ant.data(), sizeof(int) * hp.csr_ant.size()));
+    up(upload(&p->d_csr_tap, hp.csr_tap.data(), sizeof(int) * hp.csr_tap.size()));
+    if (s != MOFF_OK) {
+      free_device(p);
+      delete p;
+      return s;
+    }
+  }
+  *out = p;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_destroy(moff_plan p) {
+  if (!p) return MOFF_OK;
+  if (p->device >= 0) {
+    DeviceGuard guard(p->device);
+    (void)hipDeviceSynchronize();
+    free_device(p);
+  }
+  delete p;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_query(moff_plan p, int32_t* cells, double* cell_m, double* lm_per_pixel, int32_t* grid_n) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  const HostPlan& hp = p->hp;
+  if (cells)
+    for (int a = 0; a < hp.n_ant; ++a) {
+      cells[2 * a] = hp.ix0[a];
+      cells[2 * a + 1] = hp.iy0[a];
+    }
+  if (cell_m) *cell_m = hp.cell_m;
+  if (lm_per_pixel) std::copy(hp.lm_per_pixel.begin(), hp.lm_per_pixel.end(), lm_per_pixel);
+  if (grid_n) *grid_n = hp.N;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_set_timing(moff_plan p, int enable) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
+  if (enable && !p->ev0) {
+    DeviceGuard guard(p->device);
+    if (!guard.ok()) return MOFF_ERR_HIP;
+    if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess) return MOFF_ERR_HIP;
+  }
+  p->timing = enable != 0;
+  p->timed = false;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_last_kernel_ms(moff_plan p, double* ms) {
+  if (!p || !ms || !p->timing || !p->timed) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  if (hipEventSynchronize(p->ev1) != hipSuccess) return MOFF_ERR_HIP;
+  float f = 0.f;
+  if (hipEventElapsedTime(&f, p->ev0, p->ev1) != hipSuccess) return MOFF_ERR_HIP;
+  *ms = f;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_power_pattern(moff_plan p, int32_t ktype, double* out) {
+  if (!p || !out || ktype < 0 || ktype >= p->hp.n_ktypes) return MOFF_ERR_INVALID_ARG;
+  const size_t n = static_cast<size_t>(p->hp.N) * p->hp.N;
+  std::memcpy(out, p->hp.Pp.data() + n * ktype, n * sizeof(double));
+  return MOFF_OK;
+}
+
+moff_status moff_plan_gather_program(moff_plan p, int32_t w, uint32_t* out, float* weights, int32_t* prog_len,
+                                     int32_t* n_threads, int32_t* n_classes, int32_t* row_pitch, int32_t* n_weights) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  const HostPlan& hp = p->hp;
+  if (prog_len) *prog_len = hp.prog_len;
+  if (n_threads) *n_threads = hp.shape.NT;
+  if (n_classes) *n_classes = hp.shape.SX;
+  if (row_pitch) *row_pitch = hp.ZP;
+  const int nw = hp.NJ * hp.n_taps;
+  if (n_weights) *n_weights = nw;
+  if (!out && !weights) return MOFF_OK;
+  if (w < 0 || w >= hp.shape.SX) return MOFF_ERR_INVALID_ARG;
+  if (out) {
+    const size_t n = static_cast<size_t>(hp.prog_len) * hp.shape.NT;
+    const GatherEntry* src = hp.prog.data() + n * w;
+    for (size_t i = 0; i < n; ++i) {
+      out[2 * i] = src[i].x;
+      out[2 * i + 1] = src[i].y;
+    }
+  }
+  if (weights) std::memcpy(weights, hp.weights.data() + static_cast<size_t>(2) * nw * w, sizeof(float) * 2 * nw);
+  return MOFF_OK;
+}
+
+moff_status moff_image(moff_plan p, const void* E, int64_t n_time, const float* gains, float* image,
+                       void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  return fused_run(p, E, n_time, gains, image, nullptr, true, static_cast<hipStream_t>(stream));
+}
+
+moff_status moff_accumulate(moff_plan p, const void* E, int64_t n_time, const float* gains, float* S, double* A,
+                            void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !S || !A || !aligned16(S) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  return fused_run(p, E, n_time, gains, S, A, false, static_cast<hipStream_t>(stream));
+}
+
+moff_status moff_finalize(moff_plan p, const float* S, const double* A, int64_t n_time_total, float* image,
+                          void* stream) {
+  moff_status s = check_compute(p, n_time_total);
+  if (s != MOFF_OK) return s;
+  if (!S || !A || !image) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const HostPlan& hp = p->hp;
+  moff::FinalizeArgs f{};
+  f.S = S;
+  f.A = A;
+  f.Pp = p->d_Pp;
+  f.out = image;
+  f.N = hp.N;
+  f.n_chan = hp.n_chan;
+  f.n_types = hp.n_ktypes;
+  f.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  f.scale = image_scale(hp, n_time_total);
+  return hip_status(moff::launch_finalize(f, static_cast<hipStream_t>(stream)));
+}
+
+moff_status moff_grid(moff_plan p, const void* E, int64_t n_time, const float* gains, float* eg, void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !eg || !aligned16(eg) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  moff::GridArgs g = grid_args(p, E, n_time, gains);
+  g.Eg = reinterpret_cast<float2*>(eg);
+  return hip_status(moff::launch_grid(g, p->hp.flags & MOFF_IN_CI4, static_cast<hipStream_t>(stream)));
+}
+
+moff_status moff_self_power(moff_plan p, const void* E, int64_t n_time, const float* gains, double* A,
+                            void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !A || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  moff::GridArgs g = grid_args(p, E, n_time, gains);
+  g.A = A;
+  return hip_status(moff::launch_self_power(g, p->hp.flags & MOFF_IN_CI4, static_cast<hipStream_t>(stream)));
+}
+
+moff_status moff_fft2(moff_plan p, const float* eg, int64_t n_frames, float* y, void* stream) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
+  if (n_frames < 1 || !eg || !y || !aligned16(eg) || !aligned16(y)) return MOFF_ERR_INVALID_ARG;
+  if (n_frames * p->hp.shape.SX >= (int64_t(1) << 31)) return MOFF_ERR_UNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  moff::Fft2Args f{reinterpret_cast<const float2*>(eg), reinterpret_cast<float2*>(y), p->d_tw};
+  return hip_status(moff::launch_fft2(f, p->hp.N, n_frames, static_cast<hipStream_t>(stream)));
+}
+
+moff_status moff_detect_accumulate(moff_plan p, const float* y, int64_t n_time, float* S, void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!y || !S || !aligned16(y)) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  moff::DetectArgs d{reinterpret_cast<const float2*>(y), S, p->hp.N, p->hp.n_chan, n_time};
+  return hip_status(moff::launch_detect(d, static_cast<hipStream_t>(stream)));
+}
+
+moff_status moff_image_staged(moff_plan p, const void* E, int64_t n_time, const float* gains, float* image,
+                              void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const HostPlan& hp = p->hp;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
+  const size_t s_bytes = sizeof(float) * npix * hp.n_chan;
+  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes;
+  // time chunk: keep the per-chunk grids and fields within ~2 GiB
+  const size_t per_t = (sizeof(float2) * (static_cast<size_t>(hp.L) * hp.L + npix)) * hp.n_chan;
+  int64_t chunk = std::max<int64_t>(1, static_cast<int64_t>((size_t(2) << 30) / per_t));
+  chunk = std::min(chunk, n_time);
+  const size_t eg_bytes = sizeof(float2) * static_cast<size_t>(hp.L) * hp.L * hp.n_chan * chunk;
+  const size_t y_bytes = sizeof(float2) * npix * hp.n_chan * chunk;
+  s = ensure_workspace(p, s_bytes + a_bytes + eg_bytes + y_bytes);
+  if (s != MOFF_OK) return s;
+  char* ws = static_cast<char*>(p->d_ws);
+  float* S = reinterpret_cast<float*>(ws);
+  double* A = reinterpret_cast<double*>(ws + s_bytes);
+  float2* Eg = reinterpret_cast<float2*>(ws + s_bytes + a_bytes);
+  float2* Y = reinterpret_cast<float2*>(ws + s_bytes + a_bytes + eg_bytes);
+  if (moff::launch_zero(ws, s_bytes + a_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
+  const size_t sample_bytes = ci4 ? 1 : sizeof(float2);
+  for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
+    const int64_t nt = std::min(chunk, n_time - t0);
+    const void* Ec = static_cast<const char*>(E) + static_cast<size_t>(t0) * hp.n_chan * hp.n_ant * sample_bytes;
+    moff::GridArgs g = grid_args(p, Ec, nt, gains);
+    g.Eg = Eg;
+    g.A = A;
+    hipError_t e = moff::launch_grid(g, ci4, st);
+    if (e == hipSuccess) e = moff::launch_self_power(g, ci4, st);
+    moff::Fft2Args f{Eg, Y, p->d_tw};
+    if (e == hipSuccess) e = moff::launch_fft2(f, hp.N, nt * hp.n_chan, st);
+    moff::DetectArgs d{Y, S, hp.N, hp.n_chan, nt};
+    if (e == hipSuccess) e = moff::launch_detect(d, st);
+    if (e != hipSuccess) return MOFF_ERR_HIP;
+  }
+  moff::FinalizeArgs fa{};
+  fa.S = S;
+  fa.A = A;
+  fa.Pp = p->d_Pp;
+  fa.out = image;
+  fa.N = hp.N;
+  fa.n_chan = hp.n_chan;
+  fa.n_types = hp.n_ktypes;
+  fa.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  fa.scale = image_scale(hp, n_time);
+  return hip_status(moff::launch_finalize(fa, st));
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Kernel argument blocks and launchers (host-callable), shared by kernels.hip
+// and the C ABI.  Pointers are device pointers unless stated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "plan.h"
+
+namespace moff {
+
+enum { kModePartial = 0, kModeAccum = 1, kModeFinal = 2 };
+
+struct FusedArgs {
+  const void* E;               // [T][C][n_ant] c64 or ci4
+  const float2* gains;         // [C][n_ant] or nullptr
+  const GatherEntry* prog;     // [SX][prog_len][NT]
+  int prog_len;
+  const float2* weights;       // [SX][n_weights]
+  int n_weights;
+  const float2* tw;            // [N]
+  const int* ant_type;         // [n_ant]
+  int n_ant, n_chan, n_types;
+  int64_t n_time;
+  int slices;
+  float* out;                  // partial: [slices][C][N][N]; accum: S [C][N][N]; final: image
+  double* outA;                // partial: [slices][C][types]; accum: A [C][types]
+  const double* Pp;            // [types][N][N]
+  double scale;
+  int subtract;
+};
+
+struct ReduceArgs {
+  const float* S_part;
+  const double* A_part;
+  const double* Pp;
+  float* out;
+  double* outA;
+  int N, n_chan, n_types, slices;
+  int final_image, subtract;
+  double scale;
+};
+
+struct GridArgs {
+  const void* E;
+  const float2* gains;
+  const float2* ktab;          // [n_taps]
+  const int* csr_ptr;          // [L*L + 1]
+  const int* csr_ant;
+  const int* csr_tap;
+  const int* ant_type;
+  float2* Eg;                  // [T][C][L][L]
+  double* A;                   // [C][types]
+  int n_ant, n_chan, n_taps, n_types, L;
+  int64_t n_time;
+};
+
+struct Fft2Args {
+  const float2* Eg;            // [F][L][L]
+  float2* Y;                   // [F][N][N]
+  const float2* tw;            // [N]
+};
+
+struct DetectArgs {
+  const float2* Y;             // [T][C][N][N]
+  float* S;                    // [C][N][N]
+  int N, n_chan;
+  int64_t n_time;
+};
+
+struct FinalizeArgs {
+  const float* S;
+  const double* A;
+  const double* Pp;
+  float* out;
+  int N, n_chan, n_types, subtract;
+  double scale;
+};
+
+size_t fused_lds_bytes(int N, int n_weights, int n_ant);
+hipError_t launch_fused(const FusedArgs& a, int N, int mode, bool ci4, hipStream_t st);
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
+hipError_t launch_grid(const GridArgs& a, bool ci4, hipStream_t st);
+hipError_t launch_self_power(const GridArgs& a, bool ci4, hipStream_t st);
+hipError_t launch_fft2(const Fft2Args& a, int N, int64_t n_frames, hipStream_t st);
+hipError_t launch_detect(const DetectArgs& a, hipStream_t st);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);  // bytes: multiple of 4
+
+}  // namespace moff

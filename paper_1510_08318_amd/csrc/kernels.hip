@@ -1,0 +1,455 @@
+// gfx950 kernels of the MOFF imaging path.
+//
+//   fused_kernel      ingest + calibration + gather-gridding + padded 2-D DFT +
+//                     |.|^2 + time accumulation (+ self-power removal) for all
+//                     frames of one (column class, channel, time slice); one
+//                     launch covers every channel (Sec. 2 MOFF imaging equation,
+//                     Sec. 3 implementation steps, Sec. 4.2 autocorrelations).
+//   reduce_kernel     fixed-order reduction of per-slice partial sums, then
+//                     self-power removal and averaging (or accumulation).
+//   grid_kernel, self_power_kernel, fft2_kernel, detect_kernel, finalize_kernel
+//                     the same steps one at a time through HBM (staged path).
+//
+// No global atomics anywhere: every output element has exactly one writer and
+// every sum is taken in a fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "frame.h"
+#include "kernels.h"
+
+namespace moff {
+
+namespace {
+
+constexpr int kMaxTypesDev = 4;
+
+__device__ __forceinline__ float2 load_sample(const void* E, size_t idx, bool ci4) {
+  if (ci4) {
+    // one byte: real part in the high nibble, imaginary part in the low nibble
+    const int8_t b = reinterpret_cast<const int8_t*>(E)[idx];
+    const int re = b >> 4;
+    const int im = static_cast<int8_t>(b << 4) >> 4;
+    return make_float2(static_cast<float>(re), static_cast<float>(im));
+  }
+  return reinterpret_cast<const float2*>(E)[idx];
+}
+
+// Deterministic block sum of four doubles per thread; result valid in thread 0..3 of `out`.
+template <int NT>
+__device__ __forceinline__ void block_sum4(double v[kMaxTypesDev], double* out) {
+  __shared__ double part[NT / 64][kMaxTypesDev];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int p = 0; p < kMaxTypesDev; ++p) {
+    double x = v[p];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+    if (lane == 0) part[wave][p] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxTypesDev) {
+    double s = 0.0;
+    for (int wv = 0; wv < NT / 64; ++wv) s += part[wv][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// exp(+2 pi i k / SX) for SX dividing 4, exact.
+__device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
+  const int q = ((k * (4 / SX)) % 4 + 4) % 4;
+  return q == 0 ? v : q == 1 ? c_mul_i(v) : q == 2 ? c_neg(v) : c_mul_mi(v);
+}
+
+// Gather-gridding of one frame into the folded grid: each lane walks its slice
+// of the cell-keyed program, multiplies the calibrated antenna field by the
+// tap weight, and stores each finished cell sum.  Every folded cell is written.
+template <int NT>
+__device__ __forceinline__ void gather_frame(const GatherEntry* __restrict__ prog, int prog_len,
+                                             const float2* e, const float2* W, float2* G) {
+  float2 acc = make_float2(0.f, 0.f);
+  int k = 0;
+  for (; k + 4 <= prog_len; k += 4) {
+    GatherEntry ent[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ent[i] = prog[static_cast<size_t>(k + i) * NT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float2 ev = e[ent[i].x & 0xFFFu];
+      const float2 wv = W[(ent[i].x >> 12) & 0x7FFu];
+      acc.x = fmaf(ev.x, wv.x, fmaf(-ev.y, wv.y, acc.x));
+      acc.y = fmaf(ev.x, wv.y, fmaf(ev.y, wv.x, acc.y));
+      if (ent[i].x & kStoreBit) {
+        G[ent[i].y] = acc;
+        acc = make_float2(0.f, 0.f);
+      }
+    }
+  }
+  for (; k < prog_len; ++k) {
+    const GatherEntry en = prog[static_cast<size_t>(k) * NT];
+    const float2 ev = e[en.x & 0xFFFu];
+    const float2 wv = W[(en.x >> 12) & 0x7FFu];
+    acc.x = fmaf(ev.x, wv.x, fmaf(-ev.y, wv.y, acc.x));
+    acc.y = fmaf(ev.x, wv.y, fmaf(ev.y, wv.x, acc.y));
+    if (en.x & kStoreBit) {
+      G[en.y] = acc;
+      acc = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// fused kernel
+// ---------------------------------------------------------------------------
+
+template <int N, int MODE, bool CI4>
+__global__ __launch_bounds__(FT<N>::NT) void fused_kernel(FusedArgs a) {
+  using C = FT<N>;
+  constexpr int NT = C::NT;
+  extern __shared__ float2 lds[];
+  __shared__ double Atot[kMaxTypesDev];
+  const int w = blockIdx.x, c = blockIdx.y, slice = blockIdx.z;
+  const int tid = threadIdx.x;
+
+  float2* G = lds;                          // [L][ZP]
+  float2* tw = G + C::L * C::ZP;            // [N]
+  float2* W = tw + N;                       // [n_weights]
+  float2* gl = W + a.n_weights;             // [n_ant] gains of this channel
+  float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
+  int* ty = reinterpret_cast<int*>(e + a.n_ant + 1);  // [n_ant]
+
+  for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+  for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
+  for (int i = tid; i < a.n_ant; i += NT) {
+    gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+    ty[i] = a.ant_type[i];
+  }
+  if (tid == 0) e[a.n_ant] = make_float2(0.f, 0.f);
+
+  const int64_t T = a.n_time;
+  const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
+  const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
+  const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
+
+  float acc[C::NACC];
+#pragma unroll
+  for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
+  double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+
+  __syncthreads();
+  for (int64_t t = t0; t < t1; ++t) {
+    // ingest + calibration: e = g * E, and the self power of each antenna type
+    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+    for (int i = tid; i < a.n_ant; i += NT) {
+      const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+      e[i] = v;
+      const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+      const int tp = ty[i];
+#pragma unroll
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+    }
+    __syncthreads();
+    gather_frame<NT>(prog, a.prog_len, e, W, G);
+    __syncthreads();
+    row_stage<N>(G, tw, w);
+    __syncthreads();
+    col_stage<N>(G, tw, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
+  }
+
+  block_sum4<NT>(pw, Atot);
+
+  const size_t img_stride = static_cast<size_t>(N) * N;
+#pragma unroll
+  for (int idx = 0; idx < C::NACC; ++idx) {
+    int r, col;
+    acc_pixel<N>(idx, r, col);
+    if (C::CGUARD && col >= C::M) continue;
+    const int q = C::SX * col + w;
+    const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
+    const size_t pix = static_cast<size_t>(pr) * N + pq;
+    if constexpr (MODE == kModePartial) {
+      a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = acc[idx];
+    } else if constexpr (MODE == kModeAccum) {
+      a.out[static_cast<size_t>(c) * img_stride + pix] += acc[idx];
+    } else {
+      double v = acc[idx];
+      if (a.subtract)
+        for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
+      a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+    }
+  }
+  if (w == 0 && tid < a.n_types) {
+    if constexpr (MODE == kModePartial) {
+      a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
+    } else if constexpr (MODE == kModeAccum) {
+      a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
+    }
+  }
+}
+
+// Sum per-slice partials in slice order; then remove self power and average
+// (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
+__global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
+  const size_t npix = static_cast<size_t>(a.N) * a.N;
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= npix * a.n_chan) return;
+  const size_t c = i / npix, pix = i % npix;
+  double s = 0.0;
+  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + pix];
+  double A[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = 0; p < a.n_types; ++p)
+    for (int sl = 0; sl < a.slices; ++sl) A[p] += a.A_part[(static_cast<size_t>(sl) * a.n_chan + c) * a.n_types + p];
+  if (a.final_image) {
+    double v = s;
+    if (a.subtract)
+      for (int p = 0; p < a.n_types; ++p) v -= A[p] * a.Pp[p * npix + pix];
+    a.out[i] = static_cast<float>(v * a.scale);
+  } else {
+    a.out[i] += static_cast<float>(s);
+    if (pix == 0)
+      for (int p = 0; p < a.n_types; ++p) a.outA[c * a.n_types + p] += A[p];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// staged kernels
+// ---------------------------------------------------------------------------
+
+// One workgroup per frame: calibrate into LDS, then every aperture cell sums
+// its CSR row (antenna-ascending) and writes Eg.
+template <bool CI4>
+__global__ __launch_bounds__(256) void grid_kernel(GridArgs a) {
+  extern __shared__ float2 lds[];
+  float2* e = lds;               // [n_ant]
+  float2* K = e + a.n_ant;       // [n_taps]
+  const int64_t f = blockIdx.x;  // frame = t * n_chan + c
+  const int c = static_cast<int>(f % a.n_chan);
+  const size_t base = static_cast<size_t>(f) * a.n_ant;
+  for (int i = threadIdx.x; i < a.n_ant; i += 256) {
+    const float2 g = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+    e[i] = c_mul(g, load_sample(a.E, base + i, CI4));
+  }
+  for (int i = threadIdx.x; i < a.n_taps; i += 256) K[i] = a.ktab[i];
+  __syncthreads();
+  const int ncell = a.L * a.L;
+  float2* out = a.Eg + static_cast<size_t>(f) * ncell;
+  for (int cell = threadIdx.x; cell < ncell; cell += 256) {
+    float2 s = make_float2(0.f, 0.f);
+    for (int k = a.csr_ptr[cell]; k < a.csr_ptr[cell + 1]; ++k) {
+      const float2 ev = e[a.csr_ant[k]], kv = K[a.csr_tap[k]];
+      s.x = fmaf(ev.x, kv.x, fmaf(-ev.y, kv.y, s.x));
+      s.y = fmaf(ev.x, kv.y, fmaf(ev.y, kv.x, s.y));
+    }
+    out[cell] = s;
+  }
+}
+
+// One workgroup per channel: A[c][p] += sum_t sum_{a of type p} |g E|^2.
+template <bool CI4>
+__global__ __launch_bounds__(256) void self_power_kernel(GridArgs a) {
+  __shared__ double tot[kMaxTypesDev];
+  const int c = blockIdx.x;
+  double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < a.n_ant; i += 256) {
+    const float2 g = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+    const int tp = a.ant_type[i];
+    double s = 0.0;
+    for (int64_t t = 0; t < a.n_time; ++t) {
+      const float2 v = c_mul(g, load_sample(a.E, (static_cast<size_t>(t) * a.n_chan + c) * a.n_ant + i, CI4));
+      s += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? s : 0.0;
+  }
+  block_sum4<256>(pw, tot);
+  if (threadIdx.x < a.n_types) a.A[static_cast<size_t>(c) * a.n_types + threadIdx.x] += tot[threadIdx.x];
+}
+
+// One workgroup per (column class, frame): load and fold the aperture grid,
+// transform, store the complex image field in pixel order.
+template <int N>
+__global__ __launch_bounds__(FT<N>::NT) void fft2_kernel(Fft2Args a) {
+  using C = FT<N>;
+  extern __shared__ float2 lds[];
+  float2* G = lds;
+  float2* tw = G + C::L * C::ZP;
+  const int w = blockIdx.x % C::SX;
+  const int64_t f = blockIdx.x / C::SX;
+  for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = a.tw[i];
+  const float2* src = a.Eg + static_cast<size_t>(f) * C::L * C::L;
+  for (int cell = threadIdx.x; cell < C::L * C::NZR; cell += C::NT) {
+    const int iy = cell / C::NZR, n = cell % C::NZR;
+    float2 v = make_float2(0.f, 0.f);
+    for (int j = 0; j * C::M + n < C::L; ++j) {
+      const float2 x = quarter_rot(src[iy * C::L + n + j * C::M], j * w, C::SX);
+      v = c_add(v, x);
+    }
+    G[iy * C::ZP + n] = v;
+  }
+  __syncthreads();
+  row_stage<N>(G, tw, w);
+  __syncthreads();
+  float2* dst = a.Y + static_cast<size_t>(f) * N * N;
+  col_stage<N>(G, tw, [&](int, int r, int col, float2 v) {
+    const int q = C::SX * col + w;
+    dst[((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1))] = v;
+  });
+}
+
+// One thread per (channel, pixel): S += sum_t |Y|^2.
+__global__ __launch_bounds__(256) void detect_kernel(DetectArgs a) {
+  const size_t npix = static_cast<size_t>(a.N) * a.N;
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= npix * a.n_chan) return;
+  const size_t stride = npix * a.n_chan;
+  float s = 0.f;
+  for (int64_t t = 0; t < a.n_time; ++t) {
+    const float2 v = a.Y[static_cast<size_t>(t) * stride + i];
+    s = fmaf(v.x, v.x, fmaf(v.y, v.y, s));
+  }
+  a.S[i] += s;
+}
+
+// image = (S - sum_p A_p P_p) * scale
+__global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
+  const size_t npix = static_cast<size_t>(a.N) * a.N;
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= npix * a.n_chan) return;
+  const size_t c = i / npix, pix = i % npix;
+  double v = a.S[i];
+  if (a.subtract)
+    for (int p = 0; p < a.n_types; ++p) v -= a.A[c * a.n_types + p] * a.Pp[p * npix + pix];
+  a.out[i] = static_cast<float>(v * a.scale);
+}
+
+// Fill with zeros (a kernel rather than a memset node, so captured graphs replay it safely).
+__global__ __launch_bounds__(256) void zero_kernel(uint32_t* p, size_t n) {
+  for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += static_cast<size_t>(gridDim.x) * 256)
+    p[i] = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+size_t fused_lds_bytes(int N, int n_weights, int n_ant) {
+  const FrameShape S = frame_shape(N);
+  const int M = N / S.SX, L = N / 2;
+  return sizeof(float2) * (static_cast<size_t>(L) * grid_pitch(M) + N + n_weights + n_ant + n_ant + 1) +
+         sizeof(int) * n_ant;
+}
+
+namespace {
+
+template <int N, int MODE, bool CI4>
+hipError_t launch_fused_t(const FusedArgs& a, hipStream_t st) {
+  const FrameShape S = frame_shape(N);
+  const size_t lds = fused_lds_bytes(N, a.n_weights, a.n_ant);
+  auto k = fused_kernel<N, MODE, CI4>;
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k, dim3(S.SX, a.n_chan, a.slices), dim3(S.NT), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int N, int MODE>
+hipError_t launch_fused_m(const FusedArgs& a, bool ci4, hipStream_t st) {
+  return ci4 ? launch_fused_t<N, MODE, true>(a, st) : launch_fused_t<N, MODE, false>(a, st);
+}
+
+template <int N>
+hipError_t launch_fused_n(const FusedArgs& a, int mode, bool ci4, hipStream_t st) {
+  switch (mode) {
+    case kModePartial: return launch_fused_m<N, kModePartial>(a, ci4, st);
+    case kModeAccum: return launch_fused_m<N, kModeAccum>(a, ci4, st);
+    default: return launch_fused_m<N, kModeFinal>(a, ci4, st);
+  }
+}
+
+template <int N>
+hipError_t launch_fft2_t(const Fft2Args& a, int64_t n_frames, hipStream_t st) {
+  const FrameShape S = frame_shape(N);
+  const size_t lds = sizeof(float2) * (static_cast<size_t>(N / 2) * grid_pitch(N / S.SX) + N);
+  auto k = fft2_kernel<N>;
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(n_frames * S.SX)), dim3(S.NT), lds, st, a);  // caller keeps it < 2^31
+  return hipGetLastError();
+}
+
+unsigned blocks_for(size_t n) { return static_cast<unsigned>((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_fused(const FusedArgs& a, int N, int mode, bool ci4, hipStream_t st) {
+  switch (N) {
+    case 8: return launch_fused_n<8>(a, mode, ci4, st);
+    case 16: return launch_fused_n<16>(a, mode, ci4, st);
+    case 32: return launch_fused_n<32>(a, mode, ci4, st);
+    case 64: return launch_fused_n<64>(a, mode, ci4, st);
+    case 128: return launch_fused_n<128>(a, mode, ci4, st);
+    case 256: return launch_fused_n<256>(a, mode, ci4, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grid(const GridArgs& a, bool ci4, hipStream_t st) {
+  const size_t lds = sizeof(float2) * (a.n_ant + a.n_taps);
+  const unsigned frames = static_cast<unsigned>(a.n_time * a.n_chan);  // checked < 2^31 by the caller
+  if (ci4)
+    hipLaunchKernelGGL(grid_kernel<true>, dim3(frames), dim3(256), lds, st, a);
+  else
+    hipLaunchKernelGGL(grid_kernel<false>, dim3(frames), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_self_power(const GridArgs& a, bool ci4, hipStream_t st) {
+  if (ci4)
+    hipLaunchKernelGGL(self_power_kernel<true>, dim3(a.n_chan), dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(self_power_kernel<false>, dim3(a.n_chan), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fft2(const Fft2Args& a, int N, int64_t n_frames, hipStream_t st) {
+  switch (N) {
+    case 8: return launch_fft2_t<8>(a, n_frames, st);
+    case 16: return launch_fft2_t<16>(a, n_frames, st);
+    case 32: return launch_fft2_t<32>(a, n_frames, st);
+    case 64: return launch_fft2_t<64>(a, n_frames, st);
+    case 128: return launch_fft2_t<128>(a, n_frames, st);
+    case 256: return launch_fft2_t<256>(a, n_frames, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_detect(const DetectArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(detect_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 4;
+  const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(zero_kernel, dim3(blocks ? blocks : 1), dim3(256), 0, st, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
+
+}  // namespace moff

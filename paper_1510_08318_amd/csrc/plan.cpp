@@ -1,0 +1,288 @@
+// Host plan construction (see plan.h).  Built with -ffp-contract=off.
+#include "plan.h"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace moff {
+
+namespace {
+
+constexpr double kC = 299792458.0;  // speed of light, m/s
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// exp(+2 pi i num / den) with exact values on the quarter turns.
+std::complex<double> unit_root(long long num, long long den) {
+  long long r = ((num % den) + den) % den;
+  if ((4 * r) % den == 0) {
+    switch ((4 * r) / den) {
+      case 0: return {1.0, 0.0};
+      case 1: return {0.0, 1.0};
+      case 2: return {-1.0, 0.0};
+      default: return {0.0, -1.0};
+    }
+  }
+  double ang = kTwoPi * static_cast<double>(r) / static_cast<double>(den);
+  return {std::cos(ang), std::sin(ang)};
+}
+
+moff_status fail(std::string* why, moff_status s, const char* msg) {
+  if (why) *why = msg;
+  return s;
+}
+
+}  // namespace
+
+moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* why) {
+  if (!g || !hp) return fail(why, MOFF_ERR_INVALID_ARG, "null geometry or plan");
+  if (g->n_ant < 2 || g->n_ant > kMaxAnt) return fail(why, MOFF_ERR_INVALID_ARG, "n_ant out of [2, 4000]");
+  if (!g->ant_xy_m || !g->ktype_k || !g->ktype_vals || !g->ant_ktype || !g->freq_hz)
+    return fail(why, MOFF_ERR_INVALID_ARG, "null geometry array");
+  if (g->n_ktypes < 1 || g->n_ktypes > kMaxTypes) return fail(why, MOFF_ERR_INVALID_ARG, "n_ktypes out of [1, 4]");
+  if (g->n_chan < 1) return fail(why, MOFF_ERR_INVALID_ARG, "n_chan < 1");
+  if (g->flags & ~uint32_t(MOFF_IN_CI4 | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS))
+    return fail(why, MOFF_ERR_INVALID_ARG, "unknown flag bits");
+  if (!is_pow2(g->grid_n) || g->grid_n < 8 || g->grid_n > 256)
+    return fail(why, MOFF_ERR_GRID_NOT_POW2, "grid_n must be a power of two in [8, 256]");
+  if (!(g->cell_m >= 0.0) || !std::isfinite(g->cell_m)) return fail(why, MOFF_ERR_INVALID_ARG, "bad cell_m");
+
+  HostPlan& P = *hp;
+  P = HostPlan{};
+  P.n_ant = g->n_ant;
+  P.n_ktypes = g->n_ktypes;
+  P.n_chan = g->n_chan;
+  P.N = g->grid_n;
+  P.L = g->grid_n / 2;
+  P.flags = g->flags;
+
+  P.ktype_k.assign(g->ktype_k, g->ktype_k + g->n_ktypes);
+  P.ktype_off.resize(g->n_ktypes);
+  int off = 0;
+  for (int p = 0; p < g->n_ktypes; ++p) {
+    int k = P.ktype_k[p];
+    if (k < 1 || k > kMaxK) return fail(why, MOFF_ERR_INVALID_ARG, "kernel side out of [1, 15]");
+    P.ktype_off[p] = off;
+    off += k * k;
+  }
+  P.n_taps = off;
+  P.kvals.assign(g->ktype_vals, g->ktype_vals + 2 * off);
+  for (float v : P.kvals)
+    if (!std::isfinite(v)) return fail(why, MOFF_ERR_INVALID_ARG, "non-finite kernel value");
+
+  P.ant_xy.assign(g->ant_xy_m, g->ant_xy_m + 2 * g->n_ant);
+  for (double v : P.ant_xy)
+    if (!std::isfinite(v)) return fail(why, MOFF_ERR_INVALID_ARG, "non-finite antenna position");
+  P.ant_ktype.assign(g->ant_ktype, g->ant_ktype + g->n_ant);
+  for (int t : P.ant_ktype)
+    if (t < 0 || t >= g->n_ktypes) return fail(why, MOFF_ERR_INVALID_ARG, "ant_ktype out of range");
+  P.freq_hz.assign(g->freq_hz, g->freq_hz + g->n_chan);
+  for (double f : P.freq_hz)
+    if (!(f > 0.0) || !std::isfinite(f)) return fail(why, MOFF_ERR_INVALID_ARG, "bad frequency");
+
+  // ---- cell size: the default rule (half the shortest wavelength, widened to fit)
+  int kmax = 0;
+  for (int a = 0; a < P.n_ant; ++a) kmax = std::max(kmax, P.ktype_k[P.ant_ktype[a]]);
+  if (g->cell_m > 0.0) {
+    P.cell_m = g->cell_m;
+  } else {
+    double fmax = *std::max_element(P.freq_hz.begin(), P.freq_hz.end());
+    double lam_min = kC / fmax;
+    double xmin = P.ant_xy[0], xmax = P.ant_xy[0], ymin = P.ant_xy[1], ymax = P.ant_xy[1];
+    for (int a = 1; a < P.n_ant; ++a) {
+      xmin = std::min(xmin, P.ant_xy[2 * a]);
+      xmax = std::max(xmax, P.ant_xy[2 * a]);
+      ymin = std::min(ymin, P.ant_xy[2 * a + 1]);
+      ymax = std::max(ymax, P.ant_xy[2 * a + 1]);
+    }
+    double span = std::max(xmax - xmin, ymax - ymin);
+    int room = P.L - kmax - 1;
+    if (room <= 0) return fail(why, MOFF_ERR_FOOTPRINT_OVERFLOW, "grid too small for the largest footprint");
+    P.cell_m = std::max(lam_min / 2.0, span / static_cast<double>(room));
+  }
+
+  // ---- footprint lower-left cells: floor(x / cell - (k - 1) / 2 + 0.5), shifted to start at 0
+  P.ix0.resize(P.n_ant);
+  P.iy0.resize(P.n_ant);
+  std::vector<long long> ix(P.n_ant), iy(P.n_ant);
+  for (int a = 0; a < P.n_ant; ++a) {
+    double h = (static_cast<double>(P.ktype_k[P.ant_ktype[a]]) - 1.0) / 2.0;
+    double fx = std::floor(P.ant_xy[2 * a] / P.cell_m - h + 0.5);
+    double fy = std::floor(P.ant_xy[2 * a + 1] / P.cell_m - h + 0.5);
+    if (std::fabs(fx) > 1e15 || std::fabs(fy) > 1e15)
+      return fail(why, MOFF_ERR_FOOTPRINT_OVERFLOW, "antenna far outside the grid");
+    ix[a] = static_cast<long long>(fx);
+    iy[a] = static_cast<long long>(fy);
+  }
+  long long mx = *std::min_element(ix.begin(), ix.end());
+  long long my = *std::min_element(iy.begin(), iy.end());
+  for (int a = 0; a < P.n_ant; ++a) {
+    long long k = P.ktype_k[P.ant_ktype[a]];
+    long long x0 = ix[a] - mx, y0 = iy[a] - my;
+    if (x0 + k > P.L || y0 + k > P.L)
+      return fail(why, MOFF_ERR_FOOTPRINT_OVERFLOW, "footprints extend beyond the N/2 aperture region");
+    P.ix0[a] = static_cast<int32_t>(x0);
+    P.iy0[a] = static_cast<int32_t>(y0);
+  }
+  P.lm_per_pixel.resize(P.n_chan);
+  for (int c = 0; c < P.n_chan; ++c) P.lm_per_pixel[c] = (kC / P.freq_hz[c]) / (P.N * P.cell_m);
+
+  // ---- CSR keyed by aperture cell (stable counting sort: antenna-ascending within a cell)
+  const int L = P.L, N = P.N;
+  P.csr_ptr.assign(L * L + 1, 0);
+  for (int a = 0; a < P.n_ant; ++a) {
+    int k = P.ktype_k[P.ant_ktype[a]];
+    for (int u = 0; u < k; ++u)
+      for (int v = 0; v < k; ++v) P.csr_ptr[(P.iy0[a] + u) * L + (P.ix0[a] + v) + 1]++;
+  }
+  for (int i = 0; i < L * L; ++i) P.csr_ptr[i + 1] += P.csr_ptr[i];
+  P.csr_ant.resize(P.csr_ptr[L * L]);
+  P.csr_tap.resize(P.csr_ptr[L * L]);
+  {
+    std::vector<int32_t> fill(P.csr_ptr.begin(), P.csr_ptr.end() - 1);
+    for (int a = 0; a < P.n_ant; ++a) {
+      int p = P.ant_ktype[a], k = P.ktype_k[p];
+      for (int u = 0; u < k; ++u)
+        for (int v = 0; v < k; ++v) {
+          int cell = (P.iy0[a] + u) * L + (P.ix0[a] + v);
+          int at = fill[cell]++;
+          P.csr_ant[at] = a;
+          P.csr_tap[at] = P.ktype_off[p] + u * k + v;
+        }
+    }
+  }
+
+  // ---- power patterns |DFT_N(K_p)|^2 in float64 (same sign and origin as the image)
+  P.Pp.assign(static_cast<size_t>(P.n_ktypes) * N * N, 0.0);
+  for (int p = 0; p < P.n_ktypes; ++p) {
+    int k = P.ktype_k[p];
+    std::vector<std::complex<double>> K(k * k), A(static_cast<size_t>(N) * k), B(static_cast<size_t>(N) * k);
+    for (int i = 0; i < k * k; ++i)
+      K[i] = {P.kvals[2 * (P.ktype_off[p] + i)], P.kvals[2 * (P.ktype_off[p] + i) + 1]};
+    for (int r = 0; r < N; ++r)
+      for (int u = 0; u < k; ++u) A[r * k + u] = unit_root(static_cast<long long>(u) * (r - N / 2), N);
+    // B[r][v] = sum_u A[r][u] K[u][v]
+    for (int r = 0; r < N; ++r)
+      for (int v = 0; v < k; ++v) {
+        std::complex<double> s = 0;
+        for (int u = 0; u < k; ++u) s += A[r * k + u] * K[u * k + v];
+        B[r * k + v] = s;
+      }
+    double* out = &P.Pp[static_cast<size_t>(p) * N * N];
+    for (int r = 0; r < N; ++r)
+      for (int q = 0; q < N; ++q) {
+        std::complex<double> s = 0;
+        for (int v = 0; v < k; ++v) s += B[r * k + v] * A[q * k + v];
+        out[r * N + q] = std::norm(s);
+      }
+  }
+
+  // ---- twiddles
+  P.twiddle.resize(2 * N);
+  for (int k = 0; k < N; ++k) {
+    std::complex<double> w = unit_root(k, N);
+    P.twiddle[2 * k] = static_cast<float>(w.real());
+    P.twiddle[2 * k + 1] = static_cast<float>(w.imag());
+  }
+
+  // ---- fused frame transform: folded-grid gather programs, one per column class w
+  P.shape = frame_shape(N);
+  const FrameShape& S = P.shape;
+  if (S.N != N) return fail(why, MOFF_ERR_UNSUPPORTED, "no frame shape for this grid size");
+  P.M = N / S.SX;
+  P.NZR = std::min(L, P.M);
+  P.NJ = std::max(1, L / P.M);
+  P.ZP = grid_pitch(P.M);
+  P.weights.assign(static_cast<size_t>(2) * S.SX * P.NJ * P.n_taps, 0.f);
+  for (int w = 0; w < S.SX; ++w)
+    for (int j = 0; j < P.NJ; ++j) {
+      std::complex<double> rot = unit_root(static_cast<long long>(j) * w, S.SX);
+      for (int t = 0; t < P.n_taps; ++t) {
+        std::complex<double> kv(P.kvals[2 * t], P.kvals[2 * t + 1]);
+        std::complex<double> wv = kv * rot;
+        size_t at = (static_cast<size_t>(w) * P.NJ * P.n_taps + j * P.n_taps + t) * 2;
+        P.weights[at] = static_cast<float>(wv.real());
+        P.weights[at + 1] = static_cast<float>(wv.imag());
+      }
+    }
+
+  // folded cells (iy, n'), n' < NZR, row-major; entries from cells (iy, n' + j M), j ascending,
+  // antenna ascending within a cell.  Every folded cell is written every frame (an empty one by a
+  // single entry that reads the all-zero antenna slot).
+  const int ncell = L * P.NZR;
+  std::vector<int> cost(ncell);
+  int maxc = 0;
+  for (int iy = 0; iy < L; ++iy)
+    for (int n = 0; n < P.NZR; ++n) {
+      int c = 0;
+      for (int j = 0; j < P.NJ; ++j) {
+        int ix = n + j * P.M;
+        if (ix < L) c += P.csr_ptr[iy * L + ix + 1] - P.csr_ptr[iy * L + ix];
+      }
+      maxc = std::max(maxc, c);
+      cost[iy * P.NZR + n] = std::max(1, c);
+    }
+  P.max_cell_entries = maxc;
+  // smallest per-lane load B for which a contiguous greedy split needs <= NT lanes
+  auto lanes_needed = [&](long long B) {
+    int lanes = 1;
+    long long cur = 0;
+    for (int i = 0; i < ncell; ++i) {
+      if (cur + cost[i] > B) {
+        ++lanes;
+        cur = 0;
+      }
+      cur += cost[i];
+    }
+    return lanes;
+  };
+  long long lo = *std::max_element(cost.begin(), cost.end());
+  long long hi = std::accumulate(cost.begin(), cost.end(), 0LL);
+  while (lo < hi) {
+    long long mid = (lo + hi) / 2;
+    if (lanes_needed(mid) <= S.NT) hi = mid;
+    else lo = mid + 1;
+  }
+  const long long B = lo;
+  P.prog_len = static_cast<int>(B);
+  if (P.prog_len > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
+  const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
+  P.prog.assign(static_cast<size_t>(S.SX) * P.prog_len * S.NT, GatherEntry{zero_slot, 0});
+  for (int w = 0; w < S.SX; ++w) {
+    GatherEntry* base = &P.prog[static_cast<size_t>(w) * P.prog_len * S.NT];
+    int lane = 0, k = 0;
+    long long cur = 0;
+    for (int i = 0; i < ncell; ++i) {
+      if (cur + cost[i] > B) {
+        ++lane;
+        k = 0;
+        cur = 0;
+      }
+      cur += cost[i];
+      const int iy = i / P.NZR, n = i % P.NZR;
+      const uint32_t dst = static_cast<uint32_t>(iy * P.ZP + n);
+      int emitted = 0;
+      for (int j = 0; j < P.NJ; ++j) {
+        int ix = n + j * P.M;
+        if (ix >= L) continue;
+        for (int e = P.csr_ptr[iy * L + ix]; e < P.csr_ptr[iy * L + ix + 1]; ++e) {
+          uint32_t wi = static_cast<uint32_t>(j * P.n_taps + P.csr_tap[e]);
+          base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (wi << 12), dst};
+          ++k;
+          ++emitted;
+        }
+      }
+      if (emitted == 0) {
+        base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{zero_slot, dst};
+        ++k;
+      }
+      base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
+    }
+  }
+  if (P.NJ * P.n_taps >= 2048) return fail(why, MOFF_ERR_UNSUPPORTED, "too many kernel taps for the gather encoding");
+  return MOFF_OK;
+}
+
+}  // namespace moff

@@ -1,0 +1,68 @@
+// Host side of a MOFF plan: everything computed once per geometry
+// (Sec. 3: the antenna-to-grid mapping and W(r) need only be determined once).
+// Pure C++17, no HIP; compiled without FP contraction so that the footprint
+// cell of every antenna is decided by the same IEEE double operations as in
+// its definition.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/moff.h"
+#include "shape.h"
+
+namespace moff {
+
+// A gather entry of the fused kernel: 8 bytes, read coalesced by lane.
+//   x bits  0..11 : antenna slot in LDS (n_ant = the all-zero slot)
+//   x bits 12..21 : weight index into the workgroup's complex weight table
+//   x bit  31     : last entry of its cell -> store the running sum
+//   y             : LDS element index of the cell in the folded grid (if stored)
+struct GatherEntry {
+  uint32_t x, y;
+};
+
+constexpr uint32_t kStoreBit = 0x80000000u;
+constexpr int kMaxAnt = 4000;
+constexpr int kMaxTypes = 4;
+constexpr int kMaxK = 15;
+
+struct HostPlan {
+  // geometry (copied)
+  int n_ant = 0, n_ktypes = 0, n_chan = 0, N = 0, L = 0;
+  uint32_t flags = 0;
+  double cell_m = 0;
+  std::vector<double> ant_xy, freq_hz, lm_per_pixel;
+  std::vector<int32_t> ktype_k, ktype_off, ant_ktype;
+  std::vector<float> kvals;                 // float32 (re, im) as given, all types back to back
+  int n_taps = 0;                            // total table entries over all types
+
+  // placement
+  std::vector<int32_t> ix0, iy0;
+
+  // staged gridding: CSR over the L x L aperture cells, entries sorted by antenna
+  std::vector<int32_t> csr_ptr;              // [L*L + 1]
+  std::vector<int32_t> csr_ant, csr_tap;     // [nnz]
+
+  // power patterns, float64 [n_ktypes][N][N] in image pixel order
+  std::vector<double> Pp;
+
+  // twiddles w_N^k = exp(+2 pi i k / N), k < N, float32 (re, im)
+  std::vector<float> twiddle;
+
+  // fused frame transform
+  FrameShape shape{};
+  int M = 0, NZR = 0, NJ = 0, ZP = 0;
+  int prog_len = 0;                          // entries per lane (padded)
+  std::vector<GatherEntry> prog;             // [SX][prog_len][NT]
+  std::vector<float> weights;                // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
+  int max_cell_entries = 0;
+};
+
+// Validate the geometry and build every host table.  Returns MOFF_OK or the
+// status describing the first problem; `why` gets a human-readable reason.
+moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* why);
+
+}  // namespace moff
