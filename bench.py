@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; channels shard across GPUs "
@@ -77,6 +79,13 @@ def main():
     import torch
     import paper_1510_08318_amd as moff
     import synth
+
+    if args.copy_mib > 0:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     w = synth.make_config(args.config)
     T, C, Na = w.E.shape
