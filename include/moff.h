@@ -149,8 +149,8 @@ moff_status moff_plan_power_pattern(moff_plan plan, int32_t ktype, double* out);
  * column class `w` (0 <= w < *n_classes).  Call with out = NULL to get the
  * sizes.  out receives uint32 [prog_len][n_threads][2] entries (x, y):
  *   x bits 0..11 antenna slot (n_ant = the zero slot), bits 12..22 weight
- *   index, bit 31 "cell complete: store"; y = LDS element index of the cell
- *   in the folded grid, row pitch *row_pitch.
+ *   index, bit 31 "cell complete: store"; y = LDS element iy * (*row_pitch) + n'
+ *   of the folded-grid cell (iy, n').
  * weights (may be NULL) receives complex64 [n_weights] for class w:
  *   K[tap] * exp(+2 pi i j w / n_classes) at index j * n_taps + tap.
  * Used by host-side tests; the data never changes after plan creation.

@@ -3,8 +3,8 @@
 // q = SX * m + w of one workgroup, staged in LDS (Sec. 3, spatial Fourier
 // transform; zero padding to twice the aperture per axis, Sec. 6.1).
 //
-// Layout in LDS: the folded aperture grid G[iy][n'] (iy < L, n' < M, row pitch
-// ZP complex elements), where
+// Layout in LDS: the folded aperture grid G[iy][n'] (iy < L, n' < M, row
+// pitch M + 1 complex elements), where
 //     G[iy][n'] = sum_j exp(+2 pi i j w / SX) Eg[iy][n' + j M]
 // so that the output column q = SX m + w of row iy is
 //     Z[iy][m] = sum_{n'} G[iy][n'] w_N^{n' w} w_M^{n' m}      (an M-point DFT),
@@ -32,126 +32,174 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+constexpr int cmin(int a, int b) { return a < b ? a : b; }
+
+// Lane mapping.  Every line (row or column) is transformed by LP lanes of one
+// wave that sit 64/LP apart (lane = line_in_step + (64/LP) sub), so each group of
+// 16 consecutive lanes touches 16 different lines at the same position.  With a
+// row pitch of M + 1 (odd) every 8-byte LDS access of the transform then hits 16
+// distinct banks per 16-lane group -- the unit in which gfx950 serves 64-bit LDS
+// accesses -- and every address is a per-lane base plus a compile-time offset.
 template <int N_>
 struct FT {
   static constexpr FrameShape S = frame_shape(N_);
   static constexpr int N = N_, NT = S.NT, SX = S.SX, M = N / SX, L = N / 2, NW = NT / 64;
-  static constexpr int PR = S.PR, QR = S.QR, PC = S.PC, QC = S.QC, LPC = S.LPC;
+  static constexpr int PR = S.PR, QR = S.QR, PC = S.PC, QC = S.QC;
   static constexpr int NZR = L < M ? L : M;
   static constexpr int PRNZ = NZR / QR;          // nonzero inputs of the row pass A
-  static constexpr int JBR = PR / QR;            // row pass-B jobs per lane
-  static constexpr int RPW = 64 / QR;            // rows per wave per step
+  static constexpr int LPR = cmin(4, QR);        // lanes per row
+  static constexpr int RPW = 64 / LPR;           // rows per wave per step
+  static constexpr int JAR = QR / LPR;           // row pass-A jobs per lane
+  static constexpr int JBR = PR / LPR;           // row pass-B jobs per lane
   static constexpr int RSTEPS = (L + NW * RPW - 1) / (NW * RPW);
   static constexpr bool RGUARD = (L % (NW * RPW)) != 0;
   static constexpr int PH = PC / 2;              // column pass-A length per half-round
+  static constexpr int LPC = cmin(4, cmin(QC, PH));  // lanes per column
+  static constexpr int CPW = 64 / LPC;           // columns per wave per step
   static constexpr int JA = QC / LPC;            // column pass-A jobs per lane
   static constexpr int JB = PH / LPC;            // column pass-B jobs per lane per half-round
-  static constexpr int CPW = 64 / LPC;           // columns per wave per step
   static constexpr int CSTEPS = (M + NW * CPW - 1) / (NW * CPW);
   static constexpr bool CGUARD = (M % (NW * CPW)) != 0;
-  static constexpr int ZP = grid_pitch(M);
+  static constexpr int P = M + 1;                // LDS row pitch of the folded grid
+  static constexpr int GRID = L * P;             // folded grid, complex elements
+  static constexpr int TWR = PR * QR;            // row twiddle table [q1][n2]
+  static constexpr int TWC = PC * QC;            // column twiddle table [q1][n2]
   static constexpr int NACC = CSTEPS * 2 * JB * QC;
   static_assert(PR * QR == M && PC * QC == N, "bad factorisation");
   static_assert(PH * QC == L, "column half-round must fill the L slots");
-  static_assert(QC % LPC == 0 && PH % LPC == 0 && 64 % LPC == 0 && 64 % QR == 0 && PR % QR == 0, "bad lanes");
+  static_assert(QR % LPR == 0 && PR % LPR == 0 && QC % LPC == 0 && PH % LPC == 0, "bad lanes");
   static_assert(NZR % QR == 0, "row pruning must align with the decimation");
 };
 
-// Row stage: Z[iy][m] = sum_{n'} G[iy][n'] w_N^{n' w} w_M^{n' m}, in place.
-// tw: LDS twiddles w_N^k, k < N.
+// Per-workgroup twiddle tables (LDS), built once per launch from w_N^k:
+//   twr[q1 * QR + n2] = w_M^{n2 q1} w_N^{n2 w}   (row pass-A outputs; the second
+//                        factor is the part of the fold twiddle w_N^{n' w},
+//                        n' = QR n1 + n2, that does not depend on n1)
+//   twc[q1 * QC + n2] = w_N^{n2 q1}               (column pass-A outputs)
 template <int N>
-__device__ __forceinline__ void row_stage(float2* G, const float2* tw, int w) {
+__device__ __forceinline__ void build_twiddles(const float2* __restrict__ tw_global, int w, float2* twr, float2* twc) {
+  using C = FT<N>;
+  for (int i = threadIdx.x; i < C::TWR; i += C::NT) {
+    const int q1 = i / C::QR, n2 = i % C::QR;
+    twr[i] = tw_global[(C::SX * n2 * q1 + n2 * w) & (N - 1)];
+  }
+  for (int i = threadIdx.x; i < C::TWC; i += C::NT) {
+    const int q1 = i / C::QC, n2 = i % C::QC;
+    twc[i] = tw_global[(n2 * q1) & (N - 1)];
+  }
+}
+
+// The n1-dependent part of the fold twiddle, w_N^{QR n1 w}, for this workgroup.
+template <int N>
+__device__ __forceinline__ void fold_factors(const float2* __restrict__ tw_global, int w, float2 (&fin)[FT<N>::PRNZ]) {
+  using C = FT<N>;
+#pragma unroll
+  for (int n1 = 0; n1 < C::PRNZ; ++n1) fin[n1] = tw_global[(C::QR * n1 * w) & (N - 1)];
+}
+
+// Row stage: Z[iy][m] = sum_{n'} G[iy][n'] w_N^{n' w} w_M^{n' m}, in place.
+// Pass A (job n2): radix-PR DFT over the stride-QR decimation n' = QR n1 + n2,
+// result (q1, n2) stored at q1 QR + n2; pass B (job q1): radix-QR DFT over n2,
+// result stored at m = q1 + PR q2.
+template <int N>
+__device__ __forceinline__ void row_stage(float2* G, const float2* twr, const float2 (&fin)[FT<N>::PRNZ]) {
   using C = FT<N>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int n2 = lane % C::QR;
+  const int sub = lane / C::RPW;
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
-    const int row = (rs * C::NW + wave) * C::RPW + lane / C::QR;
+    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
     if (C::RGUARD && row >= C::L) continue;
-    float2* R = G + row * C::ZP;
-    float2 x[C::PR];
+    float2* R = G + row * C::P;
+    float2 x[C::JAR][C::PR];
 #pragma unroll
-    for (int n1 = 0; n1 < C::PRNZ; ++n1) {
-      x[n1] = R[C::QR * n1 + n2];
-      if constexpr (C::SX > 1) x[n1] = c_mul(x[n1], tw[((C::QR * n1 + n2) * w) & (N - 1)]);
+    for (int ja = 0; ja < C::JAR; ++ja)
+#pragma unroll
+      for (int n1 = 0; n1 < C::PRNZ; ++n1) {
+        x[ja][n1] = R[sub + C::LPR * ja + C::QR * n1];
+        if constexpr (C::SX > 1) x[ja][n1] = c_mul(x[ja][n1], fin[n1]);
+      }
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja) {
+      const int n2 = sub + C::LPR * ja;
+      dft_pruned<C::PR, C::PRNZ>(x[ja]);
+#pragma unroll
+      for (int q1 = (C::SX > 1 ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twr[q1 * C::QR + n2]);
     }
-    dft_pruned<C::PR, C::PRNZ>(x);
-#pragma unroll
-    for (int q1 = 1; q1 < C::PR; ++q1) x[q1] = c_mul(x[q1], tw[(C::SX * n2 * q1) & (N - 1)]);
     wave_sync();
 #pragma unroll
-    for (int q1 = 0; q1 < C::PR; ++q1) R[q1 * C::QR + n2] = x[q1];
+    for (int ja = 0; ja < C::JAR; ++ja)
+#pragma unroll
+      for (int q1 = 0; q1 < C::PR; ++q1) R[sub + C::LPR * ja + q1 * C::QR] = x[ja][q1];
     wave_sync();
     float2 y[C::JBR][C::QR];
 #pragma unroll
-    for (int jb = 0; jb < C::JBR; ++jb) {
-      const int q1 = n2 + C::QR * jb;
+    for (int jb = 0; jb < C::JBR; ++jb)
 #pragma unroll
-      for (int k = 0; k < C::QR; ++k) y[jb][k] = R[q1 * C::QR + k];
-    }
+      for (int k = 0; k < C::QR; ++k) y[jb][k] = R[(sub + C::LPR * jb) * C::QR + k];
     wave_sync();
 #pragma unroll
     for (int jb = 0; jb < C::JBR; ++jb) {
-      const int q1 = n2 + C::QR * jb;
       Dft<C::QR>::run(y[jb]);
 #pragma unroll
-      for (int q2 = 0; q2 < C::QR; ++q2) R[q1 + C::PR * q2] = y[jb][q2];
+      for (int q2 = 0; q2 < C::QR; ++q2) R[sub + C::LPR * jb + C::PR * q2] = y[jb][q2];
     }
     wave_sync();
   }
 }
 
 // Column stage: Y[r][m] = sum_{iy < L} Z[iy][m] w_N^{iy r} for r < N, in place,
-// handing every output to sink(acc_index, r, m, value) with a compile-time
-// acc_index in [0, NACC).
+// handing every output to sink(acc_index, r, m, value) with acc_index in [0, NACC).
+// Pass A (job n2): the pruned radix-PC DFT over rows QC n1 + n2, split by the
+// parity s of its output q1 = 2 j + s into two half-rounds whose PH outputs are
+// stored at rows j QC + n2; pass B (job j): radix-QC DFT over n2, output row
+// r = q1 + PC q2.
 template <int N, class Sink>
-__device__ __forceinline__ void col_stage(float2* G, const float2* tw, Sink&& sink) {
+__device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& sink) {
   using C = FT<N>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int lc = lane % C::LPC;
+  const int sub = lane / C::CPW;
 #pragma unroll
   for (int cs = 0; cs < C::CSTEPS; ++cs) {
-    const int col = (cs * C::NW + wave) * C::CPW + lane / C::LPC;
+    const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
     if (C::CGUARD && col >= C::M) continue;
-    float2* Zc = G + col;
+    float2* Zc = G + col + sub * C::P;     // row `sub` of this column
     float2 z[C::JA][C::PH];
 #pragma unroll
-    for (int ja = 0; ja < C::JA; ++ja) {
-      const int n2 = lc + C::LPC * ja;
+    for (int ja = 0; ja < C::JA; ++ja)
 #pragma unroll
-      for (int n1 = 0; n1 < C::PH; ++n1) z[ja][n1] = Zc[(C::QC * n1 + n2) * C::ZP];
-    }
+      for (int n1 = 0; n1 < C::PH; ++n1) z[ja][n1] = Zc[(C::LPC * ja + C::QC * n1) * C::P];
     wave_sync();
     static_for<0, 2>([&](auto sc) {
       constexpr int s = decltype(sc)::value;
 #pragma unroll
       for (int ja = 0; ja < C::JA; ++ja) {
-        const int n2 = lc + C::LPC * ja;
+        const int n2 = sub + C::LPC * ja;
         float2 u[C::PH];
         static_for<0, C::PH>([&](auto nc) {
           constexpr int n1 = decltype(nc)::value;
-          u[n1] = s ? rot<C::PC, n1>(z[ja][n1]) : z[ja][n1];
+          if constexpr (s == 0) u[n1] = z[ja][n1];
+          else u[n1] = rot<C::PC, n1>(z[ja][n1]);
         });
         Dft<C::PH>::run(u);
 #pragma unroll
         for (int j = 0; j < C::PH; ++j) {
           const int q1 = 2 * j + s;
-          if (q1 != 0) u[j] = c_mul(u[j], tw[(n2 * q1) & (N - 1)]);
-          Zc[(j * C::QC + n2) * C::ZP] = u[j];
+          if (q1 != 0) u[j] = c_mul(u[j], twc[q1 * C::QC + n2]);
+          Zc[(C::LPC * ja + j * C::QC) * C::P] = u[j];
         }
       }
       wave_sync();
       float2 v[C::JB][C::QC];
+      const float2* Zb = G + col + sub * C::QC * C::P;   // row (sub QC) of this column
 #pragma unroll
-      for (int jb = 0; jb < C::JB; ++jb) {
-        const int j = lc + C::LPC * jb;
+      for (int jb = 0; jb < C::JB; ++jb)
 #pragma unroll
-        for (int k = 0; k < C::QC; ++k) v[jb][k] = Zc[(j * C::QC + k) * C::ZP];
-      }
+        for (int k = 0; k < C::QC; ++k) v[jb][k] = Zb[(C::LPC * jb * C::QC + k) * C::P];
       wave_sync();
 #pragma unroll
       for (int jb = 0; jb < C::JB; ++jb) {
-        const int j = lc + C::LPC * jb;
+        const int j = sub + C::LPC * jb;
         Dft<C::QC>::run(v[jb]);
 #pragma unroll
         for (int q2 = 0; q2 < C::QC; ++q2) {
@@ -173,8 +221,8 @@ __device__ __forceinline__ void acc_pixel(int idx, int& r, int& col) {
   const int jb = (idx / C::QC) % C::JB;
   const int s = (idx / (C::QC * C::JB)) % 2;
   const int cs = idx / (C::QC * C::JB * 2);
-  const int j = lane % C::LPC + C::LPC * jb;
-  col = (cs * C::NW + wave) * C::CPW + lane / C::LPC;
+  const int j = lane / C::CPW + C::LPC * jb;
+  col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
   r = 2 * j + s + C::PC * q2;
 }
 

@@ -116,14 +116,17 @@ __global__ __launch_bounds__(FT<N>::NT) void fused_kernel(FusedArgs a) {
   const int w = blockIdx.x, c = blockIdx.y, slice = blockIdx.z;
   const int tid = threadIdx.x;
 
-  float2* G = lds;                          // [L][ZP]
-  float2* tw = G + C::L * C::ZP;            // [N]
-  float2* W = tw + N;                       // [n_weights]
+  float2* G = lds;                          // [L][P], row pitch P = M + 1
+  float2* twr = G + C::GRID;                // [PR * QR]
+  float2* twc = twr + C::TWR;               // [PC * QC]
+  float2* W = twc + C::TWC;                 // [n_weights]
   float2* gl = W + a.n_weights;             // [n_ant] gains of this channel
   float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
   int* ty = reinterpret_cast<int*>(e + a.n_ant + 1);  // [n_ant]
 
-  for (int i = tid; i < N; i += NT) tw[i] = a.tw[i];
+  build_twiddles<N>(a.tw, w, twr, twc);
+  float2 fin[C::PRNZ];
+  fold_factors<N>(a.tw, w, fin);
   for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
   for (int i = tid; i < a.n_ant; i += NT) {
     gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
@@ -156,9 +159,9 @@ __global__ __launch_bounds__(FT<N>::NT) void fused_kernel(FusedArgs a) {
     __syncthreads();
     gather_frame<NT>(prog, a.prog_len, e, W, G);
     __syncthreads();
-    row_stage<N>(G, tw, w);
+    row_stage<N>(G, twr, fin);
     __syncthreads();
-    col_stage<N>(G, tw, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
+    col_stage<N>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
   }
 
   block_sum4<NT>(pw, Atot);
@@ -277,10 +280,13 @@ __global__ __launch_bounds__(FT<N>::NT) void fft2_kernel(Fft2Args a) {
   using C = FT<N>;
   extern __shared__ float2 lds[];
   float2* G = lds;
-  float2* tw = G + C::L * C::ZP;
+  float2* twr = G + C::GRID;
+  float2* twc = twr + C::TWR;
   const int w = blockIdx.x % C::SX;
   const int64_t f = blockIdx.x / C::SX;
-  for (int i = threadIdx.x; i < N; i += C::NT) tw[i] = a.tw[i];
+  build_twiddles<N>(a.tw, w, twr, twc);
+  float2 fin[C::PRNZ];
+  fold_factors<N>(a.tw, w, fin);
   const float2* src = a.Eg + static_cast<size_t>(f) * C::L * C::L;
   for (int cell = threadIdx.x; cell < C::L * C::NZR; cell += C::NT) {
     const int iy = cell / C::NZR, n = cell % C::NZR;
@@ -289,13 +295,13 @@ __global__ __launch_bounds__(FT<N>::NT) void fft2_kernel(Fft2Args a) {
       const float2 x = quarter_rot(src[iy * C::L + n + j * C::M], j * w, C::SX);
       v = c_add(v, x);
     }
-    G[iy * C::ZP + n] = v;
+    G[iy * C::P + n] = v;
   }
   __syncthreads();
-  row_stage<N>(G, tw, w);
+  row_stage<N>(G, twr, fin);
   __syncthreads();
   float2* dst = a.Y + static_cast<size_t>(f) * N * N;
-  col_stage<N>(G, tw, [&](int, int r, int col, float2 v) {
+  col_stage<N>(G, twc, [&](int, int r, int col, float2 v) {
     const int q = C::SX * col + w;
     dst[((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1))] = v;
   });
@@ -340,7 +346,7 @@ __global__ __launch_bounds__(256) void zero_kernel(uint32_t* p, size_t n) {
 size_t fused_lds_bytes(int N, int n_weights, int n_ant) {
   const FrameShape S = frame_shape(N);
   const int M = N / S.SX, L = N / 2;
-  return sizeof(float2) * (static_cast<size_t>(L) * grid_pitch(M) + N + n_weights + n_ant + n_ant + 1) +
+  return sizeof(float2) * (static_cast<size_t>(L) * grid_pitch(M) + M + N + n_weights + n_ant + n_ant + 1) +
          sizeof(int) * n_ant;
 }
 
@@ -375,7 +381,7 @@ hipError_t launch_fused_n(const FusedArgs& a, int mode, bool ci4, hipStream_t st
 template <int N>
 hipError_t launch_fft2_t(const Fft2Args& a, int64_t n_frames, hipStream_t st) {
   const FrameShape S = frame_shape(N);
-  const size_t lds = sizeof(float2) * (static_cast<size_t>(N / 2) * grid_pitch(N / S.SX) + N);
+  const size_t lds = sizeof(float2) * (static_cast<size_t>(N / 2) * grid_pitch(N / S.SX) + N / S.SX + N);
   auto k = fft2_kernel<N>;
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));

@@ -19,7 +19,7 @@ namespace moff {
 //   x bits  0..11 : antenna slot in LDS (n_ant = the all-zero slot)
 //   x bits 12..21 : weight index into the workgroup's complex weight table
 //   x bit  31     : last entry of its cell -> store the running sum
-//   y             : LDS element index of the cell in the folded grid (if stored)
+//   y             : LDS element iy * ZP + n' of the folded-grid cell (if stored)
 struct GatherEntry {
   uint32_t x, y;
 };
@@ -54,7 +54,7 @@ struct HostPlan {
 
   // fused frame transform
   FrameShape shape{};
-  int M = 0, NZR = 0, NJ = 0, ZP = 0;
+  int M = 0, NZR = 0, NJ = 0, ZP = 0;         // ZP: LDS row pitch of the folded grid
   int prog_len = 0;                          // entries per lane (padded)
   std::vector<GatherEntry> prog;             // [SX][prog_len][NT]
   std::vector<float> weights;                // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)

@@ -162,6 +162,9 @@ def test_gather_program_replays_oracle_grid(moff, case):
             ref = np.zeros((L, NZR), complex)
             for j in range(max(1, L // M)):
                 ref += np.exp(2j * np.pi * j * cls / SX) * Eg[:, j * M:j * M + NZR]
-            got = G.reshape(L, ZP)[:, :NZR]
-            assert (stored.reshape(L, ZP)[:, :NZR] == 1).all()
+            iy = np.arange(L)[:, None]
+            n = np.arange(NZR)[None, :]
+            slot = iy * ZP + n
+            got = G[slot]
+            assert (stored[slot] == 1).all() and stored.sum() == L * NZR
             assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
