@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (heuristic configuration)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -98,6 +99,9 @@ def main():
     nnz = int(sum(w.geom.ktype_k[t] ** 2 for t in w.geom.ant_ktype))
     frames = T * C
 
+    if not args.no_tune:
+        plan.autotune(E, gains)
+    launch = plan.config(T)
     for _ in range(args.warmup):
         plan.image(E, gains, out=out)
     torch.cuda.synchronize()
@@ -158,7 +162,8 @@ def main():
         "data": "synthetic (seeded LWA-shaped sky + noise, 4+4-bit quantised)",
         "config": {"workload": "LWA-shaped MOFF imaging: 256 antennas in a 100 m disc, 3x3 dipole kernel, "
                                "128 channels 40-80 MHz, 1000 time samples, 128x128 grid, complex 4+4-bit input",
-                   "n_ant": Na, "n_chan": C, "n_time": T, "grid": N, "input": "ci4"},
+                   "n_ant": Na, "n_chan": C, "n_time": T, "grid": N, "input": "ci4",
+                   "launch": {k: launch[k] for k in ("variant", "slices", "grid", "threads", "tuned")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
         "cpu_baseline": cpu,

@@ -145,8 +145,8 @@ moff_status moff_plan_query(moff_plan plan, int32_t* cells, double* cell_m,
 moff_status moff_plan_power_pattern(moff_plan plan, int32_t ktype, double* out);
 
 /*
- * Diagnostic copy of the fused kernel's cell-keyed gather program for output
- * column class `w` (0 <= w < *n_classes).  Call with out = NULL to get the
+ * Diagnostic copy of the fused kernel's cell-keyed gather program of shape
+ * variant `variant` for output column class `w` (0 <= w < *n_classes).  Call with out = NULL to get the
  * sizes.  out receives uint32 [prog_len][n_threads][2] entries (x, y):
  *   x bits 0..11 antenna slot (n_ant = the zero slot), bits 12..22 weight
  *   index, bit 31 "cell complete: store"; y = LDS element iy * (*row_pitch) + n'
@@ -155,9 +155,30 @@ moff_status moff_plan_power_pattern(moff_plan plan, int32_t ktype, double* out);
  *   K[tap] * exp(+2 pi i j w / n_classes) at index j * n_taps + tap.
  * Used by host-side tests; the data never changes after plan creation.
  */
-moff_status moff_plan_gather_program(moff_plan plan, int32_t w, uint32_t* out, float* weights,
+moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w, uint32_t* out, float* weights,
                                      int32_t* prog_len, int32_t* n_threads, int32_t* n_classes,
                                      int32_t* row_pitch, int32_t* n_weights);
+
+/*
+ * Launch configuration of the fused path.  The frame transform has one or two
+ * shape variants per grid size (how output columns are split across
+ * workgroups, threads per workgroup); a launch also chooses the number of time
+ * slices: each (column class, channel, slice) is one workgroup, and per-slice
+ * partial sums are reduced afterwards in a fixed order.
+ *
+ * moff_plan_autotune times every candidate (variant x slices, including the
+ * slice counts that fill whole rounds of resident workgroups) with HIP events
+ * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
+ * the stream; later results do not depend on the choice beyond float32
+ * rounding order.  moff_plan_set_config forces a choice (slices = 0:
+ * heuristic); moff_plan_get_config reports the configuration a call with
+ * n_time samples would use.  Any output of get_config may be NULL.
+ */
+moff_status moff_plan_autotune(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
+                               void* hip_stream);
+moff_status moff_plan_set_config(moff_plan plan, int32_t variant, int32_t slices);
+moff_status moff_plan_get_config(moff_plan plan, int64_t n_time, int32_t* variant, int32_t* slices, int32_t* grid,
+                                 int32_t* threads, int32_t* n_variants, int32_t* tuned);
 
 /*
  * Kernel timing.  With timing enabled, every fused call records a pair of HIP

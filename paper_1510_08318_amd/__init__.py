@@ -116,16 +116,28 @@ class Plan:
         _lib.moff_plan_power_pattern(self.handle, int(ktype), _ptr(out, ctypes.c_double))
         return out
 
-    def gather_program(self, w):
-        """(entries uint32 [prog_len, n_threads, 2], weights complex64, row_pitch) of class w."""
+    def gather_program(self, w, variant=0):
+        """(entries uint32 [prog_len, n_threads, 2], weights complex64, sizes) of class w."""
         sizes = [ctypes.c_int32() for _ in range(5)]
-        _lib.moff_plan_gather_program(self.handle, 0, None, None, *[ctypes.byref(s) for s in sizes])
+        _lib.moff_plan_gather_program(self.handle, int(variant), 0, None, None, *[ctypes.byref(s) for s in sizes])
         plen, nt, ncls, pitch, nw = (s.value for s in sizes)
         out = np.zeros((plen, nt, 2), np.uint32)
         wts = np.zeros(2 * nw, np.float32)
-        _lib.moff_plan_gather_program(self.handle, int(w), _ptr(out, ctypes.c_uint32), _ptr(wts, ctypes.c_float),
-                                      *[ctypes.byref(s) for s in sizes])
+        _lib.moff_plan_gather_program(self.handle, int(variant), int(w), _ptr(out, ctypes.c_uint32),
+                                      _ptr(wts, ctypes.c_float), *[ctypes.byref(s) for s in sizes])
         return out, wts.view(np.complex64), dict(prog_len=plen, n_threads=nt, n_classes=ncls, row_pitch=pitch)
+
+    def autotune(self, E, gains=None, stream=None):
+        """Time every launch configuration on this input and keep the fastest."""
+        pE, T = self._E(E)
+        _lib.moff_plan_autotune(self.handle, pE, T, self._gains(gains), self._stream(stream))
+        return self.config(T)
+
+    def set_config(self, variant=0, slices=0):
+        _lib.moff_plan_set_config(self.handle, int(variant), int(slices))
+
+    def config(self, n_time):
+        return _lib.moff_plan_get_config(self.handle, int(n_time))
 
     def set_timing(self, enable=True):
         _lib.moff_plan_set_timing(self.handle, enable)

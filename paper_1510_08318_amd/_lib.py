@@ -51,8 +51,13 @@ SIGNATURES = {
     "moff_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "moff_plan_query": (ctypes.c_int, [ctypes.c_void_p, c_i32p, c_f64p, c_f64p, c_i32p]),
     "moff_plan_power_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_f64p]),
-    "moff_plan_gather_program": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_u32p, c_f32p, c_i32p, c_i32p,
-                                                c_i32p, c_i32p, c_i32p]),
+    "moff_plan_gather_program": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, c_u32p, c_f32p,
+                                                c_i32p, c_i32p, c_i32p, c_i32p, c_i32p]),
+    "moff_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p]),
+    "moff_plan_set_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "moff_plan_get_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, c_i32p, c_i32p, c_i32p, c_i32p, c_i32p,
+                                            c_i32p]),
     "moff_plan_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "moff_plan_last_kernel_ms": (ctypes.c_int, [ctypes.c_void_p, c_f64p]),
     "moff_image": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -141,8 +146,23 @@ def moff_plan_power_pattern(plan, ktype, out):
     _call("moff_plan_power_pattern", plan, ktype, out)
 
 
-def moff_plan_gather_program(plan, w, out, weights, prog_len, n_threads, n_classes, row_pitch, n_weights):
-    _call("moff_plan_gather_program", plan, w, out, weights, prog_len, n_threads, n_classes, row_pitch, n_weights)
+def moff_plan_gather_program(plan, variant, w, out, weights, prog_len, n_threads, n_classes, row_pitch, n_weights):
+    _call("moff_plan_gather_program", plan, variant, w, out, weights, prog_len, n_threads, n_classes, row_pitch,
+          n_weights)
+
+
+def moff_plan_autotune(plan, E, n_time, gains, stream):
+    _call("moff_plan_autotune", plan, E, n_time, gains, stream)
+
+
+def moff_plan_set_config(plan, variant, slices):
+    _call("moff_plan_set_config", plan, variant, slices)
+
+
+def moff_plan_get_config(plan, n_time):
+    vals = [ctypes.c_int32() for _ in range(6)]
+    _call("moff_plan_get_config", plan, n_time, *[ctypes.byref(v) for v in vals])
+    return dict(zip(("variant", "slices", "grid", "threads", "n_variants", "tuned"), (v.value for v in vals)))
 
 
 def moff_plan_set_timing(plan, enable):

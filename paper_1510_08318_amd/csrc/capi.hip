@@ -19,8 +19,8 @@ struct moff_plan_s {
   HostPlan hp;
   int device = -1;
   // device tables
-  GatherEntry* d_prog = nullptr;
-  float2* d_weights = nullptr;
+  GatherEntry* d_prog[moff::kMaxVariants] = {};
+  float2* d_weights[moff::kMaxVariants] = {};
   float2* d_tw = nullptr;
   double* d_Pp = nullptr;
   int* d_ant_type = nullptr;
@@ -34,6 +34,11 @@ struct moff_plan_s {
   // optional kernel timing
   bool timing = false, timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // fused launch configuration (heuristic default, or chosen by the autotuner)
+  int cu_count = 0;
+  int variant = 0;          // index into hp.variants
+  int slices = 0;           // time slices; 0 = heuristic
+  bool tuned = false;
 };
 
 namespace {
@@ -65,10 +70,13 @@ moff_status upload(T** dst, const void* src, size_t bytes) {
 }
 
 void free_device(moff_plan p) {
-  void* ptrs[] = {p->d_prog, p->d_weights, p->d_tw,      p->d_Pp,      p->d_ant_type,
-                  p->d_ktab, p->d_csr_ptr, p->d_csr_ant, p->d_csr_tap, p->d_ws};
+  void* ptrs[] = {p->d_tw, p->d_Pp, p->d_ant_type, p->d_ktab, p->d_csr_ptr, p->d_csr_ant, p->d_csr_tap, p->d_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
+  for (int v = 0; v < moff::kMaxVariants; ++v) {
+    if (p->d_prog[v]) (void)hipFree(p->d_prog[v]);
+    if (p->d_weights[v]) (void)hipFree(p->d_weights[v]);
+  }
   if (p->ev0) (void)hipEventDestroy(p->ev0);
   if (p->ev1) (void)hipEventDestroy(p->ev1);
 }
@@ -104,26 +112,41 @@ double image_scale(const HostPlan& hp, int64_t n_time) {
   return s;
 }
 
-// Number of time slices of the fused launch: enough workgroups to cover the
-// chip several times over, never more than the frames available.
-int choose_slices(const HostPlan& hp, int64_t n_time) {
-  const int per_slice = hp.shape.SX * hp.n_chan;
-  const int target = 2048;
-  int s = (target + per_slice - 1) / per_slice;
-  s = std::min<int64_t>(s, n_time);
-  s = std::min(s, 64);
-  return std::max(s, 1);
+struct LaunchConfig {
+  int variant, slices, grid;
+};
+
+// Launch configuration for n_time frames: the tuned or set choice, else a
+// heuristic: shape variant 0 and enough time slices for about two rounds of
+// resident workgroups.  One work item (column class, channel, time slice) per
+// workgroup.
+LaunchConfig launch_config(moff_plan p, int64_t n_time) {
+  const HostPlan& hp = p->hp;
+  LaunchConfig lc{};
+  lc.variant = std::min<int>(p->variant, static_cast<int>(hp.variants.size()) - 1);
+  const HostPlan::Variant& V = hp.variants[lc.variant];
+  const int per_slice = V.shape.SX * hp.n_chan;
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  const size_t lds = moff::fused_lds_bytes(hp.N, lc.variant, V.n_weights(), hp.n_ant);
+  const int resident = std::max(1, moff::fused_blocks_per_cu(hp.N, lc.variant, ci4, lds)) * std::max(1, p->cu_count);
+  int slices = p->slices;
+  if (slices <= 0) slices = (2 * resident + per_slice - 1) / per_slice;
+  slices = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({static_cast<int64_t>(slices), n_time, 256})));
+  lc.slices = slices;
+  lc.grid = per_slice * slices;
+  return lc;
 }
 
-moff::FusedArgs fused_args(moff_plan p, const void* E, int64_t n_time, const float* gains) {
+moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_time, const float* gains) {
   const HostPlan& hp = p->hp;
+  const HostPlan::Variant& V = hp.variants[variant];
   moff::FusedArgs a{};
   a.E = E;
   a.gains = reinterpret_cast<const float2*>(gains);
-  a.prog = p->d_prog;
-  a.prog_len = hp.prog_len;
-  a.weights = p->d_weights;
-  a.n_weights = hp.NJ * hp.n_taps;
+  a.prog = p->d_prog[variant];
+  a.prog_len = V.prog_len;
+  a.weights = p->d_weights[variant];
+  a.n_weights = V.n_weights();
   a.tw = p->d_tw;
   a.ant_type = p->d_ant_type;
   a.n_ant = hp.n_ant;
@@ -135,20 +158,20 @@ moff::FusedArgs fused_args(moff_plan p, const void* E, int64_t n_time, const flo
   return a;
 }
 
-moff_status fused_run(moff_plan p, const void* E, int64_t n_time, const float* gains, float* out,
-                      double* outA, bool final_image, hipStream_t st) {
+moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, int64_t n_time, const float* gains,
+                          float* out, double* outA, bool final_image, hipStream_t st) {
   const HostPlan& hp = p->hp;
-  moff::FusedArgs a = fused_args(p, E, n_time, gains);
+  moff::FusedArgs a = fused_args(p, lc.variant, E, n_time, gains);
   const bool ci4 = hp.flags & MOFF_IN_CI4;
-  if (moff::fused_lds_bytes(hp.N, a.n_weights, hp.n_ant) > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
-  const int slices = choose_slices(hp, n_time);
-  a.slices = slices;
+  if (moff::fused_lds_bytes(hp.N, lc.variant, a.n_weights, hp.n_ant) > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
+  a.slices = lc.slices;
   a.scale = image_scale(hp, n_time);
-  if (slices == 1) {
+  if (lc.slices == 1) {
     a.out = out;
     a.outA = outA;
+    a.mode = final_image ? moff::kModeFinal : moff::kModeAccum;
     if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-    hipError_t e = moff::launch_fused(a, hp.N, final_image ? moff::kModeFinal : moff::kModeAccum, ci4, st);
+    hipError_t e = moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
     if (e != hipSuccess) return MOFF_ERR_HIP;
     if (p->timing) {
       if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -157,14 +180,15 @@ moff_status fused_run(moff_plan p, const void* E, int64_t n_time, const float* g
     return MOFF_OK;
   }
   const size_t npix = static_cast<size_t>(hp.N) * hp.N;
-  const size_t s_bytes = sizeof(float) * npix * hp.n_chan * slices;
-  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * slices;
+  const size_t s_bytes = sizeof(float) * npix * hp.n_chan * lc.slices;
+  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * lc.slices;
   moff_status ms = ensure_workspace(p, s_bytes + a_bytes);
   if (ms != MOFF_OK) return ms;
   a.out = static_cast<float*>(p->d_ws);
   a.outA = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + s_bytes);
+  a.mode = moff::kModePartial;
   if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-  hipError_t e = moff::launch_fused(a, hp.N, moff::kModePartial, ci4, st);
+  hipError_t e = moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
   if (e != hipSuccess) return MOFF_ERR_HIP;
   if (p->timing) {
     if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -179,11 +203,16 @@ moff_status fused_run(moff_plan p, const void* E, int64_t n_time, const float* g
   r.N = hp.N;
   r.n_chan = hp.n_chan;
   r.n_types = hp.n_ktypes;
-  r.slices = slices;
+  r.slices = lc.slices;
   r.final_image = final_image ? 1 : 0;
   r.subtract = a.subtract;
   r.scale = a.scale;
   return hip_status(moff::launch_reduce(r, st));
+}
+
+moff_status fused_run(moff_plan p, const void* E, int64_t n_time, const float* gains, float* out, double* outA,
+                      bool final_image, hipStream_t st) {
+  return fused_run_cfg(p, launch_config(p, n_time), E, n_time, gains, out, outA, final_image, st);
 }
 
 moff::GridArgs grid_args(moff_plan p, const void* E, int64_t n_time, const float* gains) {
@@ -253,8 +282,12 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
     auto up = [&](moff_status r) {
       if (s == MOFF_OK) s = r;
     };
-    up(upload(&p->d_prog, hp.prog.data(), sizeof(GatherEntry) * hp.prog.size()));
-    up(upload(&p->d_weights, hp.weights.data(), sizeof(float) * hp.weights.size()));
+    for (size_t v = 0; v < hp.variants.size(); ++v) {
+      up(upload(&p->d_prog[v], hp.variants[v].prog.data(), sizeof(GatherEntry) * hp.variants[v].prog.size()));
+      up(upload(&p->d_weights[v], hp.variants[v].weights.data(), sizeof(float) * hp.variants[v].weights.size()));
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
     up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
     up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
     up(upload(&p->d_ant_type, hp.ant_ktype.data(), sizeof(int) * hp.ant_ktype.size()));
@@ -328,27 +361,126 @@ moff_status moff_plan_power_pattern(moff_plan p, int32_t ktype, double* out) {
   return MOFF_OK;
 }
 
-moff_status moff_plan_gather_program(moff_plan p, int32_t w, uint32_t* out, float* weights, int32_t* prog_len,
-                                     int32_t* n_threads, int32_t* n_classes, int32_t* row_pitch, int32_t* n_weights) {
-  if (!p) return MOFF_ERR_INVALID_ARG;
-  const HostPlan& hp = p->hp;
-  if (prog_len) *prog_len = hp.prog_len;
-  if (n_threads) *n_threads = hp.shape.NT;
-  if (n_classes) *n_classes = hp.shape.SX;
-  if (row_pitch) *row_pitch = hp.ZP;
-  const int nw = hp.NJ * hp.n_taps;
+moff_status moff_plan_gather_program(moff_plan p, int32_t variant, int32_t w, uint32_t* out, float* weights,
+                                     int32_t* prog_len, int32_t* n_threads, int32_t* n_classes, int32_t* row_pitch,
+                                     int32_t* n_weights) {
+  if (!p || variant < 0 || variant >= static_cast<int32_t>(p->hp.variants.size())) return MOFF_ERR_INVALID_ARG;
+  const HostPlan::Variant& V = p->hp.variants[variant];
+  if (prog_len) *prog_len = V.prog_len;
+  if (n_threads) *n_threads = V.shape.NT;
+  if (n_classes) *n_classes = V.shape.SX;
+  if (row_pitch) *row_pitch = V.ZP;
+  const int nw = V.n_weights();
   if (n_weights) *n_weights = nw;
   if (!out && !weights) return MOFF_OK;
-  if (w < 0 || w >= hp.shape.SX) return MOFF_ERR_INVALID_ARG;
+  if (w < 0 || w >= V.shape.SX) return MOFF_ERR_INVALID_ARG;
   if (out) {
-    const size_t n = static_cast<size_t>(hp.prog_len) * hp.shape.NT;
-    const GatherEntry* src = hp.prog.data() + n * w;
+    const size_t n = static_cast<size_t>(V.prog_len) * V.shape.NT;
+    const GatherEntry* src = V.prog.data() + n * w;
     for (size_t i = 0; i < n; ++i) {
       out[2 * i] = src[i].x;
       out[2 * i + 1] = src[i].y;
     }
   }
-  if (weights) std::memcpy(weights, hp.weights.data() + static_cast<size_t>(2) * nw * w, sizeof(float) * 2 * nw);
+  if (weights) std::memcpy(weights, V.weights.data() + static_cast<size_t>(2) * nw * w, sizeof(float) * 2 * nw);
+  return MOFF_OK;
+}
+
+moff_status moff_plan_set_config(moff_plan p, int32_t variant, int32_t slices) {
+  if (!p || variant < 0 || variant >= static_cast<int32_t>(p->hp.variants.size()) || slices < 0 || slices > 256)
+    return MOFF_ERR_INVALID_ARG;
+  p->variant = variant;
+  p->slices = slices;
+  p->tuned = false;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_get_config(moff_plan p, int64_t n_time, int32_t* variant, int32_t* slices, int32_t* grid,
+                                 int32_t* threads, int32_t* n_variants, int32_t* tuned) {
+  if (!p || n_time < 1) return MOFF_ERR_INVALID_ARG;
+  if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const LaunchConfig lc = launch_config(p, n_time);
+  if (variant) *variant = lc.variant;
+  if (slices) *slices = lc.slices;
+  if (grid) *grid = lc.grid;
+  if (threads) *threads = p->hp.variants[lc.variant].shape.NT;
+  if (n_variants) *n_variants = static_cast<int32_t>(p->hp.variants.size());
+  if (tuned) *tuned = p->tuned ? 1 : 0;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const float* gains, void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const HostPlan& hp = p->hp;
+  const size_t img_bytes = sizeof(float) * static_cast<size_t>(hp.N) * hp.N * hp.n_chan;
+  float* img = nullptr;
+  if (hipMalloc(&img, img_bytes) != hipSuccess) return MOFF_ERR_NOMEM;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipFree(img);
+    return MOFF_ERR_HIP;
+  }
+  const int saved_v = p->variant, saved_s = p->slices;
+  const bool saved_timing = p->timing;
+  p->timing = false;
+  float best = 1e30f;
+  int bv = saved_v, bs = saved_s;
+  moff_status result = MOFF_OK;
+  for (int v = 0; v < static_cast<int>(hp.variants.size()) && result == MOFF_OK; ++v) {
+    const HostPlan::Variant& V = hp.variants[v];
+    if (moff::fused_lds_bytes(hp.N, v, V.n_weights(), hp.n_ant) > size_t(159) * 1024) continue;
+    const int per_slice = V.shape.SX * hp.n_chan;
+    const size_t lds = moff::fused_lds_bytes(hp.N, v, V.n_weights(), hp.n_ant);
+    const int resident =
+        std::max(1, moff::fused_blocks_per_cu(hp.N, v, hp.flags & MOFF_IN_CI4, lds)) * std::max(1, p->cu_count);
+    std::vector<int> cand;
+    for (int k = 1; k <= 4; ++k) cand.push_back((k * resident + per_slice - 1) / per_slice);  // whole rounds
+    for (int sl : {1, 2, 4, 8, 16, 32, 64}) cand.push_back(sl);
+    std::sort(cand.begin(), cand.end());
+    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
+    for (int sl : cand) {
+      if (sl < 1 || sl > 256 || sl > n_time || result != MOFF_OK) continue;
+      {
+        p->variant = v;
+        p->slices = sl;
+        const LaunchConfig lc = launch_config(p, n_time);
+        result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);   // warm-up
+        if (result != MOFF_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
+        for (int rep = 0; rep < 2 && result == MOFF_OK; ++rep)
+          result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);
+        if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
+        if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
+        float ms = 0.f;
+        if (result == MOFF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+        if (result == MOFF_OK && ms < best) {
+          best = ms;
+          bv = v;
+          bs = sl;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(img);
+  p->timing = saved_timing;
+  if (result != MOFF_OK) {
+    p->variant = saved_v;
+    p->slices = saved_s;
+    return result;
+  }
+  p->variant = bv;
+  p->slices = bs;
+  p->tuned = true;
   return MOFF_OK;
 }
 
@@ -420,7 +552,7 @@ moff_status moff_fft2(moff_plan p, const float* eg, int64_t n_frames, float* y, 
   if (!p) return MOFF_ERR_INVALID_ARG;
   if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
   if (n_frames < 1 || !eg || !y || !aligned16(eg) || !aligned16(y)) return MOFF_ERR_INVALID_ARG;
-  if (n_frames * p->hp.shape.SX >= (int64_t(1) << 31)) return MOFF_ERR_UNSUPPORTED;
+  if (n_frames * p->hp.variants[0].shape.SX >= (int64_t(1) << 31)) return MOFF_ERR_UNSUPPORTED;
   DeviceGuard guard(p->device);
   if (!guard.ok()) return MOFF_ERR_HIP;
   moff::Fft2Args f{reinterpret_cast<const float2*>(eg), reinterpret_cast<float2*>(y), p->d_tw};

@@ -40,9 +40,9 @@ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 // row pitch of M + 1 (odd) every 8-byte LDS access of the transform then hits 16
 // distinct banks per 16-lane group -- the unit in which gfx950 serves 64-bit LDS
 // accesses -- and every address is a per-lane base plus a compile-time offset.
-template <int N_>
+template <int N_, int V_ = 0>
 struct FT {
-  static constexpr FrameShape S = frame_shape(N_);
+  static constexpr FrameShape S = frame_shape(N_, V_);
   static constexpr int N = N_, NT = S.NT, SX = S.SX, M = N / SX, L = N / 2, NW = NT / 64;
   static constexpr int PR = S.PR, QR = S.QR, PC = S.PC, QC = S.QC;
   static constexpr int NZR = L < M ? L : M;
@@ -76,9 +76,9 @@ struct FT {
 //                        factor is the part of the fold twiddle w_N^{n' w},
 //                        n' = QR n1 + n2, that does not depend on n1)
 //   twc[q1 * QC + n2] = w_N^{n2 q1}               (column pass-A outputs)
-template <int N>
+template <int N, int V>
 __device__ __forceinline__ void build_twiddles(const float2* __restrict__ tw_global, int w, float2* twr, float2* twc) {
-  using C = FT<N>;
+  using C = FT<N, V>;
   for (int i = threadIdx.x; i < C::TWR; i += C::NT) {
     const int q1 = i / C::QR, n2 = i % C::QR;
     twr[i] = tw_global[(C::SX * n2 * q1 + n2 * w) & (N - 1)];
@@ -90,9 +90,9 @@ __device__ __forceinline__ void build_twiddles(const float2* __restrict__ tw_glo
 }
 
 // The n1-dependent part of the fold twiddle, w_N^{QR n1 w}, for this workgroup.
-template <int N>
-__device__ __forceinline__ void fold_factors(const float2* __restrict__ tw_global, int w, float2 (&fin)[FT<N>::PRNZ]) {
-  using C = FT<N>;
+template <int N, int V>
+__device__ __forceinline__ void fold_factors(const float2* __restrict__ tw_global, int w, float2 (&fin)[FT<N, V>::PRNZ]) {
+  using C = FT<N, V>;
 #pragma unroll
   for (int n1 = 0; n1 < C::PRNZ; ++n1) fin[n1] = tw_global[(C::QR * n1 * w) & (N - 1)];
 }
@@ -101,9 +101,9 @@ __device__ __forceinline__ void fold_factors(const float2* __restrict__ tw_globa
 // Pass A (job n2): radix-PR DFT over the stride-QR decimation n' = QR n1 + n2,
 // result (q1, n2) stored at q1 QR + n2; pass B (job q1): radix-QR DFT over n2,
 // result stored at m = q1 + PR q2.
-template <int N>
-__device__ __forceinline__ void row_stage(float2* G, const float2* twr, const float2 (&fin)[FT<N>::PRNZ]) {
-  using C = FT<N>;
+template <int N, int V>
+__device__ __forceinline__ void row_stage(float2* G, const float2* twr, const float2 (&fin)[FT<N, V>::PRNZ]) {
+  using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::RPW;
 #pragma unroll
@@ -154,9 +154,9 @@ __device__ __forceinline__ void row_stage(float2* G, const float2* twr, const fl
 // parity s of its output q1 = 2 j + s into two half-rounds whose PH outputs are
 // stored at rows j QC + n2; pass B (job j): radix-QC DFT over n2, output row
 // r = q1 + PC q2.
-template <int N, class Sink>
+template <int N, int V, class Sink>
 __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& sink) {
-  using C = FT<N>;
+  using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::CPW;
 #pragma unroll
@@ -213,9 +213,9 @@ __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& s
 
 // Output pixel coordinates (r, m) of accumulator `idx` for this lane; the
 // same mapping col_stage hands to its sink.
-template <int N>
+template <int N, int V>
 __device__ __forceinline__ void acc_pixel(int idx, int& r, int& col) {
-  using C = FT<N>;
+  using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int q2 = idx % C::QC;
   const int jb = (idx / C::QC) % C::JB;

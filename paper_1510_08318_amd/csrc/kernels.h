@@ -29,6 +29,7 @@ struct FusedArgs {
   const double* Pp;            // [types][N][N]
   double scale;
   int subtract;
+  int mode;                    // kModePartial / kModeAccum / kModeFinal
 };
 
 struct ReduceArgs {
@@ -78,8 +79,11 @@ struct FinalizeArgs {
   double scale;
 };
 
-size_t fused_lds_bytes(int N, int n_weights, int n_ant);
-hipError_t launch_fused(const FusedArgs& a, int N, int mode, bool ci4, hipStream_t st);
+// Fused kernel of grid size N, shape variant V (shape.h), `grid` workgroups
+// (each loops over the SX * n_chan * slices work items with stride `grid`).
+size_t fused_lds_bytes(int N, int V, int n_weights, int n_ant);
+hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st);
+int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds);
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 hipError_t launch_grid(const GridArgs& a, bool ci4, hipStream_t st);
 hipError_t launch_self_power(const GridArgs& a, bool ci4, hipStream_t st);

@@ -107,90 +107,103 @@ __device__ __forceinline__ void gather_frame(const GatherEntry* __restrict__ pro
 // fused kernel
 // ---------------------------------------------------------------------------
 
-template <int N, int MODE, bool CI4>
-__global__ __launch_bounds__(FT<N>::NT) void fused_kernel(FusedArgs a) {
-  using C = FT<N>;
+template <int N, int V, bool CI4>
+__global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
+  using C = FT<N, V>;
   constexpr int NT = C::NT;
   extern __shared__ float2 lds[];
   __shared__ double Atot[kMaxTypesDev];
-  const int w = blockIdx.x, c = blockIdx.y, slice = blockIdx.z;
   const int tid = threadIdx.x;
 
   float2* G = lds;                          // [L][P], row pitch P = M + 1
   float2* twr = G + C::GRID;                // [PR * QR]
   float2* twc = twr + C::TWR;               // [PC * QC]
   float2* W = twc + C::TWC;                 // [n_weights]
-  float2* gl = W + a.n_weights;             // [n_ant] gains of this channel
+  float2* gl = W + a.n_weights;             // [n_ant] gains of the current channel
   float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
   int* ty = reinterpret_cast<int*>(e + a.n_ant + 1);  // [n_ant]
 
-  build_twiddles<N>(a.tw, w, twr, twc);
-  float2 fin[C::PRNZ];
-  fold_factors<N>(a.tw, w, fin);
-  for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
-  for (int i = tid; i < a.n_ant; i += NT) {
-    gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
-    ty[i] = a.ant_type[i];
-  }
+  for (int i = tid; i < a.n_ant; i += NT) ty[i] = a.ant_type[i];
   if (tid == 0) e[a.n_ant] = make_float2(0.f, 0.f);
-
   const int64_t T = a.n_time;
-  const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
-  const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
   const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
-
-  float acc[C::NACC];
-#pragma unroll
-  for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
-  double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
-
-  __syncthreads();
-  for (int64_t t = t0; t < t1; ++t) {
-    // ingest + calibration: e = g * E, and the self power of each antenna type
-    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-    for (int i = tid; i < a.n_ant; i += NT) {
-      const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
-      e[i] = v;
-      const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
-      const int tp = ty[i];
-#pragma unroll
-      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
-    }
-    __syncthreads();
-    gather_frame<NT>(prog, a.prog_len, e, W, G);
-    __syncthreads();
-    row_stage<N>(G, twr, fin);
-    __syncthreads();
-    col_stage<N>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
-  }
-
-  block_sum4<NT>(pw, Atot);
-
   const size_t img_stride = static_cast<size_t>(N) * N;
+  const int n_items = C::SX * a.n_chan * a.slices;
+
+  // One work item (column class w, channel c, time slice) per workgroup.  (A
+  // persistent loop over items makes the compiler keep far more registers live
+  // -- 127 -> 256 VGPRs at N = 64 -- so launches are instead sized in whole
+  // rounds of resident workgroups by the autotuner.)
+  {
+    const int item = blockIdx.x;
+    if (item >= n_items) return;
+    const int w = item % C::SX;
+    const int c = (item / C::SX) % a.n_chan;
+    const int slice = item / (C::SX * a.n_chan);
+
+    __syncthreads();   // the previous item is done with every LDS table
+    build_twiddles<N, V>(a.tw, w, twr, twc);
+    float2 fin[C::PRNZ];
+    fold_factors<N, V>(a.tw, w, fin);
+    for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
+    for (int i = tid; i < a.n_ant; i += NT)
+      gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+
+    const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
+    const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
+
+    float acc[C::NACC];
 #pragma unroll
-  for (int idx = 0; idx < C::NACC; ++idx) {
-    int r, col;
-    acc_pixel<N>(idx, r, col);
-    if (C::CGUARD && col >= C::M) continue;
-    const int q = C::SX * col + w;
-    const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
-    const size_t pix = static_cast<size_t>(pr) * N + pq;
-    if constexpr (MODE == kModePartial) {
-      a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = acc[idx];
-    } else if constexpr (MODE == kModeAccum) {
-      a.out[static_cast<size_t>(c) * img_stride + pix] += acc[idx];
-    } else {
-      double v = acc[idx];
-      if (a.subtract)
-        for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
-      a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
+    double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+
+    __syncthreads();
+    for (int64_t t = t0; t < t1; ++t) {
+      // ingest + calibration: e = g * E, and the self power of each antenna type
+      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+      for (int i = tid; i < a.n_ant; i += NT) {
+        const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+        e[i] = v;
+        const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+        const int tp = ty[i];
+#pragma unroll
+        for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+      }
+      __syncthreads();
+      gather_frame<NT>(prog, a.prog_len, e, W, G);
+      __syncthreads();
+      row_stage<N, V>(G, twr, fin);
+      __syncthreads();
+      col_stage<N, V>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
     }
-  }
-  if (w == 0 && tid < a.n_types) {
-    if constexpr (MODE == kModePartial) {
-      a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
-    } else if constexpr (MODE == kModeAccum) {
-      a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
+
+    block_sum4<NT>(pw, Atot);
+
+#pragma unroll
+    for (int idx = 0; idx < C::NACC; ++idx) {
+      int r, col;
+      acc_pixel<N, V>(idx, r, col);
+      if (C::CGUARD && col >= C::M) continue;
+      const int q = C::SX * col + w;
+      const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
+      const size_t pix = static_cast<size_t>(pr) * N + pq;
+      if (a.mode == kModePartial) {
+        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = acc[idx];
+      } else if (a.mode == kModeAccum) {
+        a.out[static_cast<size_t>(c) * img_stride + pix] += acc[idx];
+      } else {
+        double v = acc[idx];
+        if (a.subtract)
+          for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
+        a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+      }
+    }
+    if (w == 0 && tid < a.n_types) {
+      if (a.mode == kModePartial) {
+        a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
+      } else if (a.mode == kModeAccum) {
+        a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
+      }
     }
   }
 }
@@ -276,17 +289,17 @@ __global__ __launch_bounds__(256) void self_power_kernel(GridArgs a) {
 // One workgroup per (column class, frame): load and fold the aperture grid,
 // transform, store the complex image field in pixel order.
 template <int N>
-__global__ __launch_bounds__(FT<N>::NT) void fft2_kernel(Fft2Args a) {
-  using C = FT<N>;
+__global__ __launch_bounds__((FT<N, 0>::NT)) void fft2_kernel(Fft2Args a) {
+  using C = FT<N, 0>;
   extern __shared__ float2 lds[];
   float2* G = lds;
   float2* twr = G + C::GRID;
   float2* twc = twr + C::TWR;
   const int w = blockIdx.x % C::SX;
   const int64_t f = blockIdx.x / C::SX;
-  build_twiddles<N>(a.tw, w, twr, twc);
+  build_twiddles<N, 0>(a.tw, w, twr, twc);
   float2 fin[C::PRNZ];
-  fold_factors<N>(a.tw, w, fin);
+  fold_factors<N, 0>(a.tw, w, fin);
   const float2* src = a.Eg + static_cast<size_t>(f) * C::L * C::L;
   for (int cell = threadIdx.x; cell < C::L * C::NZR; cell += C::NT) {
     const int iy = cell / C::NZR, n = cell % C::NZR;
@@ -298,10 +311,10 @@ __global__ __launch_bounds__(FT<N>::NT) void fft2_kernel(Fft2Args a) {
     G[iy * C::P + n] = v;
   }
   __syncthreads();
-  row_stage<N>(G, twr, fin);
+  row_stage<N, 0>(G, twr, fin);
   __syncthreads();
   float2* dst = a.Y + static_cast<size_t>(f) * N * N;
-  col_stage<N>(G, twc, [&](int, int r, int col, float2 v) {
+  col_stage<N, 0>(G, twc, [&](int, int r, int col, float2 v) {
     const int q = C::SX * col + w;
     dst[((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1))] = v;
   });
@@ -343,38 +356,42 @@ __global__ __launch_bounds__(256) void zero_kernel(uint32_t* p, size_t n) {
 // launchers
 // ---------------------------------------------------------------------------
 
-size_t fused_lds_bytes(int N, int n_weights, int n_ant) {
-  const FrameShape S = frame_shape(N);
+size_t fused_lds_bytes(int N, int V, int n_weights, int n_ant) {
+  const FrameShape S = frame_shape(N, V);
   const int M = N / S.SX, L = N / 2;
-  return sizeof(float2) * (static_cast<size_t>(L) * grid_pitch(M) + M + N + n_weights + n_ant + n_ant + 1) +
+  return sizeof(float2) * (static_cast<size_t>(L) * grid_pitch(M) + S.PR * S.QR + S.PC * S.QC + n_weights + n_ant +
+                           n_ant + 1) +
          sizeof(int) * n_ant;
 }
 
 namespace {
 
-template <int N, int MODE, bool CI4>
-hipError_t launch_fused_t(const FusedArgs& a, hipStream_t st) {
-  const FrameShape S = frame_shape(N);
-  const size_t lds = fused_lds_bytes(N, a.n_weights, a.n_ant);
-  auto k = fused_kernel<N, MODE, CI4>;
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k, dim3(S.SX, a.n_chan, a.slices), dim3(S.NT), lds, st, a);
-  return hipGetLastError();
+template <int N, int V, bool CI4>
+const void* fused_symbol() {
+  return reinterpret_cast<const void*>(fused_kernel<N, V, CI4>);
 }
 
-template <int N, int MODE>
-hipError_t launch_fused_m(const FusedArgs& a, bool ci4, hipStream_t st) {
-  return ci4 ? launch_fused_t<N, MODE, true>(a, st) : launch_fused_t<N, MODE, false>(a, st);
+template <int N, int V>
+const void* fused_symbol_v(bool ci4) {
+  if constexpr (frame_shape(N, V).N == N)
+    return ci4 ? fused_symbol<N, V, true>() : fused_symbol<N, V, false>();
+  else
+    return nullptr;
 }
 
-template <int N>
-hipError_t launch_fused_n(const FusedArgs& a, int mode, bool ci4, hipStream_t st) {
-  switch (mode) {
-    case kModePartial: return launch_fused_m<N, kModePartial>(a, ci4, st);
-    case kModeAccum: return launch_fused_m<N, kModeAccum>(a, ci4, st);
-    default: return launch_fused_m<N, kModeFinal>(a, ci4, st);
+const void* fused_kernel_symbol(int N, int V, bool ci4) {
+  auto pick = [&](auto nc) -> const void* {
+    constexpr int NN = decltype(nc)::value;
+    return V == 0 ? fused_symbol_v<NN, 0>(ci4) : V == 1 ? fused_symbol_v<NN, 1>(ci4) : nullptr;
+  };
+  switch (N) {
+    case 8: return pick(std::integral_constant<int, 8>{});
+    case 16: return pick(std::integral_constant<int, 16>{});
+    case 32: return pick(std::integral_constant<int, 32>{});
+    case 64: return pick(std::integral_constant<int, 64>{});
+    case 128: return pick(std::integral_constant<int, 128>{});
+    case 256: return pick(std::integral_constant<int, 256>{});
+    default: return nullptr;
   }
 }
 
@@ -394,16 +411,23 @@ unsigned blocks_for(size_t n) { return static_cast<unsigned>((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_fused(const FusedArgs& a, int N, int mode, bool ci4, hipStream_t st) {
-  switch (N) {
-    case 8: return launch_fused_n<8>(a, mode, ci4, st);
-    case 16: return launch_fused_n<16>(a, mode, ci4, st);
-    case 32: return launch_fused_n<32>(a, mode, ci4, st);
-    case 64: return launch_fused_n<64>(a, mode, ci4, st);
-    case 128: return launch_fused_n<128>(a, mode, ci4, st);
-    case 256: return launch_fused_n<256>(a, mode, ci4, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st) {
+  const void* k = fused_kernel_symbol(N, V, ci4);
+  if (!k) return hipErrorInvalidValue;
+  const FrameShape S = frame_shape(N, V);
+  const size_t lds = fused_lds_bytes(N, V, a.n_weights, a.n_ant);
+  hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (err != hipSuccess) return err;
+  void* args[] = {const_cast<FusedArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(grid), dim3(S.NT), args, lds, st);
+}
+
+int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
+  const void* k = fused_kernel_symbol(N, V, ci4);
+  if (!k) return 0;
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, frame_shape(N, V).NT, lds) != hipSuccess) return 0;
+  return blocks;
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {

@@ -187,101 +187,107 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     P.twiddle[2 * k + 1] = static_cast<float>(w.imag());
   }
 
-  // ---- fused frame transform: folded-grid gather programs, one per column class w
-  P.shape = frame_shape(N);
-  const FrameShape& S = P.shape;
-  if (S.N != N) return fail(why, MOFF_ERR_UNSUPPORTED, "no frame shape for this grid size");
-  P.M = N / S.SX;
-  P.NZR = std::min(L, P.M);
-  P.NJ = std::max(1, L / P.M);
-  P.ZP = grid_pitch(P.M);
-  P.weights.assign(static_cast<size_t>(2) * S.SX * P.NJ * P.n_taps, 0.f);
-  for (int w = 0; w < S.SX; ++w)
-    for (int j = 0; j < P.NJ; ++j) {
-      std::complex<double> rot = unit_root(static_cast<long long>(j) * w, S.SX);
-      for (int t = 0; t < P.n_taps; ++t) {
-        std::complex<double> kv(P.kvals[2 * t], P.kvals[2 * t + 1]);
-        std::complex<double> wv = kv * rot;
-        size_t at = (static_cast<size_t>(w) * P.NJ * P.n_taps + j * P.n_taps + t) * 2;
-        P.weights[at] = static_cast<float>(wv.real());
-        P.weights[at + 1] = static_cast<float>(wv.imag());
-      }
-    }
-
-  // folded cells (iy, n'), n' < NZR, row-major; entries from cells (iy, n' + j M), j ascending,
-  // antenna ascending within a cell.  Every folded cell is written every frame (an empty one by a
-  // single entry that reads the all-zero antenna slot).
-  const int ncell = L * P.NZR;
-  std::vector<int> cost(ncell);
-  int maxc = 0;
-  for (int iy = 0; iy < L; ++iy)
-    for (int n = 0; n < P.NZR; ++n) {
-      int c = 0;
-      for (int j = 0; j < P.NJ; ++j) {
-        int ix = n + j * P.M;
-        if (ix < L) c += P.csr_ptr[iy * L + ix + 1] - P.csr_ptr[iy * L + ix];
-      }
-      maxc = std::max(maxc, c);
-      cost[iy * P.NZR + n] = std::max(1, c);
-    }
-  P.max_cell_entries = maxc;
-  // smallest per-lane load B for which a contiguous greedy split needs <= NT lanes
-  auto lanes_needed = [&](long long B) {
-    int lanes = 1;
-    long long cur = 0;
-    for (int i = 0; i < ncell; ++i) {
-      if (cur + cost[i] > B) {
-        ++lanes;
-        cur = 0;
-      }
-      cur += cost[i];
-    }
-    return lanes;
-  };
-  long long lo = *std::max_element(cost.begin(), cost.end());
-  long long hi = std::accumulate(cost.begin(), cost.end(), 0LL);
-  while (lo < hi) {
-    long long mid = (lo + hi) / 2;
-    if (lanes_needed(mid) <= S.NT) hi = mid;
-    else lo = mid + 1;
-  }
-  const long long B = lo;
-  P.prog_len = static_cast<int>(B);
-  if (P.prog_len > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
-  const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
-  P.prog.assign(static_cast<size_t>(S.SX) * P.prog_len * S.NT, GatherEntry{zero_slot, 0});
-  for (int w = 0; w < S.SX; ++w) {
-    GatherEntry* base = &P.prog[static_cast<size_t>(w) * P.prog_len * S.NT];
-    int lane = 0, k = 0;
-    long long cur = 0;
-    for (int i = 0; i < ncell; ++i) {
-      if (cur + cost[i] > B) {
-        ++lane;
-        k = 0;
-        cur = 0;
-      }
-      cur += cost[i];
-      const int iy = i / P.NZR, n = i % P.NZR;
-      const uint32_t dst = static_cast<uint32_t>(iy * P.ZP + n);
-      int emitted = 0;
-      for (int j = 0; j < P.NJ; ++j) {
-        int ix = n + j * P.M;
-        if (ix >= L) continue;
-        for (int e = P.csr_ptr[iy * L + ix]; e < P.csr_ptr[iy * L + ix + 1]; ++e) {
-          uint32_t wi = static_cast<uint32_t>(j * P.n_taps + P.csr_tap[e]);
-          base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (wi << 12), dst};
-          ++k;
-          ++emitted;
+  // ---- fused frame transform: folded-grid gather programs, per shape variant and column class w
+  for (int v = 0; v < kMaxVariants; ++v) {
+    const FrameShape S = frame_shape(N, v);
+    if (S.N != N) continue;
+    HostPlan::Variant V;
+    V.shape = S;
+    V.n_taps_ = P.n_taps;
+    V.M = N / S.SX;
+    V.NZR = std::min(L, V.M);
+    V.NJ = std::max(1, L / V.M);
+    V.ZP = grid_pitch(V.M);
+    if (V.NJ * P.n_taps >= 2048) return fail(why, MOFF_ERR_UNSUPPORTED, "too many kernel taps for the gather encoding");
+    V.weights.assign(static_cast<size_t>(2) * S.SX * V.NJ * P.n_taps, 0.f);
+    for (int w = 0; w < S.SX; ++w)
+      for (int j = 0; j < V.NJ; ++j) {
+        std::complex<double> rot = unit_root(static_cast<long long>(j) * w, S.SX);
+        for (int t = 0; t < P.n_taps; ++t) {
+          std::complex<double> kv(P.kvals[2 * t], P.kvals[2 * t + 1]);
+          std::complex<double> wv = kv * rot;
+          size_t at = (static_cast<size_t>(w) * V.NJ * P.n_taps + j * P.n_taps + t) * 2;
+          V.weights[at] = static_cast<float>(wv.real());
+          V.weights[at + 1] = static_cast<float>(wv.imag());
         }
       }
-      if (emitted == 0) {
-        base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{zero_slot, dst};
-        ++k;
+
+    // folded cells (iy, n'), n' < NZR, row-major; entries from cells (iy, n' + j M), j ascending,
+    // antenna ascending within a cell.  Every folded cell is written every frame (an empty one by a
+    // single entry that reads the all-zero antenna slot).
+    const int ncell = L * V.NZR;
+    std::vector<int> cost(ncell);
+    int maxc = 0;
+    for (int iy = 0; iy < L; ++iy)
+      for (int n = 0; n < V.NZR; ++n) {
+        int c = 0;
+        for (int j = 0; j < V.NJ; ++j) {
+          int ix = n + j * V.M;
+          if (ix < L) c += P.csr_ptr[iy * L + ix + 1] - P.csr_ptr[iy * L + ix];
+        }
+        maxc = std::max(maxc, c);
+        cost[iy * V.NZR + n] = std::max(1, c);
       }
-      base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
+    P.max_cell_entries = maxc;
+    // smallest per-lane load B for which a contiguous greedy split needs <= NT lanes
+    auto lanes_needed = [&](long long B) {
+      int lanes = 1;
+      long long cur = 0;
+      for (int i = 0; i < ncell; ++i) {
+        if (cur + cost[i] > B) {
+          ++lanes;
+          cur = 0;
+        }
+        cur += cost[i];
+      }
+      return lanes;
+    };
+    long long lo = *std::max_element(cost.begin(), cost.end());
+    long long hi = std::accumulate(cost.begin(), cost.end(), 0LL);
+    while (lo < hi) {
+      long long mid = (lo + hi) / 2;
+      if (lanes_needed(mid) <= S.NT) hi = mid;
+      else lo = mid + 1;
     }
+    const long long B = lo;
+    V.prog_len = static_cast<int>(B);
+    if (V.prog_len > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
+    const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
+    V.prog.assign(static_cast<size_t>(S.SX) * V.prog_len * S.NT, GatherEntry{zero_slot, 0});
+    for (int w = 0; w < S.SX; ++w) {
+      GatherEntry* base = &V.prog[static_cast<size_t>(w) * V.prog_len * S.NT];
+      int lane = 0, k = 0;
+      long long cur = 0;
+      for (int i = 0; i < ncell; ++i) {
+        if (cur + cost[i] > B) {
+          ++lane;
+          k = 0;
+          cur = 0;
+        }
+        cur += cost[i];
+        const int iy = i / V.NZR, n = i % V.NZR;
+        const uint32_t dst = static_cast<uint32_t>(iy * V.ZP + n);
+        int emitted = 0;
+        for (int j = 0; j < V.NJ; ++j) {
+          int ix = n + j * V.M;
+          if (ix >= L) continue;
+          for (int e = P.csr_ptr[iy * L + ix]; e < P.csr_ptr[iy * L + ix + 1]; ++e) {
+            uint32_t wi = static_cast<uint32_t>(j * P.n_taps + P.csr_tap[e]);
+            base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (wi << 12), dst};
+            ++k;
+            ++emitted;
+          }
+        }
+        if (emitted == 0) {
+          base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{zero_slot, dst};
+          ++k;
+        }
+        base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
+      }
+    }
+    P.variants.push_back(std::move(V));
   }
-  if (P.NJ * P.n_taps >= 2048) return fail(why, MOFF_ERR_UNSUPPORTED, "too many kernel taps for the gather encoding");
+  if (P.variants.empty()) return fail(why, MOFF_ERR_UNSUPPORTED, "no frame shape for this grid size");
   return MOFF_OK;
 }
 

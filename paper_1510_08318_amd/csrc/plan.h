@@ -52,12 +52,17 @@ struct HostPlan {
   // twiddles w_N^k = exp(+2 pi i k / N), k < N, float32 (re, im)
   std::vector<float> twiddle;
 
-  // fused frame transform
-  FrameShape shape{};
-  int M = 0, NZR = 0, NJ = 0, ZP = 0;         // ZP: LDS row pitch of the folded grid
-  int prog_len = 0;                          // entries per lane (padded)
-  std::vector<GatherEntry> prog;             // [SX][prog_len][NT]
-  std::vector<float> weights;                // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
+  // fused frame transform, one entry per shape variant (see shape.h)
+  struct Variant {
+    FrameShape shape{};
+    int M = 0, NZR = 0, NJ = 0, ZP = 0;       // ZP: LDS row pitch of the folded grid
+    int prog_len = 0;                        // entries per lane (padded)
+    std::vector<GatherEntry> prog;           // [SX][prog_len][NT]
+    std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
+    int n_weights() const { return NJ * n_taps_; }
+    int n_taps_ = 0;
+  };
+  std::vector<Variant> variants;
   int max_cell_entries = 0;
 };
 

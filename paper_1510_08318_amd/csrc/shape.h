@@ -13,7 +13,7 @@
 namespace moff {
 
 struct FrameShape {
-  int N, NT, SX, PR, QR, PC, QC;
+  int N = 0, NT = 0, SX = 0, PR = 0, QR = 0, PC = 0, QC = 0;
 };
 
 // LDS row pitch of the folded grid (complex elements) for M output columns per
@@ -21,14 +21,18 @@ struct FrameShape {
 // hit 16 different banks.
 constexpr int grid_pitch(int M) { return M + 1; }
 
-constexpr FrameShape frame_shape(int N) {
-  return N == 8   ? FrameShape{8, 64, 1, 4, 2, 4, 2}
-       : N == 16  ? FrameShape{16, 64, 1, 4, 4, 4, 4}
-       : N == 32  ? FrameShape{32, 64, 1, 8, 4, 8, 4}
-       : N == 64  ? FrameShape{64, 128, 1, 8, 8, 8, 8}
-       : N == 128 ? FrameShape{128, 256, 2, 8, 8, 16, 8}
-       : N == 256 ? FrameShape{256, 256, 4, 8, 8, 16, 16}
-                  : FrameShape{0, 0, 0, 0, 0, 0, 0};
+// Shape variants of the frame transform; the autotuner picks one per plan.
+// Fields: {N, NT, SX, PR, QR, PC, QC}.  A variant with N == 0 does not exist.
+constexpr int kMaxVariants = 2;
+
+constexpr FrameShape frame_shape(int N, int V = 0) {
+  return N == 8   ? (V == 0 ? FrameShape{8, 64, 1, 4, 2, 4, 2} : FrameShape{})
+       : N == 16  ? (V == 0 ? FrameShape{16, 64, 1, 4, 4, 4, 4} : FrameShape{})
+       : N == 32  ? (V == 0 ? FrameShape{32, 64, 1, 8, 4, 8, 4} : FrameShape{})
+       : N == 64  ? (V == 0 ? FrameShape{64, 128, 1, 8, 8, 8, 8} : FrameShape{})
+       : N == 128 ? (V == 0 ? FrameShape{128, 256, 2, 8, 8, 16, 8} : FrameShape{128, 256, 1, 16, 8, 16, 8})
+       : N == 256 ? (V == 0 ? FrameShape{256, 256, 4, 8, 8, 16, 16} : FrameShape{256, 512, 2, 16, 8, 16, 16})
+                  : FrameShape{};
 }
 
 }  // namespace moff

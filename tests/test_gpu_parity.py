@@ -211,3 +211,52 @@ def test_full_config2_sampled_channels(torch, moff):
     chans = [0, 77, 127]
     ref, pbar = oracle_channels(w, chans)
     assert_image_close(got[chans], ref, pbar, label="config2 full")
+
+
+@pytest.mark.parametrize("case", ["config2_sub", "config3_sub", "config5_sub", "hetero_n128_4types", "config1"])
+def test_every_variant_and_slicing(torch, moff, case):
+    """Every shape variant of the frame transform and several time slicings agree
+    with the oracle (the autotuner may pick any of them)."""
+    w = CASES[case]()
+    ref, pbar = oracle_channels(w, range(w.geom.n_chan))
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        g = to_dev(torch, w.gains) if w.gains is not None else None
+        nvar = p.config(w.E.shape[0])["n_variants"]
+        for v in range(nvar):
+            for sl in (1, 2, 3):
+                p.set_config(variant=v, slices=sl)
+                cfg = p.config(w.E.shape[0])
+                assert cfg["variant"] == v and cfg["slices"] == min(sl, w.E.shape[0])
+                got = p.image(E, g)
+                torch.cuda.synchronize()
+                assert_image_close(got.cpu().numpy(), ref, pbar, label=f"{case} v{v} s{sl}")
+
+
+def test_autotune_and_graph_replay(torch, moff):
+    """The autotuned configuration is correct, and the fused call captured in a
+    HIP graph reproduces the eager result on every replay."""
+    w = synth.make_config(2, n_time=20, n_chan=6)
+    ref, pbar = oracle_channels(w, range(6))
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        cfg = p.autotune(E)
+        assert cfg["tuned"] == 1
+        out = torch.empty((6, 128, 128), dtype=torch.float32, device="cuda:0")
+        p.image(E, out=out)                     # allocates the workspace before capture
+        torch.cuda.synchronize()
+        eager = out.clone()
+        assert_image_close(eager.cpu().numpy(), ref, pbar, label="autotuned")
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                p.image(E, out=out, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        for rep in range(3):
+            out.fill_(-1.0)                     # eager work between replays
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"replay {rep} differs"
