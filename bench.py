@@ -159,10 +159,10 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded LWA-shaped sky + noise, 4+4-bit quantised)",
-        "config": {"workload": "LWA-shaped MOFF imaging: 256 antennas in a 100 m disc, 3x3 dipole kernel, "
-                               "128 channels 40-80 MHz, 1000 time samples, 128x128 grid, complex 4+4-bit input",
-                   "n_ant": Na, "n_chan": C, "n_time": T, "grid": N, "input": "ci4",
+        "data": "synthetic (seeded point-source sky + Gaussian noise" + (", 4+4-bit quantised)" if (w.geom.flags & synth.IN_CI4) else ")"),
+        "config": {"workload": synth.CONFIG_NAMES[args.config],
+                   "n_ant": Na, "n_chan": C, "n_time": T, "grid": N,
+                   "input": "ci4" if (w.geom.flags & synth.IN_CI4) else "c64",
                    "launch": {k: launch[k] for k in ("variant", "slices", "grid", "threads", "tuned")}},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},

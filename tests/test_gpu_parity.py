@@ -260,3 +260,20 @@ def test_autotune_and_graph_replay(torch, moff):
             graph.replay()
             torch.cuda.synchronize()
             assert torch.equal(out, eager), f"replay {rep} differs"
+
+
+@pytest.mark.parametrize("cfg,chans", [(3, [0, 511, 1023]), (5, [0, 255])])
+def test_full_size_sampled_channels(torch, moff, cfg, chans):
+    """HERA-shaped and calibration workloads at full size (every channel imaged in
+    one launch, autotuned), checked on channels the oracle computes one by one."""
+    w = synth.make_config(cfg)
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        g = to_dev(torch, w.gains) if w.gains is not None else None
+        p.autotune(E, g)
+        got = p.image(E, g)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+    assert np.isfinite(got).all()
+    ref, pbar = oracle_channels(w, chans)
+    assert_image_close(got[chans], ref, pbar, label=f"config{cfg} full")
