@@ -268,6 +268,28 @@ moff_status moff_detect_accumulate(moff_plan plan, const float* y_dev, int64_t n
 moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
                               const float* gains_dev, float* image_dev, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Gain gradient (calibration feedback, Sec. 3 "Calibration"; the image is
+ * differentiable in the complex gains applied before gridding).
+ * ------------------------------------------------------------------------- */
+
+/*
+ * Vector-Jacobian product of moff_image with respect to the gains:
+ *   dL_dimage_dev : float32 [n_chan][N][N], R = dL/dI for a real loss L
+ *   dL_dgains_dev : complex64 [n_chan][n_ant], overwritten with
+ *                   dL/dRe(g) + i dL/dIm(g) = 2 dL/d(conj g)   (torch's convention)
+ * E_dev, n_time, gains_dev (NULL = unit gains) as for moff_image.  With
+ * e = g E and Y_t the image field of sample t,
+ *   grad_a = (2 s / T) sum_t conj(E_ta) [ sum_{taps} conj(K_a) Z_t - e_ta rho_p(a) ],
+ *   Z_t = adjoint 2-D DFT of R * Y_t on the aperture cells,  rho_p = sum_pix R P_p,
+ * s the pair normalisation (1 unless MOFF_NORM_PAIRS), the rho term absent under
+ * MOFF_AUTOCORR_NONE.  Every frame's grid and field are recomputed in time
+ * chunks through the plan workspace (never stored for the whole integration);
+ * the sums over time are float64.
+ */
+moff_status moff_gain_vjp(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
+                          const float* dL_dimage_dev, float* dL_dgains_dev, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

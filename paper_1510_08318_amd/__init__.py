@@ -17,7 +17,7 @@ from ._lib import (MOFF_AUTOCORR_NONE, MOFF_IN_C64, MOFF_IN_CI4, MOFF_NORM_PAIRS
                    MoffError, moff_geometry)
 
 __all__ = ["Plan", "MoffError", "MOFF_IN_C64", "MOFF_IN_CI4", "MOFF_AUTOCORR_NONE", "MOFF_NORM_PAIRS",
-           "library_path"]
+           "library_path", "moff_image_autograd"]
 
 
 def library_path():
@@ -259,3 +259,52 @@ class Plan:
         po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
         _lib.moff_image_staged(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
         return out
+
+    def gain_vjp(self, E, gains, dL_dimage, out=None, stream=None):
+        """dL/dRe(g) + i dL/dIm(g) (complex64 [n_chan, n_ant]) for R = dL/dI."""
+        torch = self._torch()
+        pE, T = self._E(E)
+        pR = self._dev(dL_dimage, "dL_dimage", (self.n_chan, self.N, self.N), torch.float32)
+        if out is None:
+            out = self._new((self.n_chan, self.n_ant), torch.complex64)
+        po = self._dev(out, "out", (self.n_chan, self.n_ant), torch.complex64)
+        _lib.moff_gain_vjp(self.handle, pE, T, self._gains(gains), pR, po, self._stream(stream))
+        return out
+
+
+def _make_autograd():
+    import torch
+
+    class MoffImage(torch.autograd.Function):
+        """Differentiable MOFF image: I = MoffImage.apply(plan, E, gains).
+
+        Forward runs the fused imaging kernel; backward runs the gain adjoint
+        (moff_gain_vjp) and returns dL/dgains in torch's complex convention.  E is
+        not differentiated (raw antenna samples)."""
+
+        @staticmethod
+        def forward(ctx, plan, E, gains):
+            ctx.plan = plan
+            ctx.save_for_backward(E, gains)
+            return plan.image(E, gains.detach().contiguous())
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            E, gains = ctx.saved_tensors
+            g = None
+            if ctx.needs_input_grad[2]:
+                g = ctx.plan.gain_vjp(E, gains.detach().contiguous(), grad_out.contiguous().float())
+            return None, None, g
+
+    return MoffImage
+
+
+_autograd_cls = None
+
+
+def moff_image_autograd(plan, E, gains):
+    """I = MOFF image of E with gains `gains` (a complex64 tensor that may require grad)."""
+    global _autograd_cls
+    if _autograd_cls is None:
+        _autograd_cls = _make_autograd()
+    return _autograd_cls.apply(plan, E, gains)

@@ -28,6 +28,9 @@ struct moff_plan_s {
   int* d_csr_ptr = nullptr;
   int* d_csr_ant = nullptr;
   int* d_csr_tap = nullptr;
+  int* d_ant_cells = nullptr;   // [n_ant][2] (ix0, iy0)
+  int* d_ktype_k = nullptr;
+  int* d_ktype_off = nullptr;
   // workspace, grown on demand
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -70,7 +73,8 @@ moff_status upload(T** dst, const void* src, size_t bytes) {
 }
 
 void free_device(moff_plan p) {
-  void* ptrs[] = {p->d_tw, p->d_Pp, p->d_ant_type, p->d_ktab, p->d_csr_ptr, p->d_csr_ant, p->d_csr_tap, p->d_ws};
+  void* ptrs[] = {p->d_tw,      p->d_Pp,      p->d_ant_type,  p->d_ktab,      p->d_csr_ptr, p->d_csr_ant,
+                  p->d_csr_tap, p->d_ant_cells, p->d_ktype_k, p->d_ktype_off, p->d_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
@@ -295,6 +299,16 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
     up(upload(&p->d_csr_ptr, hp.csr_ptr.data(), sizeof(int) * hp.csr_ptr.size()));
     up(upload(&p->d_csr_ant, hp.csr_ant.data(), sizeof(int) * hp.csr_ant.size()));
     up(upload(&p->d_csr_tap, hp.csr_tap.data(), sizeof(int) * hp.csr_tap.size()));
+    {
+      std::vector<int> cells(2 * hp.n_ant);
+      for (int a = 0; a < hp.n_ant; ++a) {
+        cells[2 * a] = hp.ix0[a];
+        cells[2 * a + 1] = hp.iy0[a];
+      }
+      up(upload(&p->d_ant_cells, cells.data(), sizeof(int) * cells.size()));
+      up(upload(&p->d_ktype_k, hp.ktype_k.data(), sizeof(int) * hp.ktype_k.size()));
+      up(upload(&p->d_ktype_off, hp.ktype_off.data(), sizeof(int) * hp.ktype_off.size()));
+    }
     if (s != MOFF_OK) {
       free_device(p);
       delete p;
@@ -622,6 +636,90 @@ moff_status moff_image_staged(moff_plan p, const void* E, int64_t n_time, const 
   fa.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
   fa.scale = image_scale(hp, n_time);
   return hip_status(moff::launch_finalize(fa, st));
+}
+
+moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* gains, const float* dL_dimage,
+                          float* dL_dgains, void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !dL_dimage || !dL_dgains || !aligned16(dL_dimage) || !aligned16(dL_dgains) ||
+      (gains && !aligned16(gains)))
+    return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const HostPlan& hp = p->hp;
+  const HostPlan::Variant& V = hp.variants[0];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
+  const size_t L2 = static_cast<size_t>(hp.L) * hp.L;
+  const size_t gp_frame = static_cast<size_t>(V.shape.SX) * hp.L * V.NZR;
+  const size_t d_bytes = sizeof(double) * 2 * hp.n_chan * hp.n_ant;
+  const size_t q_bytes = sizeof(double) * hp.n_chan * hp.n_ant;
+  // time chunk: the per-chunk grids, fields and adjoint grids within ~2 GiB
+  const size_t per_t = sizeof(float2) * (L2 + npix + gp_frame) * hp.n_chan;
+  int64_t chunk = std::max<int64_t>(1, static_cast<int64_t>((size_t(2) << 30) / per_t));
+  chunk = std::min(chunk, n_time);
+  const size_t eg_bytes = sizeof(float2) * L2 * hp.n_chan * chunk;
+  const size_t y_bytes = sizeof(float2) * npix * hp.n_chan * chunk;
+  const size_t gp_bytes = sizeof(float2) * gp_frame * hp.n_chan * chunk;
+  s = ensure_workspace(p, d_bytes + q_bytes + eg_bytes + y_bytes + gp_bytes);
+  if (s != MOFF_OK) return s;
+  char* ws = static_cast<char*>(p->d_ws);
+  double2* D = reinterpret_cast<double2*>(ws);
+  double* Q = reinterpret_cast<double*>(ws + d_bytes);
+  float2* Eg = reinterpret_cast<float2*>(ws + d_bytes + q_bytes);
+  float2* Y = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes);
+  float2* Gp = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes + y_bytes);
+  if (moff::launch_zero(ws, d_bytes + q_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
+  const size_t sample_bytes = ci4 ? 1 : sizeof(float2);
+  for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
+    const int64_t nt = std::min(chunk, n_time - t0);
+    const void* Ec = static_cast<const char*>(E) + static_cast<size_t>(t0) * hp.n_chan * hp.n_ant * sample_bytes;
+    moff::GridArgs g = grid_args(p, Ec, nt, gains);
+    g.Eg = Eg;
+    hipError_t e = moff::launch_grid(g, ci4, st);
+    moff::Fft2Args f{Eg, Y, p->d_tw};
+    if (e == hipSuccess) e = moff::launch_fft2(f, hp.N, nt * hp.n_chan, st);
+    moff::AdjFftArgs af{Y, dL_dimage, Gp, p->d_tw, hp.n_chan};
+    if (e == hipSuccess) e = moff::launch_adjoint_fft2(af, hp.N, nt * hp.n_chan, st);
+    moff::DegridArgs dg{};
+    dg.E = Ec;
+    dg.Gp = Gp;
+    dg.weights = p->d_weights[0];
+    dg.ant_type = p->d_ant_type;
+    dg.ant_cells = p->d_ant_cells;
+    dg.ktype_k = p->d_ktype_k;
+    dg.ktype_off = p->d_ktype_off;
+    dg.D = D;
+    dg.Q = Q;
+    dg.n_ant = hp.n_ant;
+    dg.n_chan = hp.n_chan;
+    dg.n_taps = hp.n_taps;
+    dg.SX = V.shape.SX;
+    dg.L = hp.L;
+    dg.M = V.M;
+    dg.NZR = V.NZR;
+    dg.NJ = V.NJ;
+    dg.n_time = nt;
+    if (e == hipSuccess) e = moff::launch_degrid(dg, ci4, st);
+    if (e != hipSuccess) return MOFF_ERR_HIP;
+  }
+  moff::GradFinalArgs gf{};
+  gf.D = D;
+  gf.Q = Q;
+  gf.R = dL_dimage;
+  gf.Pp = p->d_Pp;
+  gf.gains = reinterpret_cast<const float2*>(gains);
+  gf.ant_type = p->d_ant_type;
+  gf.grad = reinterpret_cast<float2*>(dL_dgains);
+  gf.N = hp.N;
+  gf.n_ant = hp.n_ant;
+  gf.n_chan = hp.n_chan;
+  gf.n_types = hp.n_ktypes;
+  gf.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  gf.scale = 2.0 * image_scale(hp, n_time);
+  return hip_status(moff::launch_grad_final(gf, st));
 }
 
 }  // extern "C"

@@ -18,6 +18,10 @@ __device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2
 __device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
+// a * conj(b)
+__device__ __forceinline__ float2 c_mul_conj(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
 __device__ __forceinline__ float2 c_mul_i(float2 a) { return make_float2(-a.y, a.x); }
 __device__ __forceinline__ float2 c_mul_mi(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 c_neg(float2 a) { return make_float2(-a.x, -a.y); }
@@ -135,6 +139,17 @@ __device__ __forceinline__ void dft_pruned(float2* x) {
       x[2 * k + 1] = o[k];
     }
   }
+}
+
+// Inverse-direction R-point DFT, X[k] = sum_n x[n] exp(-2 pi i n k / R), through
+// conjugation: conj(DFT(conj(x))).
+template <int R>
+__device__ __forceinline__ void idft(float2* x) {
+#pragma unroll
+  for (int i = 0; i < R; ++i) x[i].y = -x[i].y;
+  Dft<R>::run(x);
+#pragma unroll
+  for (int i = 0; i < R; ++i) x[i].y = -x[i].y;
 }
 
 }  // namespace moff

@@ -226,4 +226,119 @@ __device__ __forceinline__ void acc_pixel(int idx, int& r, int& col) {
   r = 2 * j + s + C::PC * q2;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint (transpose) of the frame transform, for gradients.  With F the
+// forward map from the folded grid G[iy][n'] (n' < NZR) to the workgroup's
+// output pixels Y[r][m], these compute F^H: exponents are negated, twiddles
+// conjugated, and the zero-input half of each forward DFT becomes an
+// output-pruned inverse DFT.
+// ---------------------------------------------------------------------------
+
+// Column stage adjoint: from values src(acc_index, r, m) at this lane's pixels
+// (the pixels col_stage hands to its sink) to Z'[iy][m] = sum_r Y'[r][m] w_N^{-iy r}
+// for iy < L, written in place into G.
+template <int N, int V, class Source>
+__device__ __forceinline__ void col_stage_adjoint(float2* G, const float2* twc, Source&& src) {
+  using C = FT<N, V>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / C::CPW;
+#pragma unroll
+  for (int cs = 0; cs < C::CSTEPS; ++cs) {
+    const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
+    if (C::CGUARD && col >= C::M) continue;
+    float2* Zc = G + col + sub * C::P;            // row `sub` of this column
+    float2* Zb = G + col + sub * C::QC * C::P;    // row (sub QC) of this column
+    float2 xacc[C::JA][C::PH];
+#pragma unroll
+    for (int ja = 0; ja < C::JA; ++ja)
+#pragma unroll
+      for (int n1 = 0; n1 < C::PH; ++n1) xacc[ja][n1] = make_float2(0.f, 0.f);
+    static_for<0, 2>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      // pass B^H (job j): inverse radix-QC over q2, conjugate twiddles, rows j QC + n2
+#pragma unroll
+      for (int jb = 0; jb < C::JB; ++jb) {
+        const int j = sub + C::LPC * jb;
+        const int q1 = 2 * j + s;
+        float2 v[C::QC];
+#pragma unroll
+        for (int q2 = 0; q2 < C::QC; ++q2)
+          v[q2] = src(((cs * 2 + s) * C::JB + jb) * C::QC + q2, q1 + C::PC * q2, col);
+        idft<C::QC>(v);
+#pragma unroll
+        for (int n2 = 0; n2 < C::QC; ++n2) {
+          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twc[q1 * C::QC + n2]);
+          Zb[(C::LPC * jb * C::QC + n2) * C::P] = v[n2];
+        }
+      }
+      wave_sync();
+      // pass A^H (job n2), half-round s: inverse radix-PH over j, times w_PC^{-n1 s}
+#pragma unroll
+      for (int ja = 0; ja < C::JA; ++ja) {
+        float2 u[C::PH];
+#pragma unroll
+        for (int j = 0; j < C::PH; ++j) u[j] = Zc[(C::LPC * ja + j * C::QC) * C::P];
+        idft<C::PH>(u);
+        static_for<0, C::PH>([&](auto nc) {
+          constexpr int n1 = decltype(nc)::value;
+          const float2 t = (s == 0) ? u[n1] : rot<C::PC, -n1>(u[n1]);
+          xacc[ja][n1] = c_add(xacc[ja][n1], t);
+        });
+      }
+      wave_sync();
+    });
+#pragma unroll
+    for (int ja = 0; ja < C::JA; ++ja)
+#pragma unroll
+      for (int n1 = 0; n1 < C::PH; ++n1) Zc[(C::LPC * ja + C::QC * n1) * C::P] = xacc[ja][n1];
+    wave_sync();
+  }
+}
+
+// Row stage adjoint: G'[iy][n'] = conj(w_N^{n' w}) sum_m Z'[iy][m] w_M^{-n' m}
+// for n' < NZR, in place.
+template <int N, int V>
+__device__ __forceinline__ void row_stage_adjoint(float2* G, const float2* twr, const float2 (&fin)[FT<N, V>::PRNZ]) {
+  using C = FT<N, V>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / C::RPW;
+#pragma unroll
+  for (int rs = 0; rs < C::RSTEPS; ++rs) {
+    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    if (C::RGUARD && row >= C::L) continue;
+    float2* R = G + row * C::P;
+    float2 y[C::JBR][C::QR];
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb)
+#pragma unroll
+      for (int q2 = 0; q2 < C::QR; ++q2) y[jb][q2] = R[sub + C::LPR * jb + C::PR * q2];
+    wave_sync();
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb) {
+      const int q1 = sub + C::LPR * jb;
+      idft<C::QR>(y[jb]);
+#pragma unroll
+      for (int n2 = 0; n2 < C::QR; ++n2) {
+        if (C::SX > 1 || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twr[q1 * C::QR + n2]);
+        R[q1 * C::QR + n2] = y[jb][n2];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja) {
+      float2 x[C::PR];
+#pragma unroll
+      for (int q1 = 0; q1 < C::PR; ++q1) x[q1] = R[sub + C::LPR * ja + q1 * C::QR];
+      idft<C::PR>(x);
+#pragma unroll
+      for (int n1 = 0; n1 < C::PRNZ; ++n1) {
+        float2 o = x[n1];
+        if constexpr (C::SX > 1) o = c_mul_conj(o, fin[n1]);
+        R[sub + C::LPR * ja + C::QR * n1] = o;
+      }
+    }
+    wave_sync();
+  }
+}
+
 }  // namespace moff

@@ -81,6 +81,45 @@ struct FinalizeArgs {
 
 // Fused kernel of grid size N, shape variant V (shape.h), `grid` workgroups
 // (each loops over the SX * n_chan * slices work items with stride `grid`).
+// Gain-gradient (adjoint) kernels.
+struct AdjFftArgs {
+  const float2* Y;             // [F][N][N] image fields of a time chunk, frame f = t * n_chan + c
+  const float* R;              // [C][N][N] dL/dI
+  float2* Gp;                  // [F][SX][L][NZR] folded adjoint grids
+  const float2* tw;            // [N]
+  int n_chan;
+};
+
+struct DegridArgs {
+  const void* E;               // [T_chunk][C][n_ant] raw samples of the chunk
+  const float2* Gp;            // [T_chunk * C][SX][L][NZR]
+  const float2* weights;       // [SX][NJ * n_taps] (variant 0)
+  const int* ant_type;
+  const int* ant_cells;        // [n_ant][2] = (ix0, iy0)
+  const int* ktype_k;          // [types]
+  const int* ktype_off;        // [types] first tap of each type
+  double2* D;                  // [C][n_ant] += sum_t conj(E) d
+  double* Q;                   // [C][n_ant] += sum_t |E|^2
+  int n_ant, n_chan, n_taps, SX, L, M, NZR, NJ;
+  int64_t n_time;
+};
+
+struct GradFinalArgs {
+  const double2* D;
+  const double* Q;
+  const float* R;              // [C][N][N]
+  const double* Pp;            // [types][N][N]
+  const float2* gains;         // [C][n_ant] or nullptr
+  const int* ant_type;
+  float2* grad;                // [C][n_ant]
+  int N, n_ant, n_chan, n_types, subtract;
+  double scale;                // 2 s / T
+};
+
+hipError_t launch_adjoint_fft2(const AdjFftArgs& a, int N, int64_t n_frames, hipStream_t st);
+hipError_t launch_degrid(const DegridArgs& a, bool ci4, hipStream_t st);
+hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
+
 size_t fused_lds_bytes(int N, int V, int n_weights, int n_ant);
 hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st);
 int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds);

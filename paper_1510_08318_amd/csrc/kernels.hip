@@ -346,6 +346,114 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinalizeArgs a) {
   a.out[i] = static_cast<float>(v * a.scale);
 }
 
+// ---------------------------------------------------------------------------
+// gain gradient (adjoint of the path)
+// ---------------------------------------------------------------------------
+
+// One workgroup per (column class, frame): Y' = R * Y on the class's pixels,
+// adjoint column and row passes, store the folded adjoint grid.
+template <int N>
+__global__ __launch_bounds__((FT<N, 0>::NT)) void adjoint_fft2_kernel(AdjFftArgs a) {
+  using C = FT<N, 0>;
+  extern __shared__ float2 lds[];
+  float2* G = lds;
+  float2* twr = G + C::GRID;
+  float2* twc = twr + C::TWR;
+  const int w = blockIdx.x % C::SX;
+  const int64_t f = blockIdx.x / C::SX;
+  const int c = static_cast<int>(f % a.n_chan);
+  build_twiddles<N, 0>(a.tw, w, twr, twc);
+  float2 fin[C::PRNZ];
+  fold_factors<N, 0>(a.tw, w, fin);
+  __syncthreads();
+  const float2* Y = a.Y + static_cast<size_t>(f) * N * N;
+  const float* R = a.R + static_cast<size_t>(c) * N * N;
+  col_stage_adjoint<N, 0>(G, twc, [&](int, int r, int col) -> float2 {
+    const int q = C::SX * col + w;
+    const size_t pix = static_cast<size_t>((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1));
+    const float2 y = Y[pix];
+    const float rr = R[pix];
+    return make_float2(y.x * rr, y.y * rr);
+  });
+  __syncthreads();
+  row_stage_adjoint<N, 0>(G, twr, fin);
+  __syncthreads();
+  float2* out = a.Gp + (static_cast<size_t>(f) * C::SX + w) * C::L * C::NZR;
+  for (int cell = threadIdx.x; cell < C::L * C::NZR; cell += C::NT) {
+    const int iy = cell / C::NZR, n = cell % C::NZR;
+    out[cell] = G[iy * C::P + n];
+  }
+}
+
+// One thread per (channel, antenna): d_t = sum over footprint taps and column
+// classes of conj(weight) * G'_t, then D += conj(E_t) d_t and Q += |E_t|^2 in
+// float64 over the chunk's time samples.
+template <bool CI4>
+__global__ __launch_bounds__(256) void degrid_kernel(DegridArgs a) {
+  const int c = blockIdx.y;
+  const int ant = blockIdx.x * 256 + threadIdx.x;
+  if (ant >= a.n_ant) return;
+  const int p = a.ant_type[ant];
+  const int k = a.ktype_k[p], off = a.ktype_off[p];
+  const int ix0 = a.ant_cells[2 * ant], iy0 = a.ant_cells[2 * ant + 1];
+  const int nw = a.NJ * a.n_taps;
+  double Dx = 0.0, Dy = 0.0, Q = 0.0;
+  for (int64_t t = 0; t < a.n_time; ++t) {
+    const int64_t f = t * a.n_chan + c;
+    float dx = 0.f, dy = 0.f;
+    for (int w = 0; w < a.SX; ++w) {
+      const float2* Gw = a.Gp + (static_cast<size_t>(f) * a.SX + w) * a.L * a.NZR;
+      const float2* Ww = a.weights + static_cast<size_t>(w) * nw;
+      for (int u = 0; u < k; ++u) {
+        const float2* Grow = Gw + static_cast<size_t>(iy0 + u) * a.NZR;
+        for (int v = 0; v < k; ++v) {
+          const int ix = ix0 + v;
+          const int j = ix / a.M, n = ix - j * a.M;
+          const float2 g = Grow[n];
+          const float2 wt = Ww[j * a.n_taps + off + u * k + v];
+          dx = fmaf(g.x, wt.x, fmaf(g.y, wt.y, dx));     // g * conj(wt)
+          dy = fmaf(g.y, wt.x, fmaf(-g.x, wt.y, dy));
+        }
+      }
+    }
+    const float2 e = load_sample(a.E, (static_cast<size_t>(t) * a.n_chan + c) * a.n_ant + ant, CI4);
+    Dx += static_cast<double>(e.x) * dx + static_cast<double>(e.y) * dy;   // conj(e) * d
+    Dy += static_cast<double>(e.x) * dy - static_cast<double>(e.y) * dx;
+    Q += static_cast<double>(e.x) * e.x + static_cast<double>(e.y) * e.y;
+  }
+  const size_t i = static_cast<size_t>(c) * a.n_ant + ant;
+  a.D[i] = make_double2(a.D[i].x + Dx, a.D[i].y + Dy);
+  a.Q[i] += Q;
+}
+
+// One workgroup per channel: rho_p = sum_pix R P_p, then
+// grad = scale (D - rho_{p(a)} g Q).
+__global__ __launch_bounds__(256) void grad_final_kernel(GradFinalArgs a) {
+  __shared__ double rho[kMaxTypesDev];
+  const int c = blockIdx.x;
+  const size_t npix = static_cast<size_t>(a.N) * a.N;
+  double part[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  if (a.subtract) {
+    const float* R = a.R + static_cast<size_t>(c) * npix;
+    for (size_t i = threadIdx.x; i < npix; i += 256) {
+      const double r = R[i];
+      for (int p = 0; p < a.n_types; ++p) part[p] += r * a.Pp[p * npix + i];
+    }
+  }
+  block_sum4<256>(part, rho);
+  for (int ant = threadIdx.x; ant < a.n_ant; ant += 256) {
+    const size_t i = static_cast<size_t>(c) * a.n_ant + ant;
+    double gx = a.D[i].x, gy = a.D[i].y;
+    if (a.subtract) {
+      const float2 g = a.gains ? a.gains[i] : make_float2(1.f, 0.f);
+      const double s = rho[a.ant_type[ant]] * a.Q[i];
+      gx -= s * g.x;
+      gy -= s * g.y;
+    }
+    a.grad[i] = make_float2(static_cast<float>(gx * a.scale), static_cast<float>(gy * a.scale));
+  }
+}
+
 // Fill with zeros (a kernel rather than a memset node, so captured graphs replay it safely).
 __global__ __launch_bounds__(256) void zero_kernel(uint32_t* p, size_t n) {
   for (size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x; i < n; i += static_cast<size_t>(gridDim.x) * 256)
@@ -479,6 +587,43 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   const size_t n = bytes / 4;
   const unsigned blocks = static_cast<unsigned>(std::min<size_t>((n + 255) / 256, 65536));
   hipLaunchKernelGGL(zero_kernel, dim3(blocks ? blocks : 1), dim3(256), 0, st, static_cast<uint32_t*>(p), n);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_fft2(const AdjFftArgs& a, int N, int64_t n_frames, hipStream_t st) {
+  auto go = [&](auto nc) -> hipError_t {
+    constexpr int NN = decltype(nc)::value;
+    using C = FT<NN, 0>;
+    const size_t lds = sizeof(float2) * (static_cast<size_t>(C::GRID) + C::TWR + C::TWC);
+    auto k = adjoint_fft2_kernel<NN>;
+    hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(n_frames * C::SX)), dim3(C::NT), lds, st, a);
+    return hipGetLastError();
+  };
+  switch (N) {
+    case 8: return go(std::integral_constant<int, 8>{});
+    case 16: return go(std::integral_constant<int, 16>{});
+    case 32: return go(std::integral_constant<int, 32>{});
+    case 64: return go(std::integral_constant<int, 64>{});
+    case 128: return go(std::integral_constant<int, 128>{});
+    case 256: return go(std::integral_constant<int, 256>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_degrid(const DegridArgs& a, bool ci4, hipStream_t st) {
+  const dim3 grid(static_cast<unsigned>((a.n_ant + 255) / 256), static_cast<unsigned>(a.n_chan));
+  if (ci4)
+    hipLaunchKernelGGL(degrid_kernel<true>, grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL(degrid_kernel<false>, grid, dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(grad_final_kernel, dim3(a.n_chan), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

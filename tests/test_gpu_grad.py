@@ -1,0 +1,141 @@
+"""GPU gain gradient (adjoint of the MOFF path) against the FP64 oracle gradient
+and against finite differences of the FP64 oracle's forward image.
+
+Tolerance: the GPU path computes the transforms in float32 and the sums over
+time in float64; errors are measured relative to the largest gradient entry of
+the channel, bound 1e-4 (the finite-difference bound asked of the adjoint).
+"""
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.skip("no GPU")
+    return _t
+
+
+@pytest.fixture(scope="module")
+def moff():
+    import paper_1510_08318_amd as m
+    m._lib.lib()
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_grad(torch, moff, w, R):
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        g = p.gain_vjp(dev(torch, w.E), dev(torch, w.gains), dev(torch, R.astype(np.float32)))
+        torch.cuda.synchronize()
+        return g.cpu().numpy().astype(np.complex128)
+
+
+def rel_err(got, ref):
+    return max(np.abs(got[c] - ref[c]).max() / np.abs(ref[c]).max() for c in range(ref.shape[0]))
+
+
+def small(seed, N, n_ant, kernels, C=2, T=3, flags=0, fmt=synth.IN_C64, extent=3.0, cell=1.0):
+    w = synth.random_case(seed, n_ant, N, C, T, kernels, fmt=fmt, extent_m=extent, cell_m=cell)
+    w.geom.flags |= flags
+    return w
+
+
+CASES = {
+    "n8": lambda r: small(1, 8, 4, [synth.random_kernel(r, 2)], extent=1.5),
+    "n16_hetero": lambda r: small(2, 16, 7, [synth.random_kernel(r, 2), synth.random_kernel(r, 3)]),
+    "n32_ci4": lambda r: small(3, 32, 12, [synth.random_kernel(r, 3)], fmt=synth.IN_CI4, extent=10.0),
+    "n64_pairs": lambda r: small(4, 64, 20, [synth.random_kernel(r, 3)], flags=synth.NORM_PAIRS, extent=30.0),
+    "n128_autos": lambda r: small(5, 128, 30, [synth.random_kernel(r, 3), synth.random_kernel(r, 5)],
+                                  flags=synth.AUTOCORR_NONE, extent=80.0, cell=1.5),
+    "config5_sub": lambda r: synth.make_config(5, n_time=3, n_chan=2),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_gradient_vs_oracle(torch, moff, case):
+    rng = np.random.default_rng(zlib.crc32(case.encode()))
+    w = CASES[case](np.random.default_rng(7))
+    if w.gains is None:
+        w.gains = synth.random_gains(rng, w.geom.n_chan, w.geom.n_ant)
+    C, N = w.geom.n_chan, w.geom.grid_n
+    R = rng.standard_normal((C, N, N)).astype(np.float32)
+    ref = oracle.gain_gradient(w.geom, w.E, w.gains, R.astype(np.float64))
+    got = gpu_grad(torch, moff, w, R)
+    err = rel_err(got, ref)
+    assert err <= TOL, f"{case}: {err:.3g}"
+
+
+def test_gradient_vs_finite_differences(torch, moff):
+    """The GPU adjoint of L(g) = sum (I - M)^2 against central differences of the
+    oracle's float64 forward image (an implementation independent of both
+    gradient codes)."""
+    rng = np.random.default_rng(11)
+    w = small(8, 32, 10, [synth.random_kernel(rng, 3), synth.random_kernel(rng, 2)], extent=8.0)
+    model = rng.standard_normal((2, 32, 32)) * 3.0
+    g0 = w.gains.astype(np.complex128)
+    L0, R = oracle.image_loss(w.geom, w.E, g0, model)
+    got = gpu_grad(torch, moff, w, R)
+    h = 1e-6
+    for _ in range(6):
+        d = rng.standard_normal(g0.shape) + 1j * rng.standard_normal(g0.shape)
+        fd = (oracle.image_loss(w.geom, w.E, g0 + h * d, model)[0]
+              - oracle.image_loss(w.geom, w.E, g0 - h * d, model)[0]) / (2 * h)
+        an = float(np.real(np.sum(np.conj(got) * d)))
+        assert abs(fd - an) <= TOL * np.sum(np.abs(got) * np.abs(d)), (fd, an)
+
+
+def test_gauge_and_optimum(torch, moff):
+    """Zero gradient at the true calibration of the calibration workload, and a
+    gradient orthogonal to a common phase rotation elsewhere."""
+    w = synth.make_config(5, n_time=4, n_chan=2)
+    g_true = w.extra["g_true"].astype(np.complex128)
+    E_sky = w.E.astype(np.complex128) / g_true[None]
+    model = oracle.moff_image(w.geom, E_sky, None)
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = dev(torch, w.E)
+        out = {}
+        for name, g in (("opt", 1.0 / g_true),
+                        ("off", (1.0 / g_true) * (1 + 0.05 * np.random.default_rng(2).standard_normal(g_true.shape)))):
+            gt = dev(torch, g.astype(np.complex64))
+            img = p.image(E, gt)
+            R = 2.0 * (img - dev(torch, model.astype(np.float32)))
+            grad = p.gain_vjp(E, gt, R.contiguous())
+            torch.cuda.synchronize()
+            out[name] = (grad.cpu().numpy().astype(np.complex128), g)
+    g_opt, _ = out["opt"]
+    g_off, goff = out["off"]
+    assert np.abs(g_opt).max() <= 1e-3 * np.abs(g_off).max()
+    for c in range(2):
+        v = np.sum(np.conj(g_off[c]) * goff[c])
+        assert abs(v.imag) <= TOL * np.sum(np.abs(g_off[c]) * np.abs(goff[c]))
+
+
+def test_autograd_function(torch, moff):
+    rng = np.random.default_rng(3)
+    w = synth.make_config(5, n_time=3, n_chan=2)
+    model = rng.standard_normal((2, 256, 256)).astype(np.float32) * 10.0
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = dev(torch, w.E)
+        gains = dev(torch, w.gains).requires_grad_(True)
+        img = moff.moff_image_autograd(p, E, gains)
+        loss = ((img - dev(torch, model)) ** 2).sum()
+        loss.backward()
+        torch.cuda.synchronize()
+        got = gains.grad.cpu().numpy().astype(np.complex128)
+        I = img.detach().cpu().numpy().astype(np.float64)
+    R = 2.0 * (I - model)
+    ref = oracle.gain_gradient(w.geom, w.E, w.gains, R)
+    assert rel_err(got, ref) <= TOL
