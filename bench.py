@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (heuristic configuration)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="also time the gain adjoint (moff_gain_vjp) on the same workload")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -142,6 +144,23 @@ def main():
         extra["staged_ms_per_step"] = round(st_ms, 3)
         extra["fused_speedup_vs_staged"] = round(st_ms / ms_per_step, 2)
         extra["staged_vs_fused_max_abs_diff"] = float((out2 - out).abs().max().item())
+
+    if args.adjoint:
+        g_in = gains if gains is not None else torch.ones((C, Na), dtype=torch.complex64, device=dev)
+        R = torch.randn((C, N, N), dtype=torch.float32, device=dev)
+        grad = torch.empty((C, Na), dtype=torch.complex64, device=dev)
+        plan.gain_vjp(E, g_in, R, out=grad)
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        reps = max(2, min(args.steps, 5))
+        a0.record(stream)
+        for _ in range(reps):
+            plan.gain_vjp(E, g_in, R, out=grad)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        extra["adjoint_ms_per_step"] = round(a0.elapsed_time(a1) / reps, 3)
+        extra["adjoint_frames_per_s"] = frames / (a0.elapsed_time(a1) / reps / 1e3)
 
     cpu = None
     if not args.no_cpu:
