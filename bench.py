@@ -8,8 +8,12 @@ samples of 4+4-bit complex input, 128 x 128 padded grid: 128,000 frames per step
 timing starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--staged]
+                    [--config 1..5] [--precision f32|f16|bf16] [--adjoint]
 
-Prints one JSON line.
+--precision f16 / bf16 runs the reduced-precision path (16-bit gridded fields,
+dense DFT on the matrix cores, float32 accumulation; grid 64 or 128) and also
+times the float32 path on the same input; the CPU-baseline leg's oracle images
+then give the per-image error of both.  Prints one JSON line.
 """
 import argparse
 import json
@@ -22,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (spec sheet)
+PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec sheet)
 
 
 def frame_flops(N, nnz):
@@ -31,10 +36,20 @@ def frame_flops(N, nnz):
     return 5 * N * N * math.log2(N * N) + 8 * nnz + 4 * N * N
 
 
+def mfma_frame_flops(N):
+    """Matrix-core work per frame of the dense-DFT path: the row stage multiplies
+    an L x 2L real block by 2L x 2N ([Re | Im] of N columns), the column stage a
+    2N x 2L block by 2L x N, with L = N / 2: 8 L N (L + N) flops."""
+    L = N // 2
+    return 8 * L * N * (L + N)
+
+
 def cpu_baseline(w, budget_s=10.0):
     """The FP64 oracle timed on the host on a bounded sample of the same workload:
     whole channels (all time samples) in channel order until about budget_s of CPU
-    work has been done; frames/s = frames imaged / seconds."""
+    work has been done; frames/s = frames imaged / seconds.  Also returns the
+    oracle images and mean squared fields of the sampled channels."""
+    import numpy as np
     import oracle
     threads = None
     try:
@@ -48,15 +63,62 @@ def cpu_baseline(w, budget_s=10.0):
     oracle.moff_channel(w.geom, w.E[:2], w.gains, 0, P)      # warm BLAS threads
     t0 = time.perf_counter()
     n = 0
+    images = []
     while n < w.E.shape[1]:
-        oracle.moff_channel(w.geom, w.E, w.gains, n, P)
+        img, parts = oracle.moff_channel(w.geom, w.E, w.gains, n, P, keep=True)
+        images.append((n, img, parts["S"] / T))
         n += 1
         if time.perf_counter() - t0 >= budget_s:
             break
     dt = time.perf_counter() - t0
-    return {"value": n * T / dt, "unit": "frames/s", "cores": threads or os.cpu_count(), "kind": "oracle",
+    del parts
+    line = {"value": n * T / dt, "unit": "frames/s", "cores": threads or os.cpu_count(), "kind": "oracle",
             "sample": f"{n} channel(s) x all {T} time samples of the same workload "
                       f"({n * T} frames, {dt:.1f} s, float64 NumPy oracle)"}
+    return line, images
+
+
+def image_errors(img, ref_images):
+    """Per sampled channel: err_inf = max|dI| / max|Pbar|, err_2 = ||dI|| / ||Pbar||."""
+    import numpy as np
+    out = []
+    for c, ref, pbar in ref_images:
+        d = img[c].astype(np.float64) - ref
+        out.append({"channel": c, "err_inf": float(np.abs(d).max() / np.abs(pbar).max()),
+                    "err_2": float(np.linalg.norm(d) / np.linalg.norm(pbar))})
+    return out
+
+
+def time_plan(plan, E, gains, out, steps, warmup, tune):
+    """(ms per step, mean fused-kernel ms, launch configuration).  The timed
+    steps run back to back on the current stream between two events; kernel
+    durations come from a second pass with per-call kernel events."""
+    import numpy as np
+    import torch
+    T = E.shape[0]
+    if tune:
+        plan.autotune(E, gains)
+    launch = plan.config(T)
+    for _ in range(warmup):
+        plan.image(E, gains, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        plan.image(E, gains, out=out)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_per_step = ev0.elapsed_time(ev1) / steps
+    plan.set_timing(True)
+    kernel_ms = []
+    for _ in range(steps):
+        plan.image(E, gains, out=out)
+        kernel_ms.append(plan.last_kernel_ms())
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+    return ms_per_step, float(np.mean(kernel_ms)), launch
 
 
 def main():
@@ -67,6 +129,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
     ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--grid", type=int, default=0, help="override the workload's grid size")
+    ap.add_argument("--precision", choices=("f32", "f16", "bf16"), default=None,
+                    help="f32: float32 FFT path; f16 / bf16: matrix-core DFT path (default: f16 for config 4)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (heuristic configuration)")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the gain adjoint (moff_gain_vjp) on the same workload")
@@ -77,8 +142,8 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; channels shard across GPUs "
                                    "with no exchange, so a multi-GPU figure is not measured here"}))
         sys.exit(2)
+    prec = args.precision or ("f16" if args.config == 4 else "f32")
 
-    import numpy as np
     import torch
     import paper_1510_08318_amd as moff
     import synth
@@ -90,45 +155,41 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    w = synth.make_config(args.config)
+    w = synth.make_config(args.config, grid_n=args.grid or None)
     T, C, Na = w.E.shape
     N = w.geom.grid_n
     dev = "cuda:0"
     E = torch.from_numpy(w.E).to(dev)
     gains = torch.from_numpy(w.gains).to(dev) if w.gains is not None else None
-    plan = moff.Plan.from_geometry(w.geom, device=0)
+    extra_flags = {"f32": 0, "f16": synth.MFMA_F16, "bf16": synth.MFMA_BF16}[prec]
+    plan = moff.Plan.from_geometry(w.geom, device=0, extra_flags=extra_flags)
     out = torch.empty((C, N, N), dtype=torch.float32, device=dev)
     nnz = int(sum(w.geom.ktype_k[t] ** 2 for t in w.geom.ant_ktype))
     frames = T * C
-
-    if not args.no_tune:
-        plan.autotune(E, gains)
-    launch = plan.config(T)
-    for _ in range(args.warmup):
-        plan.image(E, gains, out=out)
-    torch.cuda.synchronize()
-
-    plan.set_timing(True)
     stream = torch.cuda.current_stream()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    kernel_ms = []
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        plan.image(E, gains, out=out)
-        kernel_ms.append(plan.last_kernel_ms())
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    plan.set_timing(False)
-    ms_per_step = ev0.elapsed_time(ev1) / args.steps
-    k_ms = float(np.mean(kernel_ms))
-    value = frames / (ms_per_step / 1e3)
-    flops_launch = frame_flops(N, nnz) * frames
-    achieved = flops_launch / (k_ms / 1e3) / 1e12
 
+    ms_per_step, k_ms, launch = time_plan(plan, E, gains, out, args.steps, args.warmup, not args.no_tune)
+    value = frames / (ms_per_step / 1e3)
     extra = {"fused_kernel_ms": round(k_ms, 4), "frames_per_step": frames,
              "algorithmic_flops_per_frame": frame_flops(N, nnz)}
+    if prec == "f32":
+        achieved = frame_flops(N, nnz) * frames / (k_ms / 1e3) / 1e12
+        roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
+    else:
+        extra["mfma_flops_per_frame"] = mfma_frame_flops(N)
+        achieved = mfma_frame_flops(N) * frames / (k_ms / 1e3) / 1e12
+        roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16BIT_TFLOPS, "unit": "TFLOP/s",
+                    "frac": achieved / PEAK_MFMA_16BIT_TFLOPS, "traffic": None}
+        plan32 = moff.Plan.from_geometry(w.geom, device=0)
+        out32 = torch.empty_like(out)
+        ms32, k32, launch32 = time_plan(plan32, E, gains, out32, args.steps, args.warmup, not args.no_tune)
+        plan32.close()
+        extra["f32_fft_ms_per_step"] = round(ms32, 4)
+        extra["f32_fft_kernel_ms"] = round(k32, 4)
+        extra["f32_fft_frames_per_s"] = frames / (ms32 / 1e3)
+        extra["speedup_vs_f32_fft"] = round(ms32 / ms_per_step, 3)
+
     if args.staged:
         out2 = torch.empty_like(out)
         plan.image_staged(E, gains, out=out2)
@@ -164,7 +225,12 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(w)
+        cpu, ref_images = cpu_baseline(w)
+        img = out.cpu().numpy()
+        extra["error_vs_oracle"] = {prec: image_errors(img, ref_images)}
+        if prec != "f32":
+            extra["error_vs_oracle"]["f32"] = image_errors(out32.cpu().numpy(), ref_images)
+        del ref_images
 
     line = {
         "metric": "MOFF frames/s (grid x channels per time sample)",
@@ -177,14 +243,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": prec,
         "data": "synthetic (seeded point-source sky + Gaussian noise" + (", 4+4-bit quantised)" if (w.geom.flags & synth.IN_CI4) else ")"),
         "config": {"workload": synth.CONFIG_NAMES[args.config],
                    "n_ant": Na, "n_chan": C, "n_time": T, "grid": N,
                    "input": "ci4" if (w.geom.flags & synth.IN_CI4) else "c64",
                    "launch": {k: launch[k] for k in ("variant", "slices", "grid", "threads", "tuned")}},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None},
+        "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,
     }

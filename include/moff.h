@@ -60,8 +60,20 @@ enum {
   MOFF_IN_CI4 = 1,         /* E is one byte per sample: re = high nibble, im = low nibble,
                               two's complement in [-8, 7] */
   MOFF_AUTOCORR_NONE = 2,  /* keep the antenna self power: I = S / T */
-  MOFF_NORM_PAIRS = 4      /* multiply the image by 1 / (n_ant (n_ant - 1)) (Sec. 5,
+  MOFF_NORM_PAIRS = 4,     /* multiply the image by 1 / (n_ant (n_ant - 1)) (Sec. 5,
                               eq. wt-dirty-image-EPIC: average over antenna pairs) */
+  MOFF_MFMA_F16 = 8,       /* reduced precision: the gridded field is rounded to IEEE
+                              binary16 and the padded 2-D DFT (Sec. 3) runs as two dense
+                              complex matrix products on the matrix cores with float32
+                              accumulation; phase factors are made in float64 and rounded
+                              once.  grid_n must be 64 or 128.  binary16 holds gridded
+                              values up to 65504 in magnitude; components below 2^-14
+                              lose relative precision.  Error against the exact image:
+                              of order 2^-11 relative to the image peak (stated bound
+                              16 * 2^-11 on max|dI| / max(S/T)). */
+  MOFF_MFMA_BF16 = 16      /* as MOFF_MFMA_F16 with bfloat16 (float32 range, 8-bit
+                              significand; stated bound 16 * 2^-8). At most one of the
+                              two MFMA flags may be set. */
 };
 
 /*
@@ -86,7 +98,8 @@ enum {
  *                     shortest wavelength, widened if needed so that the layout
  *                     span plus the widest footprint and one cell of slack fits
  *                     in N/2 cells.
- *   flags           : MOFF_IN_* | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS.
+ *   flags           : MOFF_IN_* | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS |
+ *                     MOFF_MFMA_F16 or MOFF_MFMA_BF16.
  *
  * Footprint placement: antenna a with a k x k table covers cells
  * ix0_a .. ix0_a + k - 1 with ix0_a = floor(x_a / cell - (k - 1) / 2 + 0.5)
@@ -158,6 +171,32 @@ moff_status moff_plan_power_pattern(moff_plan plan, int32_t ktype, double* out);
 moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w, uint32_t* out, float* weights,
                                      int32_t* prog_len, int32_t* n_threads, int32_t* n_classes,
                                      int32_t* row_pitch, int32_t* n_weights);
+
+/*
+ * Tables of the reduced-precision (MOFF_MFMA_*) path, for host-side tests.
+ * Sizes first (any pointer may be NULL): prog_len entries per thread,
+ * n_threads threads, row_pitch 16-bit elements per LDS row, dft_len 16-bit
+ * words of phase-factor operands.
+ *   prog : uint32 [prog_len][n_threads][2] gather entries (x, y) over the
+ *          non-empty aperture cells (iy, ix): x bits 0..11 antenna slot (n_ant =
+ *          the zero slot), bits 12..22 kernel tap (all types back to back), bit 31
+ *          "cell complete: store"; y = iy * row_pitch + ix, the LDS index of the
+ *          cell's real part (its imaginary part is at y + grid_n / 2).
+ *   dft  : uint16 [2][grid_n / 32][grid_n / 16][2][64][8] binary16 or bfloat16
+ *          bit patterns, indexed [stage][wave][k-step][re/im][lane][slot]:
+ *          stage 0 = row transform, exp(+2 pi i ix (q - N/2) / N) / (N/2) at
+ *          column q = 32 wave + lane % 32 and contraction index
+ *          kk = 16 k-step + 8 (lane / 32) + slot (kk < N/2: real-part rows,
+ *          ix = kk; else imaginary-part rows, ix = kk - N/2); stage 1 = column
+ *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 wave + lane % 32
+ *          and iy from kk likewise.  With w the phase factor at (kk mod N/2):
+ *          re/im = 0 holds Re w for kk < N/2 and -Im w above; re/im = 1 holds
+ *          Im w below and Re w above, so that [Re x | Im x] times the two blocks
+ *          gives Re and Im of the complex product.
+ * MOFF_ERR_UNSUPPORTED if the plan has no MFMA flag.
+ */
+moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft, int32_t* prog_len,
+                                  int32_t* n_threads, int32_t* row_pitch, int32_t* dft_len);
 
 /*
  * Launch configuration of the fused path.  The frame transform has one or two

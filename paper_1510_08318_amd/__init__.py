@@ -13,11 +13,11 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (MOFF_AUTOCORR_NONE, MOFF_IN_C64, MOFF_IN_CI4, MOFF_NORM_PAIRS,  # noqa: F401
-                   MoffError, moff_geometry)
+from ._lib import (MOFF_AUTOCORR_NONE, MOFF_IN_C64, MOFF_IN_CI4, MOFF_MFMA_BF16, MOFF_MFMA_F16,  # noqa: F401
+                   MOFF_NORM_PAIRS, MoffError, moff_geometry)
 
 __all__ = ["Plan", "MoffError", "MOFF_IN_C64", "MOFF_IN_CI4", "MOFF_AUTOCORR_NONE", "MOFF_NORM_PAIRS",
-           "library_path", "moff_image_autograd"]
+           "MOFF_MFMA_F16", "MOFF_MFMA_BF16", "library_path", "moff_image_autograd"]
 
 
 def library_path():
@@ -67,11 +67,12 @@ class Plan:
         self.handle = _lib.moff_plan_create(g, self.device)
 
     @classmethod
-    def from_geometry(cls, geom, device=0):
+    def from_geometry(cls, geom, device=0, extra_flags=0):
         """Build from any object with the fields of the C geometry (ant_xy, ktype_k,
-        ktype_vals, ant_ktype, freq_hz, grid_n, cell_m, flags)."""
+        ktype_vals, ant_ktype, freq_hz, grid_n, cell_m, flags); extra_flags are
+        OR-ed into flags (e.g. MOFF_MFMA_F16)."""
         return cls(geom.ant_xy, geom.ktype_k, geom.ktype_vals, geom.ant_ktype, geom.freq_hz, geom.grid_n,
-                   geom.cell_m, geom.flags, device)
+                   geom.cell_m, int(geom.flags) | int(extra_flags), device)
 
     # ---- lifetime --------------------------------------------------------
     def close(self):
@@ -126,6 +127,19 @@ class Plan:
         _lib.moff_plan_gather_program(self.handle, int(variant), int(w), _ptr(out, ctypes.c_uint32),
                                       _ptr(wts, ctypes.c_float), *[ctypes.byref(s) for s in sizes])
         return out, wts.view(np.complex64), dict(prog_len=plen, n_threads=nt, n_classes=ncls, row_pitch=pitch)
+
+    def mfma_tables(self):
+        """(gather entries uint32 [prog_len, n_threads, 2], phase-factor operand bit
+        patterns uint16 [2, N/32, N/16, 2, 64, 8], sizes) of a MOFF_MFMA_* plan."""
+        sizes = [ctypes.c_int32() for _ in range(4)]
+        _lib.moff_plan_mfma_tables(self.handle, None, None, *[ctypes.byref(s) for s in sizes])
+        plen, nt, pitch, ndft = (s.value for s in sizes)
+        prog = np.zeros((plen, nt, 2), np.uint32)
+        dft = np.zeros(ndft, np.uint16)
+        _lib.moff_plan_mfma_tables(self.handle, _ptr(prog, ctypes.c_uint32), _ptr(dft, ctypes.c_uint16),
+                                   *[ctypes.byref(s) for s in sizes])
+        N = self.N
+        return prog, dft.reshape(2, N // 32, N // 16, 2, 64, 8), dict(prog_len=plen, n_threads=nt, row_pitch=pitch)
 
     def autotune(self, E, gains=None, stream=None):
         """Time every launch configuration on this input and keep the fastest."""

@@ -20,9 +20,12 @@ MOFF_IN_C64 = 0
 MOFF_IN_CI4 = 1
 MOFF_AUTOCORR_NONE = 2
 MOFF_NORM_PAIRS = 4
+MOFF_MFMA_F16 = 8
+MOFF_MFMA_BF16 = 16
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_u32p = ctypes.POINTER(ctypes.c_uint32)
+c_u16p = ctypes.POINTER(ctypes.c_uint16)
 c_f32p = ctypes.POINTER(ctypes.c_float)
 c_f64p = ctypes.POINTER(ctypes.c_double)
 
@@ -53,6 +56,7 @@ SIGNATURES = {
     "moff_plan_power_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_f64p]),
     "moff_plan_gather_program": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, c_u32p, c_f32p,
                                                 c_i32p, c_i32p, c_i32p, c_i32p, c_i32p]),
+    "moff_plan_mfma_tables": (ctypes.c_int, [ctypes.c_void_p, c_u32p, c_u16p, c_i32p, c_i32p, c_i32p, c_i32p]),
     "moff_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "moff_plan_set_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
@@ -151,6 +155,10 @@ def moff_plan_power_pattern(plan, ktype, out):
 def moff_plan_gather_program(plan, variant, w, out, weights, prog_len, n_threads, n_classes, row_pitch, n_weights):
     _call("moff_plan_gather_program", plan, variant, w, out, weights, prog_len, n_threads, n_classes, row_pitch,
           n_weights)
+
+
+def moff_plan_mfma_tables(plan, prog, dft, prog_len, n_threads, row_pitch, dft_len):
+    _call("moff_plan_mfma_tables", plan, prog, dft, prog_len, n_threads, row_pitch, dft_len)
 
 
 def moff_plan_autotune(plan, E, n_time, gains, stream):

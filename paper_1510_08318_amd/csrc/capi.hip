@@ -31,6 +31,8 @@ struct moff_plan_s {
   int* d_ant_cells = nullptr;   // [n_ant][2] (ix0, iy0)
   int* d_ktype_k = nullptr;
   int* d_ktype_off = nullptr;
+  GatherEntry* d_mfma_prog = nullptr;   // reduced-precision path (MOFF_MFMA_*)
+  uint16_t* d_mfma_dft = nullptr;
   // workspace, grown on demand
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -73,8 +75,9 @@ moff_status upload(T** dst, const void* src, size_t bytes) {
 }
 
 void free_device(moff_plan p) {
-  void* ptrs[] = {p->d_tw,      p->d_Pp,      p->d_ant_type,  p->d_ktab,      p->d_csr_ptr, p->d_csr_ant,
-                  p->d_csr_tap, p->d_ant_cells, p->d_ktype_k, p->d_ktype_off, p->d_ws};
+  void* ptrs[] = {p->d_tw,        p->d_Pp,        p->d_ant_type, p->d_ktab,        p->d_csr_ptr,
+                  p->d_csr_ant,   p->d_csr_tap,   p->d_ant_cells, p->d_ktype_k,    p->d_ktype_off,
+                  p->d_mfma_prog, p->d_mfma_dft,  p->d_ws};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
@@ -120,6 +123,38 @@ struct LaunchConfig {
   int variant, slices, grid;
 };
 
+bool is_mfma(const HostPlan& hp) { return hp.mfma.prec != 0; }
+
+// Work items per time slice, LDS bytes and resident workgroups of a variant.
+struct KernelFootprint {
+  int per_slice;
+  size_t lds;
+  int resident;
+  int threads;
+};
+
+KernelFootprint footprint(moff_plan p, int variant) {
+  const HostPlan& hp = p->hp;
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  KernelFootprint f{};
+  if (is_mfma(hp)) {
+    f.per_slice = hp.n_chan;
+    const bool in_lds = moff::mfma_prog_fits_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len);
+    f.lds = moff::mfma_lds_bytes(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len, in_lds);
+    f.resident = std::max(1, moff::mfma_blocks_per_cu(hp.N, hp.mfma.prec, ci4, f.lds)) * std::max(1, p->cu_count);
+    f.threads = moff::mfma_threads(hp.N);
+  } else {
+    const HostPlan::Variant& V = hp.variants[variant];
+    f.per_slice = V.shape.SX * hp.n_chan;
+    f.lds = moff::fused_lds_bytes(hp.N, variant, V.n_weights(), hp.n_ant);
+    f.resident = std::max(1, moff::fused_blocks_per_cu(hp.N, variant, ci4, f.lds)) * std::max(1, p->cu_count);
+    f.threads = V.shape.NT;
+  }
+  return f;
+}
+
+int n_variants(const HostPlan& hp) { return is_mfma(hp) ? 1 : static_cast<int>(hp.variants.size()); }
+
 // Launch configuration for n_time frames: the tuned or set choice, else a
 // heuristic: shape variant 0 and enough time slices for about two rounds of
 // resident workgroups.  One work item (column class, channel, time slice) per
@@ -127,12 +162,9 @@ struct LaunchConfig {
 LaunchConfig launch_config(moff_plan p, int64_t n_time) {
   const HostPlan& hp = p->hp;
   LaunchConfig lc{};
-  lc.variant = std::min<int>(p->variant, static_cast<int>(hp.variants.size()) - 1);
-  const HostPlan::Variant& V = hp.variants[lc.variant];
-  const int per_slice = V.shape.SX * hp.n_chan;
-  const bool ci4 = hp.flags & MOFF_IN_CI4;
-  const size_t lds = moff::fused_lds_bytes(hp.N, lc.variant, V.n_weights(), hp.n_ant);
-  const int resident = std::max(1, moff::fused_blocks_per_cu(hp.N, lc.variant, ci4, lds)) * std::max(1, p->cu_count);
+  lc.variant = std::min<int>(p->variant, n_variants(hp) - 1);
+  const KernelFootprint f = footprint(p, lc.variant);
+  const int per_slice = f.per_slice, resident = f.resident;
   int slices = p->slices;
   if (slices <= 0) slices = (2 * resident + per_slice - 1) / per_slice;
   slices = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({static_cast<int64_t>(slices), n_time, 256})));
@@ -162,20 +194,61 @@ moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_ti
   return a;
 }
 
+moff::MfmaArgs mfma_args(moff_plan p, const void* E, int64_t n_time, const float* gains) {
+  const HostPlan& hp = p->hp;
+  moff::MfmaArgs a{};
+  a.E = E;
+  a.gains = reinterpret_cast<const float2*>(gains);
+  a.prog = p->d_mfma_prog;
+  a.prog_len = hp.mfma.prog_len;
+  a.prog_in_lds = moff::mfma_prog_fits_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len) ? 1 : 0;
+  a.ktab = p->d_ktab;
+  a.n_taps = hp.n_taps;
+  a.dft = p->d_mfma_dft;
+  a.ant_type = p->d_ant_type;
+  a.n_ant = hp.n_ant;
+  a.n_chan = hp.n_chan;
+  a.n_types = hp.n_ktypes;
+  a.n_time = n_time;
+  a.Pp = p->d_Pp;
+  a.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  return a;
+}
+
+// One launch of the plan's fused kernel (float32 FFT or reduced-precision MFMA
+// transform) writing `out` / `outA` in epilogue `mode`.
+hipError_t launch_fused_kernel(moff_plan p, const LaunchConfig& lc, const void* E, int64_t n_time,
+                               const float* gains, float* out, double* outA, int mode, hipStream_t st) {
+  const HostPlan& hp = p->hp;
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  if (is_mfma(hp)) {
+    moff::MfmaArgs a = mfma_args(p, E, n_time, gains);
+    a.slices = lc.slices;
+    a.scale = image_scale(hp, n_time);
+    a.out = out;
+    a.outA = outA;
+    a.mode = mode;
+    return moff::launch_mfma(a, hp.N, hp.mfma.prec, ci4, lc.grid, st);
+  }
+  moff::FusedArgs a = fused_args(p, lc.variant, E, n_time, gains);
+  a.slices = lc.slices;
+  a.scale = image_scale(hp, n_time);
+  a.out = out;
+  a.outA = outA;
+  a.mode = mode;
+  return moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
+}
+
 moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, int64_t n_time, const float* gains,
                           float* out, double* outA, bool final_image, hipStream_t st) {
   const HostPlan& hp = p->hp;
-  moff::FusedArgs a = fused_args(p, lc.variant, E, n_time, gains);
-  const bool ci4 = hp.flags & MOFF_IN_CI4;
-  if (moff::fused_lds_bytes(hp.N, lc.variant, a.n_weights, hp.n_ant) > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
-  a.slices = lc.slices;
-  a.scale = image_scale(hp, n_time);
+  if (footprint(p, lc.variant).lds > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
+  const double scale = image_scale(hp, n_time);
+  const int subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
   if (lc.slices == 1) {
-    a.out = out;
-    a.outA = outA;
-    a.mode = final_image ? moff::kModeFinal : moff::kModeAccum;
     if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-    hipError_t e = moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
+    hipError_t e = launch_fused_kernel(p, lc, E, n_time, gains, out, outA,
+                                       final_image ? moff::kModeFinal : moff::kModeAccum, st);
     if (e != hipSuccess) return MOFF_ERR_HIP;
     if (p->timing) {
       if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -188,19 +261,18 @@ moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, in
   const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * lc.slices;
   moff_status ms = ensure_workspace(p, s_bytes + a_bytes);
   if (ms != MOFF_OK) return ms;
-  a.out = static_cast<float*>(p->d_ws);
-  a.outA = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + s_bytes);
-  a.mode = moff::kModePartial;
+  float* S_part = static_cast<float*>(p->d_ws);
+  double* A_part = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + s_bytes);
   if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-  hipError_t e = moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
+  hipError_t e = launch_fused_kernel(p, lc, E, n_time, gains, S_part, A_part, moff::kModePartial, st);
   if (e != hipSuccess) return MOFF_ERR_HIP;
   if (p->timing) {
     if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
     p->timed = true;
   }
   moff::ReduceArgs r{};
-  r.S_part = a.out;
-  r.A_part = a.outA;
+  r.S_part = S_part;
+  r.A_part = A_part;
   r.Pp = p->d_Pp;
   r.out = out;
   r.outA = outA;
@@ -209,8 +281,8 @@ moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, in
   r.n_types = hp.n_ktypes;
   r.slices = lc.slices;
   r.final_image = final_image ? 1 : 0;
-  r.subtract = a.subtract;
-  r.scale = a.scale;
+  r.subtract = subtract;
+  r.scale = scale;
   return hip_status(moff::launch_reduce(r, st));
 }
 
@@ -289,6 +361,10 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
     for (size_t v = 0; v < hp.variants.size(); ++v) {
       up(upload(&p->d_prog[v], hp.variants[v].prog.data(), sizeof(GatherEntry) * hp.variants[v].prog.size()));
       up(upload(&p->d_weights[v], hp.variants[v].weights.data(), sizeof(float) * hp.variants[v].weights.size()));
+    }
+    if (hp.mfma.prec) {
+      up(upload(&p->d_mfma_prog, hp.mfma.prog.data(), sizeof(GatherEntry) * hp.mfma.prog.size()));
+      up(upload(&p->d_mfma_dft, hp.mfma.dft.data(), sizeof(uint16_t) * hp.mfma.dft.size()));
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
@@ -400,9 +476,26 @@ moff_status moff_plan_gather_program(moff_plan p, int32_t variant, int32_t w, ui
   return MOFF_OK;
 }
 
+moff_status moff_plan_mfma_tables(moff_plan p, uint32_t* prog, uint16_t* dft, int32_t* prog_len, int32_t* n_threads,
+                                  int32_t* row_pitch, int32_t* dft_len) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  const HostPlan::Mfma& T = p->hp.mfma;
+  if (!T.prec) return MOFF_ERR_UNSUPPORTED;
+  if (prog_len) *prog_len = T.prog_len;
+  if (n_threads) *n_threads = T.NT;
+  if (row_pitch) *row_pitch = T.pitch;
+  if (dft_len) *dft_len = static_cast<int32_t>(T.dft.size());
+  if (prog)
+    for (size_t i = 0; i < T.prog.size(); ++i) {
+      prog[2 * i] = T.prog[i].x;
+      prog[2 * i + 1] = T.prog[i].y;
+    }
+  if (dft) std::memcpy(dft, T.dft.data(), sizeof(uint16_t) * T.dft.size());
+  return MOFF_OK;
+}
+
 moff_status moff_plan_set_config(moff_plan p, int32_t variant, int32_t slices) {
-  if (!p || variant < 0 || variant >= static_cast<int32_t>(p->hp.variants.size()) || slices < 0 || slices > 256)
-    return MOFF_ERR_INVALID_ARG;
+  if (!p || variant < 0 || variant >= n_variants(p->hp) || slices < 0 || slices > 256) return MOFF_ERR_INVALID_ARG;
   p->variant = variant;
   p->slices = slices;
   p->tuned = false;
@@ -410,7 +503,7 @@ moff_status moff_plan_set_config(moff_plan p, int32_t variant, int32_t slices) {
 }
 
 moff_status moff_plan_get_config(moff_plan p, int64_t n_time, int32_t* variant, int32_t* slices, int32_t* grid,
-                                 int32_t* threads, int32_t* n_variants, int32_t* tuned) {
+                                 int32_t* threads, int32_t* n_variants_out, int32_t* tuned) {
   if (!p || n_time < 1) return MOFF_ERR_INVALID_ARG;
   if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
   DeviceGuard guard(p->device);
@@ -419,8 +512,8 @@ moff_status moff_plan_get_config(moff_plan p, int64_t n_time, int32_t* variant, 
   if (variant) *variant = lc.variant;
   if (slices) *slices = lc.slices;
   if (grid) *grid = lc.grid;
-  if (threads) *threads = p->hp.variants[lc.variant].shape.NT;
-  if (n_variants) *n_variants = static_cast<int32_t>(p->hp.variants.size());
+  if (threads) *threads = footprint(p, lc.variant).threads;
+  if (n_variants_out) *n_variants_out = n_variants(p->hp);
   if (tuned) *tuned = p->tuned ? 1 : 0;
   return MOFF_OK;
 }
@@ -447,13 +540,10 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   float best = 1e30f;
   int bv = saved_v, bs = saved_s;
   moff_status result = MOFF_OK;
-  for (int v = 0; v < static_cast<int>(hp.variants.size()) && result == MOFF_OK; ++v) {
-    const HostPlan::Variant& V = hp.variants[v];
-    if (moff::fused_lds_bytes(hp.N, v, V.n_weights(), hp.n_ant) > size_t(159) * 1024) continue;
-    const int per_slice = V.shape.SX * hp.n_chan;
-    const size_t lds = moff::fused_lds_bytes(hp.N, v, V.n_weights(), hp.n_ant);
-    const int resident =
-        std::max(1, moff::fused_blocks_per_cu(hp.N, v, hp.flags & MOFF_IN_CI4, lds)) * std::max(1, p->cu_count);
+  for (int v = 0; v < n_variants(hp) && result == MOFF_OK; ++v) {
+    const KernelFootprint f = footprint(p, v);
+    if (f.lds > size_t(159) * 1024) continue;
+    const int per_slice = f.per_slice, resident = f.resident;
     std::vector<int> cand;
     for (int k = 1; k <= 4; ++k) cand.push_back((k * resident + per_slice - 1) / per_slice);  // whole rounds
     for (int sl : {1, 2, 4, 8, 16, 32, 64}) cand.push_back(sl);

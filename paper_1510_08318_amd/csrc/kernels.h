@@ -79,8 +79,6 @@ struct FinalizeArgs {
   double scale;
 };
 
-// Fused kernel of grid size N, shape variant V (shape.h), `grid` workgroups
-// (each loops over the SX * n_chan * slices work items with stride `grid`).
 // Gain-gradient (adjoint) kernels.
 struct AdjFftArgs {
   const float2* Y;             // [F][N][N] image fields of a time chunk, frame f = t * n_chan + c
@@ -116,10 +114,42 @@ struct GradFinalArgs {
   double scale;                // 2 s / T
 };
 
+// Reduced-precision fused kernel (MOFF_MFMA_*): one workgroup per (channel,
+// time slice); same epilogue modes and outputs as FusedArgs.
+struct MfmaArgs {
+  const void* E;               // [T][C][n_ant] c64 or ci4
+  const float2* gains;         // [C][n_ant] or nullptr
+  const GatherEntry* prog;     // [prog_len][NT]
+  int prog_len;
+  int prog_in_lds;             // copy the program into LDS (mfma_prog_fits_lds)
+  const float2* ktab;          // [n_taps] kernel taps, all types back to back
+  int n_taps;
+  const uint16_t* dft;         // phase-factor operands (HostPlan::Mfma::dft), 16-byte aligned
+  const int* ant_type;
+  int n_ant, n_chan, n_types;
+  int64_t n_time;
+  int slices;
+  float* out;
+  double* outA;
+  const double* Pp;
+  double scale;
+  int subtract;
+  int mode;
+};
+
+constexpr size_t kMfmaProgLdsLimit = 80 * 1024;   // keeps two workgroups' LDS within one CU
+size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds);
+bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len);
+int mfma_threads(int N);
+hipError_t launch_mfma(const MfmaArgs& a, int N, int prec, bool ci4, int grid, hipStream_t st);
+int mfma_blocks_per_cu(int N, int prec, bool ci4, size_t lds);
+
 hipError_t launch_adjoint_fft2(const AdjFftArgs& a, int N, int64_t n_frames, hipStream_t st);
 hipError_t launch_degrid(const DegridArgs& a, bool ci4, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);
 
+// Fused kernel of grid size N, shape variant V (shape.h), one work item
+// (column class, channel, time slice) per workgroup of a `grid`-sized launch.
 size_t fused_lds_bytes(int N, int V, int n_weights, int n_ant);
 hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st);
 int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds);

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 namespace moff {
@@ -34,7 +35,135 @@ moff_status fail(std::string* why, moff_status s, const char* msg) {
   return s;
 }
 
+// Round |x| to `sig` significant bits (ties to even) with the quantum never
+// below 2^min_q (gradual underflow); exact in float64 because the scalings are
+// powers of two.
+double round_sig(double ax, int sig, int min_q) {
+  if (ax == 0.0) return 0.0;
+  int e = 0;
+  (void)std::frexp(ax, &e);                 // ax = m 2^e, 0.5 <= m < 1
+  const int q = std::max(e - sig, min_q);   // quantum 2^q
+  return std::nearbyint(std::ldexp(ax, -q)) * std::ldexp(1.0, q);
+}
+
+// Contiguous greedy split of `cost` (in order) over at most `lanes` lanes with
+// the smallest per-lane maximum; returns that maximum.
+long long balanced_split(const std::vector<int>& cost, int lanes) {
+  auto lanes_needed = [&](long long B) {
+    int n = 1;
+    long long cur = 0;
+    for (int c : cost) {
+      if (cur + c > B) {
+        ++n;
+        cur = 0;
+      }
+      cur += c;
+    }
+    return n;
+  };
+  long long lo = 1, hi = 1;
+  for (int c : cost) {
+    lo = std::max<long long>(lo, c);
+    hi += c;
+  }
+  while (lo < hi) {
+    long long mid = (lo + hi) / 2;
+    if (lanes_needed(mid) <= lanes) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
+// Tables of the reduced-precision transform: the gather program over the
+// non-empty aperture cells (the LDS grid is cleared once per workgroup, so empty
+// cells are never written) and the phase-factor operands of both DFT stages in
+// the register order of the kernel.  The row stage is scaled by 1 / (N/2), a
+// power of two, so that its rounded output cannot exceed the largest gridded
+// value; the kernel multiplies |Y|^2 back by (N/2)^2 exactly.
+moff_status build_mfma_tables(HostPlan& P, std::string* why) {
+  const int N = P.N, L = P.L, NW = N / 32, KS = L / 8;
+  HostPlan::Mfma& T = P.mfma;
+  T.prec = (P.flags & MOFF_MFMA_BF16) ? 2 : 1;
+  T.NT = NW * 64;
+  T.pitch = 2 * L + 8;
+  std::vector<int> cells, cost;
+  for (int i = 0; i < L * L; ++i) {
+    const int n = P.csr_ptr[i + 1] - P.csr_ptr[i];
+    if (n > 0) {
+      cells.push_back(i);
+      cost.push_back(n);
+    }
+  }
+  const long long B = balanced_split(cost, T.NT);
+  if (B > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
+  if (P.n_taps >= 2048) return fail(why, MOFF_ERR_UNSUPPORTED, "too many kernel taps for the gather encoding");
+  T.prog_len = static_cast<int>(B);
+  const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
+  T.prog.assign(static_cast<size_t>(T.prog_len) * T.NT, GatherEntry{zero_slot, 0});
+  int lane = 0, k = 0;
+  long long cur = 0;
+  for (size_t ci = 0; ci < cells.size(); ++ci) {
+    if (cur + cost[ci] > B) {
+      ++lane;
+      k = 0;
+      cur = 0;
+    }
+    cur += cost[ci];
+    const int iy = cells[ci] / L, ix = cells[ci] % L;
+    const uint32_t dst = static_cast<uint32_t>(iy * T.pitch + ix);
+    for (int e = P.csr_ptr[cells[ci]]; e < P.csr_ptr[cells[ci] + 1]; ++e) {
+      T.prog[static_cast<size_t>(k) * T.NT + lane] =
+          GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (static_cast<uint32_t>(P.csr_tap[e]) << 12), dst};
+      ++k;
+    }
+    T.prog[static_cast<size_t>(k - 1) * T.NT + lane].x |= kStoreBit;
+  }
+
+  auto enc = [&](double v) { return T.prec == 2 ? to_bfloat16(v) : to_binary16(v); };
+  T.dft.assign(static_cast<size_t>(2) * NW * KS * 2 * 64 * 8, 0);
+  const double s1 = 1.0 / L;
+  for (int st = 0; st < 2; ++st)
+    for (int w = 0; w < NW; ++w)
+      for (int ks = 0; ks < KS; ++ks)
+        for (int ri = 0; ri < 2; ++ri)
+          for (int ln = 0; ln < 64; ++ln)
+            for (int i = 0; i < 8; ++i) {
+              const int kk = 16 * ks + 8 * (ln / 32) + i;
+              const int n = 32 * w + ln % 32;   // output column q (stage 0) or row r (stage 1)
+              const int j = kk % L;              // ix (stage 0) or iy (stage 1)
+              const bool upper = kk >= L;        // imaginary-part rows of the contraction
+              std::complex<double> f = unit_root(static_cast<long long>(j) * (n - N / 2), N);
+              if (st == 0) f *= s1;
+              const double v = ri == 0 ? (upper ? -f.imag() : f.real()) : (upper ? f.real() : f.imag());
+              T.dft[((((static_cast<size_t>(st) * NW + w) * KS + ks) * 2 + ri) * 64 + ln) * 8 + i] = enc(v);
+            }
+  return MOFF_OK;
+}
+
 }  // namespace
+
+uint16_t to_binary16(double x) {
+  const uint16_t sign = std::signbit(x) ? 0x8000u : 0u;
+  double q = round_sig(std::fabs(x), 11, -24);
+  if (!(q < 65520.0)) return static_cast<uint16_t>(sign | 0x7C00u);   // overflow to infinity
+  if (q == 0.0) return sign;
+  int e = 0;
+  (void)std::frexp(q, &e);                  // q = m 2^e
+  if (e - 1 < -14)                          // subnormal: q = mant 2^-24
+    return static_cast<uint16_t>(sign | static_cast<uint16_t>(std::ldexp(q, 24)));
+  const uint16_t mant = static_cast<uint16_t>(std::ldexp(q, 11 - e) - 1024.0);
+  return static_cast<uint16_t>(sign | ((e - 1 + 15) << 10) | mant);
+}
+
+uint16_t to_bfloat16(double x) {
+  // 8 significant bits, float32 exponent range (values here are at most 1 in
+  // magnitude, far from overflow); the rounded value is exact in float32.
+  const double q = round_sig(std::fabs(x), 8, -133);
+  float f = static_cast<float>(std::signbit(x) ? -q : q);
+  uint32_t bits = 0;
+  std::memcpy(&bits, &f, sizeof(bits));
+  return static_cast<uint16_t>(bits >> 16);
+}
 
 moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* why) {
   if (!g || !hp) return fail(why, MOFF_ERR_INVALID_ARG, "null geometry or plan");
@@ -43,10 +172,14 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     return fail(why, MOFF_ERR_INVALID_ARG, "null geometry array");
   if (g->n_ktypes < 1 || g->n_ktypes > kMaxTypes) return fail(why, MOFF_ERR_INVALID_ARG, "n_ktypes out of [1, 4]");
   if (g->n_chan < 1) return fail(why, MOFF_ERR_INVALID_ARG, "n_chan < 1");
-  if (g->flags & ~uint32_t(MOFF_IN_CI4 | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS))
+  if (g->flags & ~uint32_t(MOFF_IN_CI4 | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS | MOFF_MFMA_F16 | MOFF_MFMA_BF16))
     return fail(why, MOFF_ERR_INVALID_ARG, "unknown flag bits");
+  if ((g->flags & MOFF_MFMA_F16) && (g->flags & MOFF_MFMA_BF16))
+    return fail(why, MOFF_ERR_INVALID_ARG, "at most one of MOFF_MFMA_F16 and MOFF_MFMA_BF16");
   if (!is_pow2(g->grid_n) || g->grid_n < 8 || g->grid_n > 256)
     return fail(why, MOFF_ERR_GRID_NOT_POW2, "grid_n must be a power of two in [8, 256]");
+  if ((g->flags & (MOFF_MFMA_F16 | MOFF_MFMA_BF16)) && g->grid_n != 64 && g->grid_n != 128)
+    return fail(why, MOFF_ERR_UNSUPPORTED, "the MFMA transform is built for grid_n 64 and 128");
   if (!(g->cell_m >= 0.0) || !std::isfinite(g->cell_m)) return fail(why, MOFF_ERR_INVALID_ARG, "bad cell_m");
 
   HostPlan& P = *hp;
@@ -288,6 +421,10 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     P.variants.push_back(std::move(V));
   }
   if (P.variants.empty()) return fail(why, MOFF_ERR_UNSUPPORTED, "no frame shape for this grid size");
+  if (P.flags & (MOFF_MFMA_F16 | MOFF_MFMA_BF16)) {
+    moff_status s = build_mfma_tables(P, why);
+    if (s != MOFF_OK) return s;
+  }
   return MOFF_OK;
 }
 

@@ -64,7 +64,20 @@ struct HostPlan {
   };
   std::vector<Variant> variants;
   int max_cell_entries = 0;
+
+  // reduced-precision frame transform (MOFF_MFMA_*): dense DFT matrices on the
+  // matrix cores; see mfma.hip for the operand layout
+  struct Mfma {
+    int prec = 0;                            // 0: off, 1: binary16, 2: bfloat16
+    int NT = 0, pitch = 0, prog_len = 0;
+    std::vector<GatherEntry> prog;           // [prog_len][NT]; y = iy * pitch + ix
+    std::vector<uint16_t> dft;               // [2][N/32][N/16][2][64][8] operand bit patterns
+  } mfma;
 };
+
+// 16-bit encodings of a float64 value, rounded to nearest (ties to even).
+uint16_t to_binary16(double x);
+uint16_t to_bfloat16(double x);
 
 // Validate the geometry and build every host table.  Returns MOFF_OK or the
 // status describing the first problem; `why` gets a human-readable reason.

@@ -34,6 +34,8 @@ IN_C64 = 0
 IN_CI4 = 1
 AUTOCORR_NONE = 2
 NORM_PAIRS = 4
+MFMA_F16 = 8
+MFMA_BF16 = 16
 
 
 @dataclasses.dataclass

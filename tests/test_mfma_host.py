@@ -1,0 +1,132 @@
+"""Host-side checks of the reduced-precision (matrix-core) path's tables:
+plan validation, the gather program over non-empty aperture cells replayed on
+the CPU against the oracle's gridded field, and the 16-bit phase-factor operands
+against their definition, correctly rounded."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+MFMA = {"f16": synth.MFMA_F16, "bf16": synth.MFMA_BF16}
+
+
+@pytest.fixture(scope="module")
+def moff():
+    import paper_1510_08318_amd as m
+    m._lib.lib()
+    return m
+
+
+def _case(name):
+    rng = np.random.default_rng(9)
+    if name == "config2_n128":
+        return synth.make_config(2, n_time=2, n_chan=1)
+    if name == "config2_n64":
+        return synth.make_config(2, n_time=2, n_chan=1, grid_n=64)
+    if name == "hetero_n64":
+        return synth.random_case(6, 40, 64, 1, 2, [synth.random_kernel(rng, 3), synth.random_kernel(rng, 5)],
+                                 extent_m=40.0, cell_m=1.5)
+    return synth.make_config(5, n_time=1, n_chan=1, grid_n=128)
+
+
+def test_plan_validation(moff):
+    w = synth.make_config(1, n_time=2)       # grid_n 32
+    with pytest.raises(moff.MoffError) as ei:
+        moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16)
+    assert ei.value.status == 4               # MOFF_ERR_UNSUPPORTED: only grid_n 64 and 128
+    w = synth.make_config(2, n_time=2, n_chan=1)
+    with pytest.raises(moff.MoffError) as ei:
+        moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16 | synth.MFMA_BF16)
+    assert ei.value.status == 1               # MOFF_ERR_INVALID_ARG: both precisions
+    with moff.Plan.from_geometry(w.geom, device=-1) as p:
+        with pytest.raises(moff.MoffError) as ei:
+            p.mfma_tables()
+        assert ei.value.status == 4
+
+
+@pytest.mark.parametrize("name", ["config2_n128", "config2_n64", "hetero_n64", "config5_n128"])
+def test_mfma_gather_program_replays_oracle_grid(moff, name):
+    w = _case(name)
+    P = oracle.plan(w.geom)
+    N, L = P["N"], P["L"]
+    e = oracle.calibrated_field(w.E, w.gains, w.geom.flags, 0)[0]
+    Eg = oracle.grid_field(e[None], P)[0]
+    taps = np.concatenate([np.asarray(K, np.complex64).ravel() for K in P["kernels"]]).astype(np.complex128)
+    with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16) as p:
+        prog, _, info = p.mfma_tables()
+    pitch = info["row_pitch"]
+    assert info["n_threads"] == N // 32 * 64 and pitch == 2 * L + 8
+    x = prog[..., 0].astype(np.int64)
+    y = prog[..., 1].astype(np.int64)
+    ant, tap, st = x & 0xFFF, (x >> 12) & 0x7FF, (x >> 31) & 1
+    assert ant.max() <= w.geom.n_ant and tap.max() < len(taps)
+    ev = np.concatenate([e, [0.0]])
+    G = np.zeros(L * pitch, complex)
+    stored = np.zeros(L * pitch, int)
+    acc = np.zeros(prog.shape[1], complex)
+    for k in range(prog.shape[0]):
+        acc = acc + ev[ant[k]] * taps[tap[k]]
+        s = st[k] == 1
+        assert (y[k][s] + L < L * pitch).all()
+        G[y[k][s]] = acc[s]
+        stored[y[k][s]] += 1
+        acc[s] = 0
+    # every lane ends on a stored cell (no partial sum is dropped)
+    assert np.all(np.abs(acc) == 0)
+    slot = np.arange(L)[:, None] * pitch + np.arange(L)[None, :]
+    nonempty = np.zeros((L, L), bool)
+    for a in range(w.geom.n_ant):
+        k = P["kernels"][P["ant_ktype"][a]].shape[0]
+        nonempty[P["iy0"][a]:P["iy0"][a] + k, P["ix0"][a]:P["ix0"][a] + k] = True
+    assert (stored[slot] == nonempty.astype(int)).all() and stored.sum() == nonempty.sum()
+    assert np.max(np.abs(G[slot] - Eg)) <= 1e-6 * max(1.0, np.abs(Eg).max())
+
+
+def _phase(j, n, N):
+    """exp(+2 pi i j (n - N/2) / N), exact on the quarter turns."""
+    m = np.mod(j * (n - N // 2), N)
+    c, s = np.cos(2 * np.pi * m / N), np.sin(2 * np.pi * m / N)
+    q = (4 * m) % N == 0
+    c = np.where(q, np.round(c), c)
+    s = np.where(q, np.round(s), s)
+    return c + 1j * s
+
+
+def _expected_operands(N):
+    """float64 [2, N/32, N/16, 2, 64, 8] operand values by their definition."""
+    L, NW, KS = N // 2, N // 32, N // 16
+    st, wv, ks, ri, ln, i = np.meshgrid(np.arange(2), np.arange(NW), np.arange(KS), np.arange(2), np.arange(64),
+                                        np.arange(8), indexing="ij")
+    kk = 16 * ks + 8 * (ln // 32) + i
+    n = 32 * wv + ln % 32
+    f = _phase(kk % L, n, N) * np.where(st == 0, 1.0 / L, 1.0)
+    upper = kk >= L
+    return np.where(ri == 0, np.where(upper, -f.imag, f.real), np.where(upper, f.real, f.imag))
+
+
+def _bf16_decode(bits):
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("N", [64, 128])
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_mfma_phase_operands_correctly_rounded(moff, N, prec):
+    w = synth.make_config(2, n_time=2, n_chan=1, grid_n=N)
+    with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=MFMA[prec]) as p:
+        _, dft, _ = p.mfma_tables()
+    exact = _expected_operands(N)
+    assert dft.shape == exact.shape
+    if prec == "f16":
+        # numpy rounds float64 -> binary16 to nearest even in one step
+        want = exact.astype(np.float16).view(np.uint16)
+        zero = exact == 0
+        assert np.array_equal(dft[~zero], want[~zero])
+        assert np.all((dft[zero] & 0x7FFF) == 0)
+    else:
+        got = _bf16_decode(dft)
+        ax = np.abs(exact)
+        e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+        half_ulp = np.where(ax > 0, 2.0 ** (e - 8), 0.0)
+        assert np.all(np.abs(got - exact) <= half_ulp)
+        assert np.all(np.sign(got) * np.sign(exact) >= 0)
