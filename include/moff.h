@@ -175,20 +175,23 @@ moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w,
 /*
  * Tables of the reduced-precision (MOFF_MFMA_*) path, for host-side tests.
  * Sizes first (any pointer may be NULL): prog_len entries per thread,
- * n_threads threads, row_pitch 16-bit elements per LDS row, dft_len 16-bit
- * words of phase-factor operands.
+ * n_threads threads, row_pitch 16-bit elements per grid row, grid_base the
+ * LDS byte offset of the 16-bit aperture grid, dft_len 16-bit words of
+ * phase-factor operands.
  *   prog : uint32 [prog_len][n_threads][2] gather entries (x, y) over the
- *          non-empty aperture cells (iy, ix): x bits 0..11 antenna slot (n_ant =
- *          the zero slot), bits 12..22 kernel tap (all types back to back), bit 31
- *          "cell complete: store"; y = iy * row_pitch + ix, the LDS index of the
- *          cell's real part (its imaginary part is at y + grid_n / 2).
+ *          non-empty aperture cells (iy, ix), in LDS byte offsets: x low half =
+ *          8 * antenna (8 * n_ant is an all-zero slot), x high half =
+ *          8 * (n_ant + 1 + tap) (kernel taps of all types back to back);
+ *          y = 0, or on the last entry of a cell y = grid_base +
+ *          2 * (iy * row_pitch + ix), where the cell's real part is stored (its
+ *          imaginary part is grid_n / 2 elements further on).
  *   dft  : uint16 [2][grid_n / 32][grid_n / 16][2][64][8] binary16 or bfloat16
- *          bit patterns, indexed [stage][wave][k-step][re/im][lane][slot]:
+ *          bit patterns, indexed [stage][block][k-step][re/im][lane][slot]:
  *          stage 0 = row transform, exp(+2 pi i ix (q - N/2) / N) / (N/2) at
- *          column q = 32 wave + lane % 32 and contraction index
+ *          column q = 32 block + lane % 32 and contraction index
  *          kk = 16 k-step + 8 (lane / 32) + slot (kk < N/2: real-part rows,
  *          ix = kk; else imaginary-part rows, ix = kk - N/2); stage 1 = column
- *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 wave + lane % 32
+ *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 block + lane % 32
  *          and iy from kk likewise.  With w the phase factor at (kk mod N/2):
  *          re/im = 0 holds Re w for kk < N/2 and -Im w above; re/im = 1 holds
  *          Im w below and Re w above, so that [Re x | Im x] times the two blocks
@@ -196,7 +199,7 @@ moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w,
  * MOFF_ERR_UNSUPPORTED if the plan has no MFMA flag.
  */
 moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft, int32_t* prog_len,
-                                  int32_t* n_threads, int32_t* row_pitch, int32_t* dft_len);
+                                  int32_t* n_threads, int32_t* row_pitch, int32_t* grid_base, int32_t* dft_len);
 
 /*
  * Launch configuration of the fused path.  The frame transform has one or two

@@ -56,7 +56,8 @@ SIGNATURES = {
     "moff_plan_power_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, c_f64p]),
     "moff_plan_gather_program": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, c_u32p, c_f32p,
                                                 c_i32p, c_i32p, c_i32p, c_i32p, c_i32p]),
-    "moff_plan_mfma_tables": (ctypes.c_int, [ctypes.c_void_p, c_u32p, c_u16p, c_i32p, c_i32p, c_i32p, c_i32p]),
+    "moff_plan_mfma_tables": (ctypes.c_int, [ctypes.c_void_p, c_u32p, c_u16p, c_i32p, c_i32p, c_i32p, c_i32p,
+                                             c_i32p]),
     "moff_plan_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                           ctypes.c_void_p]),
     "moff_plan_set_config": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
@@ -157,8 +158,8 @@ def moff_plan_gather_program(plan, variant, w, out, weights, prog_len, n_threads
           n_weights)
 
 
-def moff_plan_mfma_tables(plan, prog, dft, prog_len, n_threads, row_pitch, dft_len):
-    _call("moff_plan_mfma_tables", plan, prog, dft, prog_len, n_threads, row_pitch, dft_len)
+def moff_plan_mfma_tables(plan, prog, dft, prog_len, n_threads, row_pitch, grid_base, dft_len):
+    _call("moff_plan_mfma_tables", plan, prog, dft, prog_len, n_threads, row_pitch, grid_base, dft_len)
 
 
 def moff_plan_autotune(plan, E, n_time, gains, stream):

@@ -477,13 +477,14 @@ moff_status moff_plan_gather_program(moff_plan p, int32_t variant, int32_t w, ui
 }
 
 moff_status moff_plan_mfma_tables(moff_plan p, uint32_t* prog, uint16_t* dft, int32_t* prog_len, int32_t* n_threads,
-                                  int32_t* row_pitch, int32_t* dft_len) {
+                                  int32_t* row_pitch, int32_t* grid_base, int32_t* dft_len) {
   if (!p) return MOFF_ERR_INVALID_ARG;
   const HostPlan::Mfma& T = p->hp.mfma;
   if (!T.prec) return MOFF_ERR_UNSUPPORTED;
   if (prog_len) *prog_len = T.prog_len;
   if (n_threads) *n_threads = T.NT;
   if (row_pitch) *row_pitch = T.pitch;
+  if (grid_base) *grid_base = T.grid_base;
   if (dft_len) *dft_len = static_cast<int32_t>(T.dft.size());
   if (prog)
     for (size_t i = 0; i < T.prog.size(); ++i) {

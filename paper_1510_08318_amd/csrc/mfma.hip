@@ -16,18 +16,21 @@
 // between the stages, W and V once from float64 phase factors); every product
 // accumulates in float32 (v_mfma_f32_32x32x16_{f16,bf16}).
 //
-// One workgroup of N/32 waves owns one (channel, time slice) and loops over its
-// frames; per frame:
+// One workgroup (2 waves at N = 64, 8 at N = 128) owns one (channel, time
+// slice) and loops over its frames; per frame:
 //   1. ingest + calibration: e = g E into LDS (float32), self power in float64
 //      (the next frame's samples are loaded during this frame's matrix work);
 //   2. gather-gridding: each lane walks its balanced slice of the cell-keyed
 //      program (no atomics) and stores finished cells as 16-bit values;
-//   3. row stage: wave w computes Z for columns 32w .. 32w+31 with its W
-//      operands held in registers for the whole launch, Eg read from LDS;
-//      Z is written to LDS transposed (column-major), the layout the column
-//      stage reads;
-//   4. column stage: wave w computes Y for rows 32w .. 32w+31 with its V
-//      operands in registers and accumulates |Y|^2 in registers.
+//   3. row stage: each wave owns a 32-column block of Z (and part of its
+//      rows), with that block's W operands held in registers for the whole
+//      launch and Eg read from LDS; Z is written to LDS transposed
+//      (column-major), the layout the column stage reads;
+//   4. column stage: the same wave owns the same-numbered 32-row block of Y
+//      (and part of its columns), with that block's V operands in registers,
+//      and accumulates |Y|^2 in registers.
+// Two waves per SIMD (8-wave workgroups at N = 128) let one wave's matrix
+// work overlap another's vector and LDS work.
 // After the last frame the accumulators go through the same epilogue modes as
 // the float32 fused kernel (per-slice partial, running sum, final image).
 //
@@ -71,11 +74,14 @@ __device__ __forceinline__ f32x16 mfma32<__bf16>(Vec<__bf16>::v8 a, Vec<__bf16>:
 template <int N>
 struct MfmaShape {
   static constexpr int L = N / 2;
-  static constexpr int NW = N / 32;        // waves per workgroup
+  static constexpr int NW = mfma_waves(N); // waves per workgroup
   static constexpr int NT = NW * 64;
   static constexpr int KS = L / 8;         // 16-deep steps over the doubled contraction 2L
-  static constexpr int RB = L / 32;        // 32-row blocks of the row stage
-  static constexpr int CB = N / 32;        // 32-column blocks of the column stage
+  static constexpr int NB = N / 32;        // output blocks: row-stage column blocks = column-stage row blocks
+  static constexpr int WPB = NW / NB;      // waves sharing one output block
+  static constexpr int RBW = L / 32 / WPB; // row stage: 32-row blocks per wave
+  static constexpr int CBW = NB / WPB;     // column stage: 32-column blocks per wave
+  static_assert(NW % NB == 0 && RBW >= 1 && CBW >= 1, "wave split must tile both stages");
   static constexpr int PITCH = 2 * L + 8;  // LDS row length, 16-bit elements
   static constexpr int EG = L * PITCH;     // Eg [L][PITCH]: real parts at ix, imaginary at L + ix
   static constexpr int ZT = N * PITCH;     // Zt [N][PITCH]: Zt[q][iy] = Re Z, Zt[q][L + iy] = Im Z
@@ -83,20 +89,10 @@ struct MfmaShape {
 
 }  // namespace
 
-namespace {
-
-__host__ __device__ inline size_t mfma_tables_bytes(int N, int n_taps, int n_ant) {
-  const int L = N / 2, pitch = 2 * L + 8;
-  const size_t b = sizeof(uint16_t) * static_cast<size_t>(L + N) * pitch + sizeof(float2) * (n_taps + 2 * n_ant + 1) +
-                   sizeof(int) * n_ant;
-  return (b + 15) & ~size_t(15);
-}
-
-}  // namespace
-
 size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds) {
-  const size_t prog = prog_in_lds ? sizeof(GatherEntry) * static_cast<size_t>(prog_len) * (N / 32 * 64) : 0;
-  return mfma_tables_bytes(N, n_taps, n_ant) + prog;
+  const MfmaLayout m = mfma_layout(N, n_taps, n_ant);
+  const size_t prog = prog_in_lds ? sizeof(GatherEntry) * static_cast<size_t>(prog_len) * (mfma_waves(N) * 64) : 0;
+  return static_cast<size_t>(m.prog) + prog;
 }
 
 bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len) {
@@ -104,24 +100,29 @@ bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len) {
 }
 
 template <int N, class H, bool CI4>
-__global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
+__global__ __launch_bounds__((MfmaShape<N>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
+void mfma_kernel(MfmaArgs a) {
   using S = MfmaShape<N>;
   using V8 = typename Vec<H>::v8;
   using V4 = typename Vec<H>::v4;
   constexpr int NT = S::NT, L = S::L, KS = S::KS, PITCH = S::PITCH;
   extern __shared__ uint4 lds_mfma[];
   __shared__ double Atot[kMaxTypesDev];
-  H* Eg = reinterpret_cast<H*>(lds_mfma);
-  H* Zt = Eg + S::EG;
-  float2* K = reinterpret_cast<float2*>(Zt + S::ZT);   // [n_taps]
-  float2* gl = K + a.n_taps;                            // [n_ant]
-  float2* e = gl + a.n_ant;                             // [n_ant + 1], last slot stays zero
-  int* ty = reinterpret_cast<int*>(e + a.n_ant + 1);    // [n_ant]
+  char* lds = reinterpret_cast<char*>(lds_mfma);
+  const MfmaLayout lay = mfma_layout(N, a.n_taps, a.n_ant);
+  float2* e = reinterpret_cast<float2*>(lds + lay.e);   // [n_ant + 1], last slot stays zero
+  float2* K = reinterpret_cast<float2*>(lds + lay.k);   // [n_taps]
+  H* Eg = reinterpret_cast<H*>(lds + lay.eg);
+  H* Zt = reinterpret_cast<H*>(lds + lay.zt);
+  float2* gl = reinterpret_cast<float2*>(lds + lay.gl); // [n_ant]
+  int* ty = reinterpret_cast<int*>(lds + lay.ty);       // [n_ant]
   // gather program [prog_len][NT], copied into LDS when it fits
-  GatherEntry* lprog = reinterpret_cast<GatherEntry*>(reinterpret_cast<char*>(lds_mfma) +
-                                                      mfma_tables_bytes(N, a.n_taps, a.n_ant));
+  GatherEntry* lprog = reinterpret_cast<GatherEntry*>(lds + lay.prog);
 
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  // wave w owns output block blk (its row-stage columns and column-stage rows)
+  // and part sub of that block's other dimension
+  const int blk = w / S::WPB, sub = w % S::WPB;
   const int item = blockIdx.x;
   if (item >= a.n_chan * a.slices) return;
   const int c = item % a.n_chan;
@@ -133,15 +134,15 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
     const V8* src = reinterpret_cast<const V8*>(a.dft);
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
-      w_re[ks] = src[(((0 * S::NW + w) * KS + ks) * 2 + 0) * 64 + lane];
-      w_im[ks] = src[(((0 * S::NW + w) * KS + ks) * 2 + 1) * 64 + lane];
-      v_re[ks] = src[(((1 * S::NW + w) * KS + ks) * 2 + 0) * 64 + lane];
-      v_im[ks] = src[(((1 * S::NW + w) * KS + ks) * 2 + 1) * 64 + lane];
+      w_re[ks] = src[(((0 * S::NB + blk) * KS + ks) * 2 + 0) * 64 + lane];
+      w_im[ks] = src[(((0 * S::NB + blk) * KS + ks) * 2 + 1) * 64 + lane];
+      v_re[ks] = src[(((1 * S::NB + blk) * KS + ks) * 2 + 0) * 64 + lane];
+      v_im[ks] = src[(((1 * S::NB + blk) * KS + ks) * 2 + 1) * 64 + lane];
     }
   }
 
   // clear the aperture grid once: cells without antennas are never written
-  for (int i = tid; i < S::EG * 2 / 16; i += NT) lds_mfma[i] = make_uint4(0u, 0u, 0u, 0u);
+  for (int i = tid; i < S::EG * 2 / 16; i += NT) reinterpret_cast<uint4*>(Eg)[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < a.n_taps; i += NT) K[i] = a.ktab[i];
   for (int i = tid; i < a.n_ant; i += NT) {
     ty[i] = a.ant_type[i];
@@ -158,9 +159,18 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
 
   // Raw samples of the next frame are loaded into registers before the row
   // stage and used after the column stage, so the HBM latency is hidden behind
-  // the matrix work; antennas beyond kPrefetch * NT are loaded when used.
-  constexpr int kPrefetch = 4;
-  float2 raw[kPrefetch];
+  // the matrix work.  The first kPrefetch * NT antennas keep their gain and
+  // their float64 self power in registers (one slot each); antennas beyond
+  // that are loaded, calibrated and typed through LDS when used.
+  constexpr int kPrefetch = N == 128 ? 2 : 4;
+  float2 raw[kPrefetch], gs[kPrefetch];
+  double pws[kPrefetch];
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int i = tid + j * NT;
+    gs[j] = (a.gains && i < a.n_ant) ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+    pws[j] = 0.0;
+  }
   auto load_raw = [&](int64_t t) {
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
 #pragma unroll
@@ -182,15 +192,19 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
 #pragma unroll
     for (int j = 0; j < kPrefetch; ++j) {
       const int i = tid + j * NT;
-      if (i < a.n_ant) calibrate(i, raw[j]);
+      if (i < a.n_ant) {
+        const float2 v = c_mul(gs[j], raw[j]);
+        e[i] = v;
+        pws[j] += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+      }
     }
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
     for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) calibrate(i, load_sample(a.E, base + i, CI4));
   };
 
-  float acc[S::CB][16];
+  float acc[S::CBW][16];
 #pragma unroll
-  for (int cb = 0; cb < S::CB; ++cb)
+  for (int cb = 0; cb < S::CBW; ++cb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[cb][j] = 0.f;
   const int row = lane & 31, half = lane >> 5;
@@ -205,14 +219,17 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
     // 2. gather-gridding into 16-bit cells
     {
       float2 g = make_float2(0.f, 0.f);
+      // entry: x = byte offsets of e[ant] (low half) and K[tap] (high half),
+      // y = byte address of the finished cell's real part, or 0
       auto step = [&](GatherEntry en) {
-        const float2 ev = e[en.x & 0xFFFu];
-        const float2 kv = K[(en.x >> 12) & 0x7FFu];
+        const float2 ev = *reinterpret_cast<const float2*>(lds + (en.x & 0xFFFFu));
+        const float2 kv = *reinterpret_cast<const float2*>(lds + (en.x >> 16));
         g.x = fmaf(ev.x, kv.x, fmaf(-ev.y, kv.y, g.x));
         g.y = fmaf(ev.x, kv.y, fmaf(ev.y, kv.x, g.y));
-        if (en.x & kStoreBit) {
-          Eg[en.y] = static_cast<H>(g.x);
-          Eg[en.y + L] = static_cast<H>(g.y);
+        if (en.y != 0u) {
+          H* cell = reinterpret_cast<H*>(lds + en.y);
+          cell[0] = static_cast<H>(g.x);
+          cell[L] = static_cast<H>(g.y);
           g = make_float2(0.f, 0.f);
         }
       };
@@ -229,9 +246,10 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
     __syncthreads();
     if (t + 1 < t1) load_raw(t + 1);
 
-    // 3. row stage: Z = Eg W for this wave's 32 output columns
+    // 3. row stage: Z = Eg W for the 32 output columns of block blk
 #pragma unroll
-    for (int rb = 0; rb < S::RB; ++rb) {
+    for (int i_rb = 0; i_rb < S::RBW; ++i_rb) {
+      const int rb = sub * S::RBW + i_rb;
       f32x16 zr = {}, zi = {};
       const H* arow = Eg + (32 * rb + row) * PITCH + 8 * half;
 #pragma unroll
@@ -240,8 +258,8 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
         zr = mfma32<H>(av, w_re[ks], zr);
         zi = mfma32<H>(av, w_im[ks], zi);
       }
-      // lane holds rows iy = 32 rb + 8 g + 4 half + (0..3) of column q = 32 w + row
-      H* zcol = Zt + (32 * w + row) * PITCH + 32 * rb + 4 * half;
+      // lane holds rows iy = 32 rb + 8 g + 4 half + (0..3) of column q = 32 blk + row
+      H* zcol = Zt + (32 * blk + row) * PITCH + 32 * rb + 4 * half;
 #pragma unroll
       for (int g = 0; g < 4; ++g) {
         V4 vr, vi;
@@ -256,9 +274,10 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
     }
     __syncthreads();
 
-    // 4. column stage: Y = V Z for this wave's 32 output rows, |Y|^2 accumulated
+    // 4. column stage: Y = V Z for the 32 output rows of block blk, |Y|^2 accumulated
 #pragma unroll
-    for (int cb = 0; cb < S::CB; ++cb) {
+    for (int i_cb = 0; i_cb < S::CBW; ++i_cb) {
+      const int cb = sub * S::CBW + i_cb;
       f32x16 yr = {}, yi = {};
       const H* bcol = Zt + (32 * cb + row) * PITCH + 8 * half;
 #pragma unroll
@@ -268,23 +287,32 @@ __global__ __launch_bounds__((MfmaShape<N>::NT)) void mfma_kernel(MfmaArgs a) {
         yi = mfma32<H>(v_im[ks], bv, yi);
       }
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc[cb][j] = fmaf(yr[j], yr[j], fmaf(yi[j], yi[j], acc[cb][j]));
+      for (int j = 0; j < 16; ++j) acc[i_cb][j] = fmaf(yr[j], yr[j], fmaf(yi[j], yi[j], acc[i_cb][j]));
     }
   }
 
+#pragma unroll
+  for (int j = 0; j < kPrefetch; ++j) {
+    const int i = tid + j * NT;
+    if (i < a.n_ant) {
+      const int tp = ty[i];
+#pragma unroll
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? pws[j] : 0.0;
+    }
+  }
   block_sum4<NT>(pw, Atot);
 
   // epilogue: the row stage carried a factor 1 / L, so |Y|^2 is scaled back by L^2 (exact)
   const size_t img_stride = static_cast<size_t>(N) * N;
   constexpr float kBack = static_cast<float>(L) * static_cast<float>(L);
 #pragma unroll
-  for (int cb = 0; cb < S::CB; ++cb)
+  for (int i_cb = 0; i_cb < S::CBW; ++i_cb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const int r = 32 * w + 8 * (j / 4) + 4 * half + (j % 4);
-      const int q = 32 * cb + row;
+      const int r = 32 * blk + 8 * (j / 4) + 4 * half + (j % 4);
+      const int q = 32 * (sub * S::CBW + i_cb) + row;
       const size_t pix = static_cast<size_t>(r) * N + q;
-      const float s = acc[cb][j] * kBack;
+      const float s = acc[i_cb][j] * kBack;
       if (a.mode == kModePartial) {
         a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = s;
       } else if (a.mode == kModeAccum) {

@@ -81,11 +81,11 @@ long long balanced_split(const std::vector<int>& cost, int lanes) {
 // power of two, so that its rounded output cannot exceed the largest gridded
 // value; the kernel multiplies |Y|^2 back by (N/2)^2 exactly.
 moff_status build_mfma_tables(HostPlan& P, std::string* why) {
-  const int N = P.N, L = P.L, NW = N / 32, KS = L / 8;
+  const int N = P.N, L = P.L, NB = N / 32, KS = L / 8;
   HostPlan::Mfma& T = P.mfma;
   T.prec = (P.flags & MOFF_MFMA_BF16) ? 2 : 1;
-  T.NT = NW * 64;
-  T.pitch = 2 * L + 8;
+  T.NT = mfma_waves(N) * 64;
+  T.pitch = mfma_layout(N, P.n_taps, P.n_ant).pitch;
   std::vector<int> cells, cost;
   for (int i = 0; i < L * L; ++i) {
     const int n = P.csr_ptr[i + 1] - P.csr_ptr[i];
@@ -96,10 +96,17 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
   }
   const long long B = balanced_split(cost, T.NT);
   if (B > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
-  if (P.n_taps >= 2048) return fail(why, MOFF_ERR_UNSUPPORTED, "too many kernel taps for the gather encoding");
+  if (mfma_layout(N, P.n_taps, P.n_ant).eg > 0xFFFF)
+    return fail(why, MOFF_ERR_UNSUPPORTED, "too many antennas and taps for the gather encoding");
   T.prog_len = static_cast<int>(B);
-  const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
-  T.prog.assign(static_cast<size_t>(T.prog_len) * T.NT, GatherEntry{zero_slot, 0});
+  const MfmaLayout lay = mfma_layout(N, P.n_taps, P.n_ant);
+  T.grid_base = lay.eg;
+  // entry: x = byte offset of e[ant] | byte offset of K[tap] << 16; y = byte
+  // address of the cell's real part on the last entry of a cell, else 0
+  auto xword = [&](int ant, int tap) {
+    return static_cast<uint32_t>(lay.e + 8 * ant) | (static_cast<uint32_t>(lay.k + 8 * tap) << 16);
+  };
+  T.prog.assign(static_cast<size_t>(T.prog_len) * T.NT, GatherEntry{xword(P.n_ant, 0), 0});
   int lane = 0, k = 0;
   long long cur = 0;
   for (size_t ci = 0; ci < cells.size(); ++ci) {
@@ -110,20 +117,18 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
     }
     cur += cost[ci];
     const int iy = cells[ci] / L, ix = cells[ci] % L;
-    const uint32_t dst = static_cast<uint32_t>(iy * T.pitch + ix);
     for (int e = P.csr_ptr[cells[ci]]; e < P.csr_ptr[cells[ci] + 1]; ++e) {
-      T.prog[static_cast<size_t>(k) * T.NT + lane] =
-          GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (static_cast<uint32_t>(P.csr_tap[e]) << 12), dst};
+      T.prog[static_cast<size_t>(k) * T.NT + lane] = GatherEntry{xword(P.csr_ant[e], P.csr_tap[e]), 0};
       ++k;
     }
-    T.prog[static_cast<size_t>(k - 1) * T.NT + lane].x |= kStoreBit;
+    T.prog[static_cast<size_t>(k - 1) * T.NT + lane].y = static_cast<uint32_t>(lay.eg + 2 * (iy * T.pitch + ix));
   }
 
   auto enc = [&](double v) { return T.prec == 2 ? to_bfloat16(v) : to_binary16(v); };
-  T.dft.assign(static_cast<size_t>(2) * NW * KS * 2 * 64 * 8, 0);
+  T.dft.assign(static_cast<size_t>(2) * NB * KS * 2 * 64 * 8, 0);
   const double s1 = 1.0 / L;
   for (int st = 0; st < 2; ++st)
-    for (int w = 0; w < NW; ++w)
+    for (int w = 0; w < NB; ++w)
       for (int ks = 0; ks < KS; ++ks)
         for (int ri = 0; ri < 2; ++ri)
           for (int ln = 0; ln < 64; ++ln)
@@ -135,7 +140,7 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
               std::complex<double> f = unit_root(static_cast<long long>(j) * (n - N / 2), N);
               if (st == 0) f *= s1;
               const double v = ri == 0 ? (upper ? -f.imag() : f.real()) : (upper ? f.real() : f.imag());
-              T.dft[((((static_cast<size_t>(st) * NW + w) * KS + ks) * 2 + ri) * 64 + ln) * 8 + i] = enc(v);
+              T.dft[((((static_cast<size_t>(st) * NB + w) * KS + ks) * 2 + ri) * 64 + ln) * 8 + i] = enc(v);
             }
   return MOFF_OK;
 }

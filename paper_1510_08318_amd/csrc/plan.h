@@ -69,8 +69,8 @@ struct HostPlan {
   // matrix cores; see mfma.hip for the operand layout
   struct Mfma {
     int prec = 0;                            // 0: off, 1: binary16, 2: bfloat16
-    int NT = 0, pitch = 0, prog_len = 0;
-    std::vector<GatherEntry> prog;           // [prog_len][NT]; y = iy * pitch + ix
+    int NT = 0, pitch = 0, prog_len = 0, grid_base = 0;
+    std::vector<GatherEntry> prog;           // [prog_len][NT]; LDS byte offsets (mfma_layout)
     std::vector<uint16_t> dft;               // [2][N/32][N/16][2][64][8] operand bit patterns
   } mfma;
 };

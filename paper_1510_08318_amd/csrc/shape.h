@@ -35,4 +35,33 @@ constexpr FrameShape frame_shape(int N, int V = 0) {
                   : FrameShape{};
 }
 
+// Waves per workgroup of the reduced-precision (matrix-core) frame transform.
+constexpr int mfma_waves(int N) { return N == 128 ? 8 : 2; }
+
+// Dynamic-LDS layout of the reduced-precision kernel, byte offsets.  The
+// calibrated samples e[n_ant + 1] (last slot zero) and the kernel taps come
+// first so that gather entries can address them with 16-bit byte offsets; the
+// 16-bit grid Eg [N/2][pitch] and the transposed row-stage output Zt [N][pitch]
+// follow, then per-antenna gains and types, then (optionally) the program.
+struct MfmaLayout {
+  int pitch;   // 16-bit elements per Eg / Zt row
+  int e, k, eg, zt, gl, ty, prog;
+};
+
+constexpr int align_up(int x, int a) { return (x + a - 1) / a * a; }
+
+constexpr MfmaLayout mfma_layout(int N, int n_taps, int n_ant) {
+  const int L = N / 2, pitch = 2 * L + 8;
+  MfmaLayout m{};
+  m.pitch = pitch;
+  m.e = 0;
+  m.k = 8 * (n_ant + 1);
+  m.eg = align_up(m.k + 8 * n_taps, 16);
+  m.zt = m.eg + 2 * L * pitch;
+  m.gl = m.zt + 2 * N * pitch;
+  m.ty = m.gl + 8 * n_ant;
+  m.prog = align_up(m.ty + 4 * n_ant, 16);
+  return m;
+}
+
 }  // namespace moff

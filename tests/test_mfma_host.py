@@ -55,22 +55,27 @@ def test_mfma_gather_program_replays_oracle_grid(moff, name):
     taps = np.concatenate([np.asarray(K, np.complex64).ravel() for K in P["kernels"]]).astype(np.complex128)
     with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16) as p:
         prog, _, info = p.mfma_tables()
-    pitch = info["row_pitch"]
-    assert info["n_threads"] == N // 32 * 64 and pitch == 2 * L + 8
+    pitch, base, na = info["row_pitch"], info["grid_base"], w.geom.n_ant
+    assert info["n_threads"] == (512 if N == 128 else 128) and pitch == 2 * L + 8
+    assert base % 16 == 0 and base >= 8 * (na + 1 + len(taps))
     x = prog[..., 0].astype(np.int64)
     y = prog[..., 1].astype(np.int64)
-    ant, tap, st = x & 0xFFF, (x >> 12) & 0x7FF, (x >> 31) & 1
-    assert ant.max() <= w.geom.n_ant and tap.max() < len(taps)
+    eoff, koff = x & 0xFFFF, x >> 16
+    assert (eoff % 8 == 0).all() and (koff % 8 == 0).all()
+    ant, tap = eoff // 8, koff // 8 - (na + 1)
+    st = y != 0
+    assert ant.max() <= na and tap.min() >= 0 and tap.max() < len(taps)
+    slot = (y - base) // 2
+    assert ((y[st] - base) % 2 == 0).all() and (slot[st] >= 0).all() and (slot[st] + L < L * pitch).all()
     ev = np.concatenate([e, [0.0]])
     G = np.zeros(L * pitch, complex)
     stored = np.zeros(L * pitch, int)
     acc = np.zeros(prog.shape[1], complex)
     for k in range(prog.shape[0]):
         acc = acc + ev[ant[k]] * taps[tap[k]]
-        s = st[k] == 1
-        assert (y[k][s] + L < L * pitch).all()
-        G[y[k][s]] = acc[s]
-        stored[y[k][s]] += 1
+        s = st[k]
+        G[slot[k][s]] = acc[s]
+        stored[slot[k][s]] += 1
         acc[s] = 0
     # every lane ends on a stored cell (no partial sum is dropped)
     assert np.all(np.abs(acc) == 0)
