@@ -28,6 +28,67 @@ sys.path.insert(0, ROOT)
 PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (spec sheet)
 PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec sheet)
 
+# HBM traffic per launch of the timed kernel, measured with rocprofv3 --pmc
+# FETCH_SIZE and, in a second run, WRITE_SIZE on this script (KiB per dispatch;
+# profiles/fused_kernel_lwa_n128.md, profiles/mfma_kernel_lwa_f16_n128.md).
+# Scaled by what the same counters read for one 256 MiB device copy in the same
+# runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
+# precision, shape variant, workgroups); valid only for the library sources they
+# were measured on, identified by TRAFFIC_SOURCES_SHA.
+TRAFFIC_SOURCES_SHA = "42d4ed4f334574fe"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
+TRAFFIC_KIB = {
+    (2, "f32", 0, 256): (32949, 16384),
+    (2, "f32", 0, 512): (32404, 32776),
+    (2, "f32", 0, 768): (32405, 49164),
+    (2, "f32", 0, 1024): (32414, 65552),
+    (2, "f32", 0, 1536): (32412, 98328),
+    (2, "f32", 0, 2048): (32408, 131104),
+    (2, "f32", 0, 2304): (32407, 147492),
+    (2, "f32", 0, 3072): (32406, 196656),
+    (2, "f32", 0, 4096): (32406, 262208),
+    (2, "f32", 0, 8192): (32406, 524416),
+    (2, "f32", 0, 16384): (32407, 1048832),
+    (2, "f32", 1, 128): (17171, 8192),
+    (2, "f32", 1, 256): (16594, 16393),
+    (2, "f32", 1, 512): (16594, 32785),
+    (2, "f32", 1, 1024): (16610, 65569),
+    (2, "f32", 1, 1536): (16608, 98352),
+    (2, "f32", 1, 2048): (16594, 131136),
+    (2, "f32", 1, 4096): (16611, 262272),
+    (2, "f32", 1, 8192): (16605, 524544),
+    (4, "f16", 0, 128): (129421, 8192),
+    (4, "f16", 0, 256): (128930, 16393),
+    (4, "f16", 0, 512): (129436, 32785),
+    (4, "f16", 0, 768): (130010, 49177),
+    (4, "f16", 0, 1024): (130595, 65568),
+    (4, "f16", 0, 2048): (131529, 131136),
+    (4, "f16", 0, 4096): (130004, 262272),
+    (4, "f16", 0, 8192): (129871, 524544),
+}
+
+
+def library_sources_sha():
+    import glob
+    import hashlib
+    m = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1510_08318_amd", "csrc", "*"))):
+        m.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            m.update(fh.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(config, prec, launch, default_grid):
+    """HBM bytes per launch from the recorded counters, or None when this
+    launch or these sources were not profiled."""
+    if not default_grid or library_sources_sha() != TRAFFIC_SOURCES_SHA:
+        return None
+    kib = TRAFFIC_KIB.get((config, prec, launch["variant"], launch["grid"]))
+    if kib is None:
+        return None
+    return int(round((kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE) * 1024))
+
 
 def frame_flops(N, nnz):
     """Algorithmic work per frame: the FFT count 5 N^2 log2 N^2 for the padded
@@ -172,15 +233,18 @@ def main():
     value = frames / (ms_per_step / 1e3)
     extra = {"fused_kernel_ms": round(k_ms, 4), "frames_per_step": frames,
              "algorithmic_flops_per_frame": frame_flops(N, nnz)}
+    traffic = measured_traffic(args.config, prec, launch, args.grid == 0)
+    if traffic is not None:
+        extra["traffic_GBps"] = traffic / (k_ms / 1e3) / 1e9
     if prec == "f32":
         achieved = frame_flops(N, nnz) * frames / (k_ms / 1e3) / 1e12
         roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None}
+                    "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic}
     else:
         extra["mfma_flops_per_frame"] = mfma_frame_flops(N)
         achieved = mfma_frame_flops(N) * frames / (k_ms / 1e3) / 1e12
         roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16BIT_TFLOPS, "unit": "TFLOP/s",
-                    "frac": achieved / PEAK_MFMA_16BIT_TFLOPS, "traffic": None}
+                    "frac": achieved / PEAK_MFMA_16BIT_TFLOPS, "traffic": traffic}
         plan32 = moff.Plan.from_geometry(w.geom, device=0)
         out32 = torch.empty_like(out)
         ms32, k32, launch32 = time_plan(plan32, E, gains, out32, args.steps, args.warmup, not args.no_tune)
