@@ -23,3 +23,4 @@ from .moff import (AUTOCORR_NONE, IN_C64, IN_CI4, NORM_PAIRS, FootprintOverflow,
                    moff_channel, moff_image, plan, power_pattern, self_power)
 from .fx import fx_analytic_image, fx_discrete_image, visibilities  # noqa: F401
 from .grad import gain_gradient, image_loss  # noqa: F401
+from .uv_autocorr import uv_channel, uv_image  # noqa: F401
