@@ -71,9 +71,20 @@ enum {
                               lose relative precision.  Error against the exact image:
                               of order 2^-11 relative to the image peak (stated bound
                               16 * 2^-11 on max|dI| / max(S/T)). */
-  MOFF_MFMA_BF16 = 16      /* as MOFF_MFMA_F16 with bfloat16 (float32 range, 8-bit
+  MOFF_MFMA_BF16 = 16,     /* as MOFF_MFMA_F16 with bfloat16 (float32 range, 8-bit
                               significand; stated bound 16 * 2^-8). At most one of the
                               two MFMA flags may be set. */
+  MOFF_AUTOCORR_UV = 32    /* remove the autocorrelations with the uv-plane rule of
+                              Sec. 4.2 instead of per-antenna subtraction: the
+                              time-averaged image S / T is taken to the uv plane, the
+                              tables' autocorrelation kernel a = sum_p n_p (K_p corr K_p)
+                              (n_p antennas of type p) is subtracted at zero spacing,
+                              scaled so the result is zero there, and the result is
+                              transformed back: I = (S - beta sum_p n_p P_p) / T with
+                              beta = sum_pix S / (N^2 a[0]).  Exact when footprints never
+                              overlap and antennas have equal power; otherwise
+                              cross-correlations of overlapping footprints at zero
+                              spacing are removed too.  Not with MOFF_AUTOCORR_NONE. */
 };
 
 /*
@@ -98,8 +109,8 @@ enum {
  *                     shortest wavelength, widened if needed so that the layout
  *                     span plus the widest footprint and one cell of slack fits
  *                     in N/2 cells.
- *   flags           : MOFF_IN_* | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS |
- *                     MOFF_MFMA_F16 or MOFF_MFMA_BF16.
+ *   flags           : MOFF_IN_* | MOFF_AUTOCORR_NONE or MOFF_AUTOCORR_UV |
+ *                     MOFF_NORM_PAIRS | MOFF_MFMA_F16 or MOFF_MFMA_BF16.
  *
  * Footprint placement: antenna a with a k x k table covers cells
  * ix0_a .. ix0_a + k - 1 with ix0_a = floor(x_a / cell - (k - 1) / 2 + 0.5)
@@ -325,7 +336,9 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  *   grad_a = (2 s / T) sum_t conj(E_ta) [ sum_{taps} conj(K_a) Z_t - e_ta rho_p(a) ],
  *   Z_t = adjoint 2-D DFT of R * Y_t on the aperture cells,  rho_p = sum_pix R P_p,
  * s the pair normalisation (1 unless MOFF_NORM_PAIRS), the rho term absent under
- * MOFF_AUTOCORR_NONE.  Every frame's grid and field are recomputed in time
+ * MOFF_AUTOCORR_NONE.  Under MOFF_AUTOCORR_UV the rho term is absent and R is
+ * first shifted per channel by sum_pix R Pn / (N^2 a[0]) (the derivative of the
+ * zero-spacing rule).  Every frame's grid and field are recomputed in time
  * chunks through the plan workspace (never stored for the whole integration);
  * the sums over time are float64.
  */

@@ -13,11 +13,11 @@ import ctypes
 import numpy as np
 
 from . import _lib
-from ._lib import (MOFF_AUTOCORR_NONE, MOFF_IN_C64, MOFF_IN_CI4, MOFF_MFMA_BF16, MOFF_MFMA_F16,  # noqa: F401
-                   MOFF_NORM_PAIRS, MoffError, moff_geometry)
+from ._lib import (MOFF_AUTOCORR_NONE, MOFF_AUTOCORR_UV, MOFF_IN_C64, MOFF_IN_CI4, MOFF_MFMA_BF16,  # noqa: F401
+                   MOFF_MFMA_F16, MOFF_NORM_PAIRS, MoffError, moff_geometry)
 
 __all__ = ["Plan", "MoffError", "MOFF_IN_C64", "MOFF_IN_CI4", "MOFF_AUTOCORR_NONE", "MOFF_NORM_PAIRS",
-           "MOFF_MFMA_F16", "MOFF_MFMA_BF16", "library_path", "moff_image_autograd"]
+           "MOFF_MFMA_F16", "MOFF_MFMA_BF16", "MOFF_AUTOCORR_UV", "library_path", "moff_image_autograd"]
 
 
 def library_path():

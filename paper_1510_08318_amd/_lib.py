@@ -22,6 +22,7 @@ MOFF_AUTOCORR_NONE = 2
 MOFF_NORM_PAIRS = 4
 MOFF_MFMA_F16 = 8
 MOFF_MFMA_BF16 = 16
+MOFF_AUTOCORR_UV = 32
 
 c_i32p = ctypes.POINTER(ctypes.c_int32)
 c_u32p = ctypes.POINTER(ctypes.c_uint32)

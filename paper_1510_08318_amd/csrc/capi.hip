@@ -33,9 +33,12 @@ struct moff_plan_s {
   int* d_ktype_off = nullptr;
   GatherEntry* d_mfma_prog = nullptr;   // reduced-precision path (MOFF_MFMA_*)
   uint16_t* d_mfma_dft = nullptr;
+  double* d_Pn = nullptr;               // uv-plane autocorrelation rule (MOFF_AUTOCORR_UV)
   // workspace, grown on demand
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  void* d_aux = nullptr;                // S / A or shifted sensitivities of the uv rule
+  size_t aux_bytes = 0;
   // optional kernel timing
   bool timing = false, timed = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -77,7 +80,7 @@ moff_status upload(T** dst, const void* src, size_t bytes) {
 void free_device(moff_plan p) {
   void* ptrs[] = {p->d_tw,        p->d_Pp,        p->d_ant_type, p->d_ktab,        p->d_csr_ptr,
                   p->d_csr_ant,   p->d_csr_tap,   p->d_ant_cells, p->d_ktype_k,    p->d_ktype_off,
-                  p->d_mfma_prog, p->d_mfma_dft,  p->d_ws};
+                  p->d_mfma_prog, p->d_mfma_dft,  p->d_Pn,        p->d_ws,         p->d_aux};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
@@ -101,7 +104,22 @@ moff_status ensure_workspace(moff_plan p, size_t bytes) {
   return MOFF_OK;
 }
 
+moff_status ensure_aux(moff_plan p, size_t bytes) {
+  if (bytes <= p->aux_bytes) return MOFF_OK;
+  if (p->d_aux) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(p->d_aux);
+    p->d_aux = nullptr;
+    p->aux_bytes = 0;
+  }
+  if (hipMalloc(&p->d_aux, bytes) != hipSuccess) return MOFF_ERR_NOMEM;
+  p->aux_bytes = bytes;
+  return MOFF_OK;
+}
+
 moff_status hip_status(hipError_t e) { return e == hipSuccess ? MOFF_OK : MOFF_ERR_HIP; }
+
+bool uv_rule(const HostPlan& hp) { return (hp.flags & MOFF_AUTOCORR_UV) != 0; }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
@@ -117,6 +135,20 @@ double image_scale(const HostPlan& hp, int64_t n_time) {
   double s = 1.0 / static_cast<double>(n_time);
   if (hp.flags & MOFF_NORM_PAIRS) s /= static_cast<double>(hp.n_ant) * (hp.n_ant - 1);
   return s;
+}
+
+// The uv-plane rule on accumulated sums S [C][N][N] (Sec. 4.2), into `image`.
+moff_status uv_finalize(moff_plan p, const float* S, int64_t n_time, float* image, hipStream_t st) {
+  const HostPlan& hp = p->hp;
+  moff::UvArgs u{};
+  u.S = S;
+  u.Pn = p->d_Pn;
+  u.out = image;
+  u.N = hp.N;
+  u.n_chan = hp.n_chan;
+  u.a0 = hp.a0;
+  u.scale = image_scale(hp, n_time);
+  return hip_status(moff::launch_uv_finalize(u, st));
 }
 
 struct LaunchConfig {
@@ -370,6 +402,7 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
     up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
     up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
+    up(upload(&p->d_Pn, hp.Pn.data(), sizeof(double) * hp.Pn.size()));
     up(upload(&p->d_ant_type, hp.ant_ktype.data(), sizeof(int) * hp.ant_ktype.size()));
     up(upload(&p->d_ktab, hp.kvals.data(), sizeof(float) * hp.kvals.size()));
     up(upload(&p->d_csr_ptr, hp.csr_ptr.data(), sizeof(int) * hp.csr_ptr.size()));
@@ -596,7 +629,20 @@ moff_status moff_image(moff_plan p, const void* E, int64_t n_time, const float* 
   if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
   DeviceGuard guard(p->device);
   if (!guard.ok()) return MOFF_ERR_HIP;
-  return fused_run(p, E, n_time, gains, image, nullptr, true, static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!uv_rule(p->hp)) return fused_run(p, E, n_time, gains, image, nullptr, true, st);
+  // uv-plane rule: accumulate S (and A) first, then remove the zero-spacing component
+  const HostPlan& hp = p->hp;
+  const size_t s_bytes = sizeof(float) * static_cast<size_t>(hp.N) * hp.N * hp.n_chan;
+  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes;
+  s = ensure_aux(p, s_bytes + a_bytes);
+  if (s != MOFF_OK) return s;
+  float* S = static_cast<float*>(p->d_aux);
+  double* A = reinterpret_cast<double*>(static_cast<char*>(p->d_aux) + s_bytes);
+  if (moff::launch_zero(p->d_aux, s_bytes + a_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
+  s = fused_run(p, E, n_time, gains, S, A, false, st);
+  if (s != MOFF_OK) return s;
+  return uv_finalize(p, S, n_time, image, st);
 }
 
 moff_status moff_accumulate(moff_plan p, const void* E, int64_t n_time, const float* gains, float* S, double* A,
@@ -617,6 +663,7 @@ moff_status moff_finalize(moff_plan p, const float* S, const double* A, int64_t 
   DeviceGuard guard(p->device);
   if (!guard.ok()) return MOFF_ERR_HIP;
   const HostPlan& hp = p->hp;
+  if (uv_rule(hp)) return uv_finalize(p, S, n_time_total, image, static_cast<hipStream_t>(stream));
   moff::FinalizeArgs f{};
   f.S = S;
   f.A = A;
@@ -716,6 +763,7 @@ moff_status moff_image_staged(moff_plan p, const void* E, int64_t n_time, const 
     if (e == hipSuccess) e = moff::launch_detect(d, st);
     if (e != hipSuccess) return MOFF_ERR_HIP;
   }
+  if (uv_rule(hp)) return uv_finalize(p, S, n_time, image, st);
   moff::FinalizeArgs fa{};
   fa.S = S;
   fa.A = A;
@@ -763,6 +811,24 @@ moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const floa
   float2* Y = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes);
   float2* Gp = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes + y_bytes);
   if (moff::launch_zero(ws, d_bytes + q_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
+  // Under the uv-plane rule the image is scale * (S - beta Pn) with beta linear in
+  // S, so its sensitivities with respect to S are R shifted by <R, Pn> / (N^2 a0)
+  // per channel, and no per-antenna term remains.
+  const float* R = dL_dimage;
+  if (uv_rule(hp)) {
+    s = ensure_aux(p, sizeof(float) * npix * hp.n_chan);
+    if (s != MOFF_OK) return s;
+    moff::UvArgs u{};
+    u.S = dL_dimage;
+    u.Pn = p->d_Pn;
+    u.out = static_cast<float*>(p->d_aux);
+    u.N = hp.N;
+    u.n_chan = hp.n_chan;
+    u.a0 = hp.a0;
+    u.scale = 1.0;
+    if (moff::launch_uv_adjoint_shift(u, st) != hipSuccess) return MOFF_ERR_HIP;
+    R = u.out;
+  }
   const size_t sample_bytes = ci4 ? 1 : sizeof(float2);
   for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
     const int64_t nt = std::min(chunk, n_time - t0);
@@ -772,7 +838,7 @@ moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const floa
     hipError_t e = moff::launch_grid(g, ci4, st);
     moff::Fft2Args f{Eg, Y, p->d_tw};
     if (e == hipSuccess) e = moff::launch_fft2(f, hp.N, nt * hp.n_chan, st);
-    moff::AdjFftArgs af{Y, dL_dimage, Gp, p->d_tw, hp.n_chan};
+    moff::AdjFftArgs af{Y, R, Gp, p->d_tw, hp.n_chan};
     if (e == hipSuccess) e = moff::launch_adjoint_fft2(af, hp.N, nt * hp.n_chan, st);
     moff::DegridArgs dg{};
     dg.E = Ec;
@@ -799,7 +865,7 @@ moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const floa
   moff::GradFinalArgs gf{};
   gf.D = D;
   gf.Q = Q;
-  gf.R = dL_dimage;
+  gf.R = R;
   gf.Pp = p->d_Pp;
   gf.gains = reinterpret_cast<const float2*>(gains);
   gf.ant_type = p->d_ant_type;
@@ -808,7 +874,7 @@ moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const floa
   gf.n_ant = hp.n_ant;
   gf.n_chan = hp.n_chan;
   gf.n_types = hp.n_ktypes;
-  gf.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  gf.subtract = (hp.flags & (MOFF_AUTOCORR_NONE | MOFF_AUTOCORR_UV)) ? 0 : 1;
   gf.scale = 2.0 * image_scale(hp, n_time);
   return hip_status(moff::launch_grad_final(gf, st));
 }

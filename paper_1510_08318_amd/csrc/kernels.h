@@ -144,6 +144,19 @@ int mfma_threads(int N);
 hipError_t launch_mfma(const MfmaArgs& a, int N, int prec, bool ci4, int grid, hipStream_t st);
 int mfma_blocks_per_cu(int N, int prec, bool ci4, size_t lds);
 
+// uv-plane autocorrelation removal (uv_autocorr.hip): `S` is the per-channel
+// input (accumulated squared image, or dL/dI for the adjoint shift), `out` the
+// per-channel output, both [C][N][N]; Pn = sum_p n_p P_p and a0 = sum_p n_p sum|K_p|^2.
+struct UvArgs {
+  const float* S;
+  const double* Pn;            // [N][N]
+  float* out;
+  int N, n_chan;
+  double a0, scale;
+};
+hipError_t launch_uv_finalize(const UvArgs& a, hipStream_t st);
+hipError_t launch_uv_adjoint_shift(const UvArgs& a, hipStream_t st);
+
 hipError_t launch_adjoint_fft2(const AdjFftArgs& a, int N, int64_t n_frames, hipStream_t st);
 hipError_t launch_degrid(const DegridArgs& a, bool ci4, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);

@@ -177,8 +177,11 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     return fail(why, MOFF_ERR_INVALID_ARG, "null geometry array");
   if (g->n_ktypes < 1 || g->n_ktypes > kMaxTypes) return fail(why, MOFF_ERR_INVALID_ARG, "n_ktypes out of [1, 4]");
   if (g->n_chan < 1) return fail(why, MOFF_ERR_INVALID_ARG, "n_chan < 1");
-  if (g->flags & ~uint32_t(MOFF_IN_CI4 | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS | MOFF_MFMA_F16 | MOFF_MFMA_BF16))
+  if (g->flags &
+      ~uint32_t(MOFF_IN_CI4 | MOFF_AUTOCORR_NONE | MOFF_NORM_PAIRS | MOFF_MFMA_F16 | MOFF_MFMA_BF16 | MOFF_AUTOCORR_UV))
     return fail(why, MOFF_ERR_INVALID_ARG, "unknown flag bits");
+  if ((g->flags & MOFF_AUTOCORR_NONE) && (g->flags & MOFF_AUTOCORR_UV))
+    return fail(why, MOFF_ERR_INVALID_ARG, "MOFF_AUTOCORR_NONE and MOFF_AUTOCORR_UV exclude each other");
   if ((g->flags & MOFF_MFMA_F16) && (g->flags & MOFF_MFMA_BF16))
     return fail(why, MOFF_ERR_INVALID_ARG, "at most one of MOFF_MFMA_F16 and MOFF_MFMA_BF16");
   if (!is_pow2(g->grid_n) || g->grid_n < 8 || g->grid_n > 256)
@@ -315,6 +318,27 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         for (int v = 0; v < k; ++v) s += B[r * k + v] * A[q * k + v];
         out[r * N + q] = std::norm(s);
       }
+  }
+
+  // ---- uv-plane rule: power patterns summed over antennas, table autocorrelation at zero lag
+  {
+    std::vector<int> count(P.n_ktypes, 0);
+    for (int a = 0; a < P.n_ant; ++a) count[P.ant_ktype[a]]++;
+    P.Pn.assign(static_cast<size_t>(N) * N, 0.0);
+    P.a0 = 0.0;
+    for (int p = 0; p < P.n_ktypes; ++p) {
+      double e2 = 0.0;
+      const int kk = P.ktype_k[p] * P.ktype_k[p];
+      for (int i = 0; i < kk; ++i) {
+        const double re = P.kvals[2 * (P.ktype_off[p] + i)], im = P.kvals[2 * (P.ktype_off[p] + i) + 1];
+        e2 += re * re + im * im;
+      }
+      P.a0 += count[p] * e2;
+      const double* src = &P.Pp[static_cast<size_t>(p) * N * N];
+      for (size_t i = 0; i < static_cast<size_t>(N) * N; ++i) P.Pn[i] += count[p] * src[i];
+    }
+    if (!(P.a0 > 0.0) && (g->flags & MOFF_AUTOCORR_UV))
+      return fail(why, MOFF_ERR_INVALID_ARG, "MOFF_AUTOCORR_UV needs a nonzero illumination table");
   }
 
   // ---- twiddles

@@ -48,6 +48,10 @@ struct HostPlan {
 
   // power patterns, float64 [n_ktypes][N][N] in image pixel order
   std::vector<double> Pp;
+  // uv-plane autocorrelation rule: Pn = sum_p n_p P_p [N][N] and
+  // a0 = sum_p n_p sum |K_p|^2 (the tables' autocorrelation at zero lag)
+  std::vector<double> Pn;
+  double a0 = 0.0;
 
   // twiddles w_N^k = exp(+2 pi i k / N), k < N, float32 (re, im)
   std::vector<float> twiddle;

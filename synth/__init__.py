@@ -36,6 +36,7 @@ AUTOCORR_NONE = 2
 NORM_PAIRS = 4
 MFMA_F16 = 8
 MFMA_BF16 = 16
+AUTOCORR_UV = 32
 
 
 @dataclasses.dataclass

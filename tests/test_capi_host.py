@@ -171,3 +171,12 @@ def test_gather_program_replays_oracle_grid(moff, case):
             got = G[slot]
             assert (stored[slot] == 1).all() and stored.sum() == L * NZR
             assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
+
+
+def test_uv_rule_flag_validation(moff):
+    w = synth.make_config(1, n_time=2)
+    with pytest.raises(moff.MoffError) as ei:
+        moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.AUTOCORR_UV | synth.AUTOCORR_NONE)
+    assert ei.value.status == 1
+    with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.AUTOCORR_UV) as p:
+        assert p.N == 32
