@@ -273,19 +273,30 @@ def main():
     if args.adjoint:
         g_in = gains if gains is not None else torch.ones((C, Na), dtype=torch.complex64, device=dev)
         R = torch.randn((C, N, N), dtype=torch.float32, device=dev)
-        grad = torch.empty((C, Na), dtype=torch.complex64, device=dev)
-        plan.gain_vjp(E, g_in, R, out=grad)
-        torch.cuda.synchronize()
-        a0 = torch.cuda.Event(enable_timing=True)
-        a1 = torch.cuda.Event(enable_timing=True)
         reps = max(2, min(args.steps, 5))
-        a0.record(stream)
-        for _ in range(reps):
-            plan.gain_vjp(E, g_in, R, out=grad)
-        a1.record(stream)
-        torch.cuda.synchronize()
-        extra["adjoint_ms_per_step"] = round(a0.elapsed_time(a1) / reps, 3)
-        extra["adjoint_frames_per_s"] = frames / (a0.elapsed_time(a1) / reps / 1e3)
+        grads = {}
+        for staged in (False, True):
+            grad = torch.empty((C, Na), dtype=torch.complex64, device=dev)
+            plan.gain_vjp(E, g_in, R, out=grad, staged=staged)
+            torch.cuda.synchronize()
+            a0 = torch.cuda.Event(enable_timing=True)
+            a1 = torch.cuda.Event(enable_timing=True)
+            a0.record(stream)
+            for _ in range(reps):
+                plan.gain_vjp(E, g_in, R, out=grad, staged=staged)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ms = a0.elapsed_time(a1) / reps
+            key = "adjoint_staged" if staged else "adjoint"
+            extra[key + "_ms_per_step"] = round(ms, 3)
+            extra[key + "_frames_per_s"] = frames / (ms / 1e3)
+            grads[staged] = grad
+        plan.set_timing(True)
+        plan.gain_vjp(E, g_in, R, out=grads[False])
+        extra["adjoint_kernel_ms"] = round(plan.last_kernel_ms(), 4)
+        plan.set_timing(False)
+        extra["adjoint_fused_vs_staged_max_rel_diff"] = float(
+            ((grads[False] - grads[True]).abs().max() / grads[True].abs().max()).item())
 
     cpu = None
     if not args.no_cpu:

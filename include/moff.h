@@ -338,12 +338,19 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  * s the pair normalisation (1 unless MOFF_NORM_PAIRS), the rho term absent under
  * MOFF_AUTOCORR_NONE.  Under MOFF_AUTOCORR_UV the rho term is absent and R is
  * first shifted per channel by sum_pix R Pn / (N^2 a[0]) (the derivative of the
- * zero-spacing rule).  Every frame's grid and field are recomputed in time
- * chunks through the plan workspace (never stored for the whole integration);
- * the sums over time are float64.
+ * zero-spacing rule).  Every frame's grid and field are recomputed, never
+ * stored for the whole integration; the sums over time are float64.
+ * moff_gain_vjp runs one fused kernel in which each frame's grid, field and
+ * adjoint stay on chip (when the plan's antennas fit its per-lane slots:
+ * n_ant <= 4 x the workgroup size; otherwise it falls back to the staged form).
+ * moff_gain_vjp_staged computes the same gradient with the steps separated by
+ * HBM buffers, in time chunks through the plan workspace.  With timing enabled,
+ * the HIP events bracket the fused adjoint kernel.
  */
 moff_status moff_gain_vjp(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
                           const float* dL_dimage_dev, float* dL_dgains_dev, void* hip_stream);
+moff_status moff_gain_vjp_staged(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
+                                 const float* dL_dimage_dev, float* dL_dgains_dev, void* hip_stream);
 
 #ifdef __cplusplus
 }

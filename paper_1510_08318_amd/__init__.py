@@ -275,15 +275,17 @@ class Plan:
         _lib.moff_image_staged(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
         return out
 
-    def gain_vjp(self, E, gains, dL_dimage, out=None, stream=None):
-        """dL/dRe(g) + i dL/dIm(g) (complex64 [n_chan, n_ant]) for R = dL/dI."""
+    def gain_vjp(self, E, gains, dL_dimage, out=None, stream=None, staged=False):
+        """dL/dRe(g) + i dL/dIm(g) (complex64 [n_chan, n_ant]) for R = dL/dI
+        (staged=True: the HBM-staged form of the same computation)."""
         torch = self._torch()
         pE, T = self._E(E)
         pR = self._dev(dL_dimage, "dL_dimage", (self.n_chan, self.N, self.N), torch.float32)
         if out is None:
             out = self._new((self.n_chan, self.n_ant), torch.complex64)
         po = self._dev(out, "out", (self.n_chan, self.n_ant), torch.complex64)
-        _lib.moff_gain_vjp(self.handle, pE, T, self._gains(gains), pR, po, self._stream(stream))
+        fn = _lib.moff_gain_vjp_staged if staged else _lib.moff_gain_vjp
+        fn(self.handle, pE, T, self._gains(gains), pR, po, self._stream(stream))
         return out
 
 

@@ -34,6 +34,7 @@ struct moff_plan_s {
   GatherEntry* d_mfma_prog = nullptr;   // reduced-precision path (MOFF_MFMA_*)
   uint16_t* d_mfma_dft = nullptr;
   double* d_Pn = nullptr;               // uv-plane autocorrelation rule (MOFF_AUTOCORR_UV)
+  uint32_t* d_adj_slots = nullptr;      // fused adjoint: antennas per lane (variant 0); null if they do not fit
   // workspace, grown on demand
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -80,7 +81,8 @@ moff_status upload(T** dst, const void* src, size_t bytes) {
 void free_device(moff_plan p) {
   void* ptrs[] = {p->d_tw,        p->d_Pp,        p->d_ant_type, p->d_ktab,        p->d_csr_ptr,
                   p->d_csr_ant,   p->d_csr_tap,   p->d_ant_cells, p->d_ktype_k,    p->d_ktype_off,
-                  p->d_mfma_prog, p->d_mfma_dft,  p->d_Pn,        p->d_ws,         p->d_aux};
+                  p->d_mfma_prog, p->d_mfma_dft,  p->d_Pn,        p->d_ws,         p->d_aux,
+                  p->d_adj_slots};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
@@ -342,6 +344,154 @@ moff::GridArgs grid_args(moff_plan p, const void* E, int64_t n_time, const float
   return g;
 }
 
+moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* gains, const float* dL_dimage,
+                     float* dL_dgains, void* stream, bool force_staged) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !dL_dimage || !dL_dgains || !aligned16(dL_dimage) || !aligned16(dL_dgains) ||
+      (gains && !aligned16(gains)))
+    return MOFF_ERR_INVALID_ARG;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const HostPlan& hp = p->hp;
+  const HostPlan::Variant& V = hp.variants[0];
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
+  // Under the uv-plane rule the image is scale * (S - beta Pn) with beta linear in
+  // S, so its sensitivities with respect to S are R shifted by <R, Pn> / (N^2 a0)
+  // per channel, and no per-antenna term remains.
+  const float* R = dL_dimage;
+  if (uv_rule(hp)) {
+    s = ensure_aux(p, sizeof(float) * npix * hp.n_chan);
+    if (s != MOFF_OK) return s;
+    moff::UvArgs u{};
+    u.S = dL_dimage;
+    u.Pn = p->d_Pn;
+    u.out = static_cast<float*>(p->d_aux);
+    u.N = hp.N;
+    u.n_chan = hp.n_chan;
+    u.a0 = hp.a0;
+    u.scale = 1.0;
+    if (moff::launch_uv_adjoint_shift(u, st) != hipSuccess) return MOFF_ERR_HIP;
+    R = u.out;
+  }
+  moff::GradFinalArgs gf{};
+  gf.R = R;
+  gf.Pp = p->d_Pp;
+  gf.gains = reinterpret_cast<const float2*>(gains);
+  gf.ant_type = p->d_ant_type;
+  gf.grad = reinterpret_cast<float2*>(dL_dgains);
+  gf.N = hp.N;
+  gf.n_ant = hp.n_ant;
+  gf.n_chan = hp.n_chan;
+  gf.n_types = hp.n_ktypes;
+  gf.subtract = (hp.flags & (MOFF_AUTOCORR_NONE | MOFF_AUTOCORR_UV)) ? 0 : 1;
+  gf.scale = 2.0 * image_scale(hp, n_time);
+
+  const size_t lds = moff::fused_lds_bytes(hp.N, 0, V.n_weights(), hp.n_ant);
+  if (!force_staged && p->d_adj_slots && lds <= size_t(159) * 1024) {
+    // fused: every frame's grid, field and adjoint stay in LDS
+    const int per_slice = V.shape.SX * hp.n_chan;
+    const int resident =
+        std::max(1, moff::adjoint_fused_blocks_per_cu(hp.N, 0, ci4, lds)) * std::max(1, p->cu_count);
+    const int slices = static_cast<int>(
+        std::max<int64_t>(1, std::min<int64_t>({(2 * resident + per_slice - 1) / per_slice, n_time, 64})));
+    const int parts = slices * V.shape.SX;
+    const size_t na = static_cast<size_t>(hp.n_chan) * hp.n_ant;
+    s = ensure_workspace(p, sizeof(double2) * na * (parts + 1) + sizeof(double) * na);
+    if (s != MOFF_OK) return s;
+    double2* Dp = static_cast<double2*>(p->d_ws);
+    double2* D = Dp + na * parts;
+    double* Q = reinterpret_cast<double*>(D + na);
+    moff::AdjFusedArgs a{};
+    a.E = E;
+    a.gains = reinterpret_cast<const float2*>(gains);
+    a.prog = p->d_prog[0];
+    a.prog_len = V.prog_len;
+    a.weights = p->d_weights[0];
+    a.n_weights = V.n_weights();
+    a.tw = p->d_tw;
+    a.slots = p->d_adj_slots;
+    a.R = R;
+    a.n_ant = hp.n_ant;
+    a.n_chan = hp.n_chan;
+    a.n_taps = hp.n_taps;
+    a.n_time = n_time;
+    a.slices = slices;
+    a.Dp = Dp;
+    if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
+    if (moff::launch_adjoint_fused(a, hp.N, 0, ci4, per_slice * slices, st) != hipSuccess) return MOFF_ERR_HIP;
+    if (p->timing) {
+      if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
+      p->timed = true;
+    }
+    if (moff::launch_adjoint_reduce(Dp, parts, hp.n_chan, hp.n_ant, D, st) != hipSuccess) return MOFF_ERR_HIP;
+    if (moff::launch_antenna_power(E, ci4, n_time, hp.n_chan, hp.n_ant, Q, st) != hipSuccess) return MOFF_ERR_HIP;
+    gf.D = D;
+    gf.Q = Q;
+    return hip_status(moff::launch_grad_final(gf, st));
+  }
+
+  // staged: per time chunk, grids, fields and adjoint grids through HBM
+  const size_t L2 = static_cast<size_t>(hp.L) * hp.L;
+  const size_t gp_frame = static_cast<size_t>(V.shape.SX) * hp.L * V.NZR;
+  const size_t d_bytes = sizeof(double) * 2 * hp.n_chan * hp.n_ant;
+  const size_t q_bytes = sizeof(double) * hp.n_chan * hp.n_ant;
+  // time chunk: the per-chunk grids, fields and adjoint grids within ~2 GiB
+  const size_t per_t = sizeof(float2) * (L2 + npix + gp_frame) * hp.n_chan;
+  int64_t chunk = std::max<int64_t>(1, static_cast<int64_t>((size_t(2) << 30) / per_t));
+  chunk = std::min(chunk, n_time);
+  const size_t eg_bytes = sizeof(float2) * L2 * hp.n_chan * chunk;
+  const size_t y_bytes = sizeof(float2) * npix * hp.n_chan * chunk;
+  const size_t gp_bytes = sizeof(float2) * gp_frame * hp.n_chan * chunk;
+  s = ensure_workspace(p, d_bytes + q_bytes + eg_bytes + y_bytes + gp_bytes);
+  if (s != MOFF_OK) return s;
+  char* ws = static_cast<char*>(p->d_ws);
+  double2* D = reinterpret_cast<double2*>(ws);
+  double* Q = reinterpret_cast<double*>(ws + d_bytes);
+  float2* Eg = reinterpret_cast<float2*>(ws + d_bytes + q_bytes);
+  float2* Y = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes);
+  float2* Gp = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes + y_bytes);
+  if (moff::launch_zero(ws, d_bytes + q_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
+  const size_t sample_bytes = ci4 ? 1 : sizeof(float2);
+  for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
+    const int64_t nt = std::min(chunk, n_time - t0);
+    const void* Ec = static_cast<const char*>(E) + static_cast<size_t>(t0) * hp.n_chan * hp.n_ant * sample_bytes;
+    moff::GridArgs g = grid_args(p, Ec, nt, gains);
+    g.Eg = Eg;
+    hipError_t e = moff::launch_grid(g, ci4, st);
+    moff::Fft2Args f{Eg, Y, p->d_tw};
+    if (e == hipSuccess) e = moff::launch_fft2(f, hp.N, nt * hp.n_chan, st);
+    moff::AdjFftArgs af{Y, R, Gp, p->d_tw, hp.n_chan};
+    if (e == hipSuccess) e = moff::launch_adjoint_fft2(af, hp.N, nt * hp.n_chan, st);
+    moff::DegridArgs dg{};
+    dg.E = Ec;
+    dg.Gp = Gp;
+    dg.weights = p->d_weights[0];
+    dg.ant_type = p->d_ant_type;
+    dg.ant_cells = p->d_ant_cells;
+    dg.ktype_k = p->d_ktype_k;
+    dg.ktype_off = p->d_ktype_off;
+    dg.D = D;
+    dg.Q = Q;
+    dg.n_ant = hp.n_ant;
+    dg.n_chan = hp.n_chan;
+    dg.n_taps = hp.n_taps;
+    dg.SX = V.shape.SX;
+    dg.L = hp.L;
+    dg.M = V.M;
+    dg.NZR = V.NZR;
+    dg.NJ = V.NJ;
+    dg.n_time = nt;
+    if (e == hipSuccess) e = moff::launch_degrid(dg, ci4, st);
+    if (e != hipSuccess) return MOFF_ERR_HIP;
+  }
+  gf.D = D;
+  gf.Q = Q;
+  return hip_status(moff::launch_grad_final(gf, st));
+}
+
 }  // namespace
 
 extern "C" {
@@ -403,6 +553,8 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
     up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
     up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
     up(upload(&p->d_Pn, hp.Pn.data(), sizeof(double) * hp.Pn.size()));
+    if (!hp.variants[0].slots.empty())
+      up(upload(&p->d_adj_slots, hp.variants[0].slots.data(), sizeof(uint32_t) * hp.variants[0].slots.size()));
     up(upload(&p->d_ant_type, hp.ant_ktype.data(), sizeof(int) * hp.ant_ktype.size()));
     up(upload(&p->d_ktab, hp.kvals.data(), sizeof(float) * hp.kvals.size()));
     up(upload(&p->d_csr_ptr, hp.csr_ptr.data(), sizeof(int) * hp.csr_ptr.size()));
@@ -779,104 +931,12 @@ moff_status moff_image_staged(moff_plan p, const void* E, int64_t n_time, const 
 
 moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* gains, const float* dL_dimage,
                           float* dL_dgains, void* stream) {
-  moff_status s = check_compute(p, n_time);
-  if (s != MOFF_OK) return s;
-  if (!E || !dL_dimage || !dL_dgains || !aligned16(dL_dimage) || !aligned16(dL_dgains) ||
-      (gains && !aligned16(gains)))
-    return MOFF_ERR_INVALID_ARG;
-  DeviceGuard guard(p->device);
-  if (!guard.ok()) return MOFF_ERR_HIP;
-  const HostPlan& hp = p->hp;
-  const HostPlan::Variant& V = hp.variants[0];
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  const bool ci4 = hp.flags & MOFF_IN_CI4;
-  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
-  const size_t L2 = static_cast<size_t>(hp.L) * hp.L;
-  const size_t gp_frame = static_cast<size_t>(V.shape.SX) * hp.L * V.NZR;
-  const size_t d_bytes = sizeof(double) * 2 * hp.n_chan * hp.n_ant;
-  const size_t q_bytes = sizeof(double) * hp.n_chan * hp.n_ant;
-  // time chunk: the per-chunk grids, fields and adjoint grids within ~2 GiB
-  const size_t per_t = sizeof(float2) * (L2 + npix + gp_frame) * hp.n_chan;
-  int64_t chunk = std::max<int64_t>(1, static_cast<int64_t>((size_t(2) << 30) / per_t));
-  chunk = std::min(chunk, n_time);
-  const size_t eg_bytes = sizeof(float2) * L2 * hp.n_chan * chunk;
-  const size_t y_bytes = sizeof(float2) * npix * hp.n_chan * chunk;
-  const size_t gp_bytes = sizeof(float2) * gp_frame * hp.n_chan * chunk;
-  s = ensure_workspace(p, d_bytes + q_bytes + eg_bytes + y_bytes + gp_bytes);
-  if (s != MOFF_OK) return s;
-  char* ws = static_cast<char*>(p->d_ws);
-  double2* D = reinterpret_cast<double2*>(ws);
-  double* Q = reinterpret_cast<double*>(ws + d_bytes);
-  float2* Eg = reinterpret_cast<float2*>(ws + d_bytes + q_bytes);
-  float2* Y = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes);
-  float2* Gp = reinterpret_cast<float2*>(ws + d_bytes + q_bytes + eg_bytes + y_bytes);
-  if (moff::launch_zero(ws, d_bytes + q_bytes, st) != hipSuccess) return MOFF_ERR_HIP;
-  // Under the uv-plane rule the image is scale * (S - beta Pn) with beta linear in
-  // S, so its sensitivities with respect to S are R shifted by <R, Pn> / (N^2 a0)
-  // per channel, and no per-antenna term remains.
-  const float* R = dL_dimage;
-  if (uv_rule(hp)) {
-    s = ensure_aux(p, sizeof(float) * npix * hp.n_chan);
-    if (s != MOFF_OK) return s;
-    moff::UvArgs u{};
-    u.S = dL_dimage;
-    u.Pn = p->d_Pn;
-    u.out = static_cast<float*>(p->d_aux);
-    u.N = hp.N;
-    u.n_chan = hp.n_chan;
-    u.a0 = hp.a0;
-    u.scale = 1.0;
-    if (moff::launch_uv_adjoint_shift(u, st) != hipSuccess) return MOFF_ERR_HIP;
-    R = u.out;
-  }
-  const size_t sample_bytes = ci4 ? 1 : sizeof(float2);
-  for (int64_t t0 = 0; t0 < n_time; t0 += chunk) {
-    const int64_t nt = std::min(chunk, n_time - t0);
-    const void* Ec = static_cast<const char*>(E) + static_cast<size_t>(t0) * hp.n_chan * hp.n_ant * sample_bytes;
-    moff::GridArgs g = grid_args(p, Ec, nt, gains);
-    g.Eg = Eg;
-    hipError_t e = moff::launch_grid(g, ci4, st);
-    moff::Fft2Args f{Eg, Y, p->d_tw};
-    if (e == hipSuccess) e = moff::launch_fft2(f, hp.N, nt * hp.n_chan, st);
-    moff::AdjFftArgs af{Y, R, Gp, p->d_tw, hp.n_chan};
-    if (e == hipSuccess) e = moff::launch_adjoint_fft2(af, hp.N, nt * hp.n_chan, st);
-    moff::DegridArgs dg{};
-    dg.E = Ec;
-    dg.Gp = Gp;
-    dg.weights = p->d_weights[0];
-    dg.ant_type = p->d_ant_type;
-    dg.ant_cells = p->d_ant_cells;
-    dg.ktype_k = p->d_ktype_k;
-    dg.ktype_off = p->d_ktype_off;
-    dg.D = D;
-    dg.Q = Q;
-    dg.n_ant = hp.n_ant;
-    dg.n_chan = hp.n_chan;
-    dg.n_taps = hp.n_taps;
-    dg.SX = V.shape.SX;
-    dg.L = hp.L;
-    dg.M = V.M;
-    dg.NZR = V.NZR;
-    dg.NJ = V.NJ;
-    dg.n_time = nt;
-    if (e == hipSuccess) e = moff::launch_degrid(dg, ci4, st);
-    if (e != hipSuccess) return MOFF_ERR_HIP;
-  }
-  moff::GradFinalArgs gf{};
-  gf.D = D;
-  gf.Q = Q;
-  gf.R = R;
-  gf.Pp = p->d_Pp;
-  gf.gains = reinterpret_cast<const float2*>(gains);
-  gf.ant_type = p->d_ant_type;
-  gf.grad = reinterpret_cast<float2*>(dL_dgains);
-  gf.N = hp.N;
-  gf.n_ant = hp.n_ant;
-  gf.n_chan = hp.n_chan;
-  gf.n_types = hp.n_ktypes;
-  gf.subtract = (hp.flags & (MOFF_AUTOCORR_NONE | MOFF_AUTOCORR_UV)) ? 0 : 1;
-  gf.scale = 2.0 * image_scale(hp, n_time);
-  return hip_status(moff::launch_grad_final(gf, st));
+  return gain_vjp(p, E, n_time, gains, dL_dimage, dL_dgains, stream, false);
+}
+
+moff_status moff_gain_vjp_staged(moff_plan p, const void* E, int64_t n_time, const float* gains,
+                                 const float* dL_dimage, float* dL_dgains, void* stream) {
+  return gain_vjp(p, E, n_time, gains, dL_dimage, dL_dgains, stream, true);
 }
 
 }  // extern "C"

@@ -295,6 +295,97 @@ __device__ __forceinline__ void col_stage_adjoint(float2* G, const float2* twc, 
   }
 }
 
+// Column stage followed by its adjoint, column by column in place: the forward
+// pruned column DFT, each output pixel scaled by this lane's sensitivity
+// rr[acc_index] (the pixels col_stage hands to its sink), and the adjoint back
+// to Z'[iy][m] for iy < L.  The same as col_stage into a buffer, a pixel-wise
+// product and col_stage_adjoint from it, without holding the column's outputs.
+template <int N, int V>
+__device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc, const float (&rr)[FT<N, V>::NACC]) {
+  using C = FT<N, V>;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / C::CPW;
+#pragma unroll
+  for (int cs = 0; cs < C::CSTEPS; ++cs) {
+    const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
+    if (C::CGUARD && col >= C::M) continue;
+    float2* Zc = G + col + sub * C::P;            // row `sub` of this column
+    float2* Zb = G + col + sub * C::QC * C::P;    // row (sub QC) of this column
+    float2 z[C::JA][C::PH], xacc[C::JA][C::PH];
+#pragma unroll
+    for (int ja = 0; ja < C::JA; ++ja)
+#pragma unroll
+      for (int n1 = 0; n1 < C::PH; ++n1) {
+        z[ja][n1] = Zc[(C::LPC * ja + C::QC * n1) * C::P];
+        xacc[ja][n1] = make_float2(0.f, 0.f);
+      }
+    wave_sync();
+    static_for<0, 2>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      // forward pass A, half-round s
+#pragma unroll
+      for (int ja = 0; ja < C::JA; ++ja) {
+        const int n2 = sub + C::LPC * ja;
+        float2 u[C::PH];
+        static_for<0, C::PH>([&](auto nc) {
+          constexpr int n1 = decltype(nc)::value;
+          if constexpr (s == 0) u[n1] = z[ja][n1];
+          else u[n1] = rot<C::PC, n1>(z[ja][n1]);
+        });
+        Dft<C::PH>::run(u);
+#pragma unroll
+        for (int j = 0; j < C::PH; ++j) {
+          const int q1 = 2 * j + s;
+          if (q1 != 0) u[j] = c_mul(u[j], twc[q1 * C::QC + n2]);
+          Zc[(C::LPC * ja + j * C::QC) * C::P] = u[j];
+        }
+      }
+      wave_sync();
+      // forward pass B, pixel scaling, adjoint pass B^H: the same slots of this lane
+#pragma unroll
+      for (int jb = 0; jb < C::JB; ++jb) {
+        const int j = sub + C::LPC * jb;
+        const int q1 = 2 * j + s;
+        float2 v[C::QC];
+#pragma unroll
+        for (int k = 0; k < C::QC; ++k) v[k] = Zb[(C::LPC * jb * C::QC + k) * C::P];
+        Dft<C::QC>::run(v);
+#pragma unroll
+        for (int q2 = 0; q2 < C::QC; ++q2) {
+          const float r = rr[((cs * 2 + s) * C::JB + jb) * C::QC + q2];
+          v[q2] = make_float2(v[q2].x * r, v[q2].y * r);
+        }
+        idft<C::QC>(v);
+#pragma unroll
+        for (int n2 = 0; n2 < C::QC; ++n2) {
+          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twc[q1 * C::QC + n2]);
+          Zb[(C::LPC * jb * C::QC + n2) * C::P] = v[n2];
+        }
+      }
+      wave_sync();
+      // adjoint pass A^H, half-round s
+#pragma unroll
+      for (int ja = 0; ja < C::JA; ++ja) {
+        float2 u[C::PH];
+#pragma unroll
+        for (int j = 0; j < C::PH; ++j) u[j] = Zc[(C::LPC * ja + j * C::QC) * C::P];
+        idft<C::PH>(u);
+        static_for<0, C::PH>([&](auto nc) {
+          constexpr int n1 = decltype(nc)::value;
+          const float2 t = (s == 0) ? u[n1] : rot<C::PC, -n1>(u[n1]);
+          xacc[ja][n1] = c_add(xacc[ja][n1], t);
+        });
+      }
+      wave_sync();
+    });
+#pragma unroll
+    for (int ja = 0; ja < C::JA; ++ja)
+#pragma unroll
+      for (int n1 = 0; n1 < C::PH; ++n1) Zc[(C::LPC * ja + C::QC * n1) * C::P] = xacc[ja][n1];
+    wave_sync();
+  }
+}
+
 // Row stage adjoint: G'[iy][n'] = conj(w_N^{n' w}) sum_m Z'[iy][m] w_M^{-n' m}
 // for n' < NZR, in place.
 template <int N, int V>

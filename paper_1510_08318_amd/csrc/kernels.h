@@ -157,6 +157,32 @@ struct UvArgs {
 hipError_t launch_uv_finalize(const UvArgs& a, hipStream_t st);
 hipError_t launch_uv_adjoint_shift(const UvArgs& a, hipStream_t st);
 
+// Fused gain adjoint: one workgroup per (column class, channel, time slice) runs
+// ingest, gridding, the frame transform, the pixel-wise product with R, the
+// adjoint transform and the degridding for every frame, and writes per-antenna
+// partial sums Dp[(slice * SX + w)][C][n_ant] += conj(E) d over its frames.
+struct AdjFusedArgs {
+  const void* E;               // [T][C][n_ant] c64 or ci4
+  const float2* gains;         // [C][n_ant] or nullptr
+  const GatherEntry* prog;     // [SX][prog_len][NT] (the forward gather program)
+  int prog_len;
+  const float2* weights;       // [SX][n_weights]
+  int n_weights;
+  const float2* tw;            // [N]
+  const uint32_t* slots;       // [NT][kAdjSlots][2] (HostPlan::Variant::slots)
+  const float* R;              // [C][N][N] dL/dI
+  int n_ant, n_chan, n_taps;
+  int64_t n_time;
+  int slices;
+  double2* Dp;                 // [slices * SX][C][n_ant]
+};
+hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st);
+int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, size_t lds);
+// Q[c][a] = sum_t |E[t][c][a]|^2 (float64); D[c][a] = sum_k Dp[k][c][a] over `parts` partials.
+hipError_t launch_antenna_power(const void* E, bool ci4, int64_t n_time, int n_chan, int n_ant, double* Q,
+                                hipStream_t st);
+hipError_t launch_adjoint_reduce(const double2* Dp, int parts, int n_chan, int n_ant, double2* D, hipStream_t st);
+
 hipError_t launch_adjoint_fft2(const AdjFftArgs& a, int N, int64_t n_frames, hipStream_t st);
 hipError_t launch_degrid(const DegridArgs& a, bool ci4, hipStream_t st);
 hipError_t launch_grad_final(const GradFinalArgs& a, hipStream_t st);

@@ -175,6 +175,143 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// fused gain adjoint
+// ---------------------------------------------------------------------------
+
+template <int N, int V, bool CI4>
+__global__ __launch_bounds__((FT<N, V>::NT)) void adjoint_fused_kernel(AdjFusedArgs a) {
+  using C = FT<N, V>;
+  constexpr int NT = C::NT;
+  extern __shared__ float2 lds[];
+  const int tid = threadIdx.x;
+
+  float2* G = lds;                          // [L][P], row pitch P = M + 1
+  float2* twr = G + C::GRID;                // [PR * QR]
+  float2* twc = twr + C::TWR;               // [PC * QC]
+  float2* W = twc + C::TWC;                 // [n_weights]
+  float2* gl = W + a.n_weights;             // [n_ant] gains of the current channel
+  float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
+
+  const int item = blockIdx.x;
+  if (item >= C::SX * a.n_chan * a.slices) return;
+  const int w = item % C::SX;
+  const int c = (item / C::SX) % a.n_chan;
+  const int slice = item / (C::SX * a.n_chan);
+  const size_t img_stride = static_cast<size_t>(N) * N;
+
+  build_twiddles<N, V>(a.tw, w, twr, twc);
+  float2 fin[C::PRNZ];
+  fold_factors<N, V>(a.tw, w, fin);
+  for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
+  for (int i = tid; i < a.n_ant; i += NT)
+    gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+  if (tid == 0) e[a.n_ant] = make_float2(0.f, 0.f);
+
+  // sensitivities of the pixels this lane's column stage produces
+  float rr[C::NACC];
+  const float* Rc = a.R + static_cast<size_t>(c) * img_stride;
+#pragma unroll
+  for (int idx = 0; idx < C::NACC; ++idx) {
+    int r, col;
+    acc_pixel<N, V>(idx, r, col);
+    const int q = C::SX * col + w;
+    rr[idx] = (C::CGUARD && col >= C::M) ? 0.f
+                                         : Rc[static_cast<size_t>((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1))];
+  }
+
+  // this lane's antennas for the degridding
+  uint32_t s0[kAdjSlots], s1[kAdjSlots];
+  double2 D[kAdjSlots];
+#pragma unroll
+  for (int s = 0; s < kAdjSlots; ++s) {
+    s0[s] = a.slots[(static_cast<size_t>(tid) * kAdjSlots + s) * 2];
+    s1[s] = a.slots[(static_cast<size_t>(tid) * kAdjSlots + s) * 2 + 1];
+    D[s] = make_double2(0.0, 0.0);
+  }
+
+  const int64_t T = a.n_time;
+  const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
+  const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
+  const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
+
+  __syncthreads();
+  for (int64_t t = t0; t < t1; ++t) {
+    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+    for (int i = tid; i < a.n_ant; i += NT) e[i] = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+    float2 Er[kAdjSlots];
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s) {
+      const uint32_t ant = s0[s] & 0xFFFu;
+      Er[s] = ant != kAdjEmpty ? load_sample(a.E, base + ant, CI4) : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    gather_frame<NT>(prog, a.prog_len, e, W, G);
+    __syncthreads();
+    row_stage<N, V>(G, twr, fin);
+    __syncthreads();
+    col_stage_roundtrip<N, V>(G, twc, rr);
+    __syncthreads();
+    row_stage_adjoint<N, V>(G, twr, fin);
+    __syncthreads();
+    // degridding: d = sum over the footprint of conj(weight) G', then D += conj(E) d
+#pragma unroll
+    for (int s = 0; s < kAdjSlots; ++s) {
+      const uint32_t ant = s0[s] & 0xFFFu;
+      if (ant == kAdjEmpty) continue;
+      const int off = (s0[s] >> 12) & 0xFFFu, k = (s0[s] >> 24) & 0xFu;
+      const int ix0 = s1[s] & 0xFFFFu, iy0 = s1[s] >> 16;
+      float dx = 0.f, dy = 0.f;
+      for (int u = 0; u < k; ++u) {
+        const float2* Grow = G + (iy0 + u) * C::P;
+        for (int v = 0; v < k; ++v) {
+          const int ix = ix0 + v;
+          const int j = ix / C::M, n = ix - j * C::M;
+          const float2 g = Grow[n];
+          const float2 wt = W[j * a.n_taps + off + u * k + v];
+          dx = fmaf(g.x, wt.x, fmaf(g.y, wt.y, dx));
+          dy = fmaf(g.y, wt.x, fmaf(-g.x, wt.y, dy));
+        }
+      }
+      D[s].x += static_cast<double>(Er[s].x) * dx + static_cast<double>(Er[s].y) * dy;
+      D[s].y += static_cast<double>(Er[s].x) * dy - static_cast<double>(Er[s].y) * dx;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kAdjSlots; ++s) {
+    const uint32_t ant = s0[s] & 0xFFFu;
+    if (ant == kAdjEmpty) continue;
+    a.Dp[(static_cast<size_t>(slice * C::SX + w) * a.n_chan + c) * a.n_ant + ant] = D[s];
+  }
+}
+
+// One thread per (channel, antenna): Q = sum_t |E|^2 in float64.
+template <bool CI4>
+__global__ __launch_bounds__(256) void antenna_power_kernel(const void* E, int64_t n_time, int n_chan, int n_ant,
+                                                            double* Q) {
+  const int c = blockIdx.y;
+  const int ant = blockIdx.x * 256 + threadIdx.x;
+  if (ant >= n_ant) return;
+  double q = 0.0;
+  for (int64_t t = 0; t < n_time; ++t) {
+    const float2 v = load_sample(E, (static_cast<size_t>(t) * n_chan + c) * n_ant + ant, CI4);
+    q += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+  }
+  Q[static_cast<size_t>(c) * n_ant + ant] = q;
+}
+
+// D = sum of the per-(slice, class) partial sums, in order.
+__global__ __launch_bounds__(256) void adjoint_reduce_kernel(const double2* Dp, int parts, size_t n, double2* D) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= n) return;
+  double x = 0.0, y = 0.0;
+  for (int k = 0; k < parts; ++k) {
+    x += Dp[static_cast<size_t>(k) * n + i].x;
+    y += Dp[static_cast<size_t>(k) * n + i].y;
+  }
+  D[i] = make_double2(x, y);
+}
+
 // Sum per-slice partials in slice order; then remove self power and average
 // (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
@@ -495,6 +632,75 @@ hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hi
   if (err != hipSuccess) return err;
   void* args[] = {const_cast<FusedArgs*>(&a)};
   return hipLaunchKernel(k, dim3(grid), dim3(S.NT), args, lds, st);
+}
+
+namespace {
+
+template <int N, int V, bool CI4>
+const void* adjoint_fused_symbol() {
+  return reinterpret_cast<const void*>(adjoint_fused_kernel<N, V, CI4>);
+}
+
+template <int N, int V>
+const void* adjoint_fused_symbol_v(bool ci4) {
+  if constexpr (frame_shape(N, V).N == N)
+    return ci4 ? adjoint_fused_symbol<N, V, true>() : adjoint_fused_symbol<N, V, false>();
+  else
+    return nullptr;
+}
+
+const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4) {
+  auto pick = [&](auto nc) -> const void* {
+    constexpr int NN = decltype(nc)::value;
+    // variant 0 only: at N = 256 variant 1's 512-thread workgroups would spill the
+    // column round trip's state (forward inputs, adjoint sums, pixel sensitivities)
+    return V == 0 ? adjoint_fused_symbol_v<NN, 0>(ci4) : nullptr;
+  };
+  switch (N) {
+    case 8: return pick(std::integral_constant<int, 8>{});
+    case 16: return pick(std::integral_constant<int, 16>{});
+    case 32: return pick(std::integral_constant<int, 32>{});
+    case 64: return pick(std::integral_constant<int, 64>{});
+    case 128: return pick(std::integral_constant<int, 128>{});
+    case 256: return pick(std::integral_constant<int, 256>{});
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st) {
+  const void* k = adjoint_fused_kernel_symbol(N, V, ci4);
+  if (!k) return hipErrorInvalidValue;
+  const FrameShape S = frame_shape(N, V);
+  const size_t lds = fused_lds_bytes(N, V, a.n_weights, a.n_ant);
+  hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+  if (err != hipSuccess) return err;
+  void* args[] = {const_cast<AdjFusedArgs*>(&a)};
+  return hipLaunchKernel(k, dim3(grid), dim3(S.NT), args, lds, st);
+}
+
+int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
+  const void* k = adjoint_fused_kernel_symbol(N, V, ci4);
+  if (!k) return 0;
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, frame_shape(N, V).NT, lds) != hipSuccess) return 1;
+  return n;
+}
+
+hipError_t launch_antenna_power(const void* E, bool ci4, int64_t n_time, int n_chan, int n_ant, double* Q,
+                                hipStream_t st) {
+  const dim3 grid((n_ant + 255) / 256, n_chan);
+  if (ci4) hipLaunchKernelGGL(antenna_power_kernel<true>, grid, dim3(256), 0, st, E, n_time, n_chan, n_ant, Q);
+  else hipLaunchKernelGGL(antenna_power_kernel<false>, grid, dim3(256), 0, st, E, n_time, n_chan, n_ant, Q);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_reduce(const double2* Dp, int parts, int n_chan, int n_ant, double2* D, hipStream_t st) {
+  const size_t n = static_cast<size_t>(n_chan) * n_ant;
+  hipLaunchKernelGGL(adjoint_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st, Dp, parts,
+                     n, D);
+  return hipGetLastError();
 }
 
 int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {

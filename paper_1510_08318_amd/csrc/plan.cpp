@@ -145,6 +145,36 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
   return MOFF_OK;
 }
 
+// Whole antennas to lanes for the fused adjoint's degridding: longest tables
+// first, each to the least-loaded lane with a free slot (ties: lowest lane).
+// Leaves `slots` empty when some antenna finds no free slot.
+void build_adjoint_slots(const HostPlan& P, int NT, std::vector<uint32_t>* slots) {
+  slots->clear();
+  if (P.n_ant > NT * kAdjSlots) return;
+  std::vector<int> order(P.n_ant);
+  std::iota(order.begin(), order.end(), 0);
+  auto taps = [&](int a) { return P.ktype_k[P.ant_ktype[a]] * P.ktype_k[P.ant_ktype[a]]; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return taps(x) > taps(y); });
+  std::vector<long long> load(NT, 0);
+  std::vector<int> used(NT, 0);
+  std::vector<uint32_t> out(static_cast<size_t>(NT) * kAdjSlots * 2, 0);
+  for (size_t i = 0; i < out.size(); i += 2) out[i] = kAdjEmpty;
+  for (int a : order) {
+    int best = -1;
+    for (int l = 0; l < NT; ++l)
+      if (used[l] < kAdjSlots && (best < 0 || load[l] < load[best])) best = l;
+    if (best < 0) return;
+    const int p = P.ant_ktype[a], k = P.ktype_k[p];
+    const size_t at = (static_cast<size_t>(best) * kAdjSlots + used[best]) * 2;
+    out[at] = static_cast<uint32_t>(a) | (static_cast<uint32_t>(P.ktype_off[p]) << 12) |
+              (static_cast<uint32_t>(k) << 24);
+    out[at + 1] = static_cast<uint32_t>(P.ix0[a]) | (static_cast<uint32_t>(P.iy0[a]) << 16);
+    used[best]++;
+    load[best] += taps(a);
+  }
+  *slots = std::move(out);
+}
+
 }  // namespace
 
 uint16_t to_binary16(double x) {
@@ -447,6 +477,7 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
       }
     }
+    build_adjoint_slots(P, S.NT, &V.slots);
     P.variants.push_back(std::move(V));
   }
   if (P.variants.empty()) return fail(why, MOFF_ERR_UNSUPPORTED, "no frame shape for this grid size");

@@ -25,6 +25,13 @@ struct GatherEntry {
 };
 
 constexpr uint32_t kStoreBit = 0x80000000u;
+
+// Antenna slots of the fused adjoint: each lane degrids up to kAdjSlots whole
+// antennas, two words per slot:
+//   w0 bits 0..11 antenna (kAdjEmpty = none), bits 12..23 first tap of its
+//      table, bits 24..27 table side k;   w1 = ix0 | iy0 << 16.
+constexpr int kAdjSlots = 4;
+constexpr uint32_t kAdjEmpty = 0xFFFu;
 constexpr int kMaxAnt = 4000;
 constexpr int kMaxTypes = 4;
 constexpr int kMaxK = 15;
@@ -65,6 +72,7 @@ struct HostPlan {
     std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
     int n_weights() const { return NJ * n_taps_; }
     int n_taps_ = 0;
+    std::vector<uint32_t> slots;             // [NT][kAdjSlots][2]; empty if the antennas do not fit
   };
   std::vector<Variant> variants;
   int max_cell_entries = 0;

@@ -277,3 +277,17 @@ def test_full_size_sampled_channels(torch, moff, cfg, chans):
     assert np.isfinite(got).all()
     ref, pbar = oracle_channels(w, chans)
     assert_image_close(got[chans], ref, pbar, label=f"config{cfg} full")
+
+
+@pytest.mark.parametrize("case", ["config1", "config2_sub", "config5_sub", "hetero_n32_ci4"])
+def test_fused_image_equals_visibility_route(torch, moff, case):
+    """Cross-method check of the device output (Sec. 2: the MOFF image equals the
+    visibility-based image, eq. dirty-image-FX, through eq. e-field-conv): the GPU
+    MOFF image against the oracle's FX route, which correlates antenna pairs,
+    grids each visibility with the cross-correlation of the two placed footprints
+    and transforms once, sharing no step with the MOFF oracle."""
+    w = CASES[case]()
+    got = run_image(torch, moff, w)
+    _, pbar = oracle_channels(w, range(w.geom.n_chan))
+    fx = np.stack([oracle.fx_discrete_image(w.geom, w.E, w.gains, c) for c in range(w.geom.n_chan)])
+    assert_image_close(got, fx, pbar, label=f"{case} vs FX route")
