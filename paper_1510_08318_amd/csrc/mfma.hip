@@ -16,7 +16,7 @@
 // between the stages, W and V once from float64 phase factors); every product
 // accumulates in float32 (v_mfma_f32_32x32x16_{f16,bf16}).
 //
-// One workgroup (2 waves at N = 64, 8 at N = 128) owns one (channel, time
+// One workgroup (2 waves at N = 64, 4 at N = 128) owns one (channel, time
 // slice) and loops over its frames; per frame:
 //   1. ingest + calibration: e = g E into LDS (float32), self power in float64
 //      (the next frame's samples are loaded during this frame's matrix work);
@@ -29,8 +29,10 @@
 //   4. column stage: the same wave owns the same-numbered 32-row block of Y
 //      (and part of its columns), with that block's V operands in registers,
 //      and accumulates |Y|^2 in registers.
-// Two waves per SIMD (8-wave workgroups at N = 128) let one wave's matrix
-// work overlap another's vector and LDS work.
+// Registers are held to 256 per lane so that two workgroups share each CU:
+// their frames drift out of step, and one workgroup's matrix work overlaps the
+// other's gathering and LDS traffic (8-wave workgroups, whose waves meet at the
+// same barriers, were 15 % slower at N = 128).
 // After the last frame the accumulators go through the same epilogue modes as
 // the float32 fused kernel (per-slice partial, running sum, final image).
 //
@@ -159,18 +161,15 @@ void mfma_kernel(MfmaArgs a) {
 
   // Raw samples of the next frame are loaded into registers before the row
   // stage and used after the column stage, so the HBM latency is hidden behind
-  // the matrix work.  The first kPrefetch * NT antennas keep their gain and
-  // their float64 self power in registers (one slot each); antennas beyond
-  // that are loaded, calibrated and typed through LDS when used.
-  constexpr int kPrefetch = N == 128 ? 2 : 4;
-  float2 raw[kPrefetch], gs[kPrefetch];
-  double pws[kPrefetch];
+  // the matrix work.  The first kPrefetch * NT antennas keep their self power
+  // in a register (one slot each); antennas beyond that are loaded when used.
+  // Per-thread self-power sums are float32 (this path's error budget is set by
+  // its 16-bit operands); threads are combined in float64.
+  constexpr int kPrefetch = N == 128 ? 1 : 4;
+  float2 raw[kPrefetch];
+  float pws[kPrefetch];
 #pragma unroll
-  for (int j = 0; j < kPrefetch; ++j) {
-    const int i = tid + j * NT;
-    gs[j] = (a.gains && i < a.n_ant) ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
-    pws[j] = 0.0;
-  }
+  for (int j = 0; j < kPrefetch; ++j) pws[j] = 0.f;
   auto load_raw = [&](int64_t t) {
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
 #pragma unroll
@@ -179,23 +178,23 @@ void mfma_kernel(MfmaArgs a) {
       if (i < a.n_ant) raw[j] = load_sample(a.E, base + i, CI4);
     }
   };
-  double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  float pwt[kMaxTypesDev] = {0.f, 0.f, 0.f, 0.f};
   auto calibrate = [&](int i, float2 x) {
     const float2 v = c_mul(gl[i], x);
     e[i] = v;
-    const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+    const float p = fmaf(v.x, v.x, v.y * v.y);
     const int tp = ty[i];
 #pragma unroll
-    for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+    for (int q = 0; q < kMaxTypesDev; ++q) pwt[q] += (tp == q) ? p : 0.f;
   };
   auto ingest = [&](int64_t t) {
 #pragma unroll
     for (int j = 0; j < kPrefetch; ++j) {
       const int i = tid + j * NT;
       if (i < a.n_ant) {
-        const float2 v = c_mul(gs[j], raw[j]);
+        const float2 v = c_mul(gl[i], raw[j]);
         e[i] = v;
-        pws[j] += static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+        pws[j] += fmaf(v.x, v.x, v.y * v.y);
       }
     }
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
@@ -291,13 +290,16 @@ void mfma_kernel(MfmaArgs a) {
     }
   }
 
+  double pw[kMaxTypesDev];
+#pragma unroll
+  for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = pwt[q];
 #pragma unroll
   for (int j = 0; j < kPrefetch; ++j) {
     const int i = tid + j * NT;
     if (i < a.n_ant) {
       const int tp = ty[i];
 #pragma unroll
-      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? pws[j] : 0.0;
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? static_cast<double>(pws[j]) : 0.0;
     }
   }
   block_sum4<NT>(pw, Atot);

@@ -36,7 +36,7 @@ constexpr FrameShape frame_shape(int N, int V = 0) {
 }
 
 // Waves per workgroup of the reduced-precision (matrix-core) frame transform.
-constexpr int mfma_waves(int N) { return N == 128 ? 8 : 2; }
+constexpr int mfma_waves(int N) { return N == 128 ? 4 : 2; }
 
 // Dynamic-LDS layout of the reduced-precision kernel, byte offsets.  The
 // calibrated samples e[n_ant + 1] (last slot zero) and the kernel taps come

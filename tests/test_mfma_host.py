@@ -56,7 +56,7 @@ def test_mfma_gather_program_replays_oracle_grid(moff, name):
     with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16) as p:
         prog, _, info = p.mfma_tables()
     pitch, base, na = info["row_pitch"], info["grid_base"], w.geom.n_ant
-    assert info["n_threads"] == (512 if N == 128 else 128) and pitch == 2 * L + 8
+    assert info["n_threads"] == (256 if N == 128 else 128) and pitch == 2 * L + 8
     assert base % 16 == 0 and base >= 8 * (na + 1 + len(taps))
     x = prog[..., 0].astype(np.int64)
     y = prog[..., 1].astype(np.int64)
