@@ -180,3 +180,17 @@ def test_uv_rule_flag_validation(moff):
     assert ei.value.status == 1
     with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.AUTOCORR_UV) as p:
         assert p.N == 32
+
+
+def test_host_only_plan_rejects_compute(moff):
+    """A plan built without a device answers compute calls with
+    MOFF_ERR_UNSUPPORTED before touching any device."""
+    from paper_1510_08318_amd import _lib
+    w = synth.make_config(1, n_time=2)
+    with moff.Plan.from_geometry(w.geom, device=-1) as p:
+        L = _lib.lib()
+        dummy = ctypes.c_void_p(16)
+        assert L.moff_image(p.handle, dummy, 2, None, dummy, None) == 4
+        assert L.moff_accumulate(p.handle, dummy, 2, None, dummy, dummy, None) == 4
+        assert L.moff_gain_vjp(p.handle, dummy, 2, None, dummy, dummy, None) == 4
+        assert L.moff_image_staged(p.handle, dummy, 2, None, dummy, None) == 4
