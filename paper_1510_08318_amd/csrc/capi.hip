@@ -157,6 +157,8 @@ struct LaunchConfig {
   int variant, slices, grid;
 };
 
+constexpr int kTuneReps = 4;   // timed calls per autotuner candidate
+
 bool is_mfma(const HostPlan& hp) { return hp.mfma.prec != 0; }
 
 // Work items per time slice, LDS bytes and resident workgroups of a variant.
@@ -743,13 +745,18 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
         const LaunchConfig lc = launch_config(p, n_time);
         result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);   // warm-up
         if (result != MOFF_OK) break;
-        if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
-        for (int rep = 0; rep < 2 && result == MOFF_OK; ++rep)
-          result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);
-        if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
-        if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
-        float ms = 0.f;
-        if (result == MOFF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+        // the fastest of several separately timed calls: near-equal candidates
+        // are then ranked by their undisturbed time, not by one noisy sample
+        float ms = 1e30f;
+        for (int rep = 0; rep < kTuneReps && result == MOFF_OK; ++rep) {
+          if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK) result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);
+          if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
+          float one = 0.f;
+          if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK) ms = std::min(ms, one);
+        }
         if (result == MOFF_OK && ms < best) {
           best = ms;
           bv = v;
