@@ -144,14 +144,20 @@ def cpu_baseline(w, budget_s=10.0):
 
 
 def image_errors(img, ref_images):
-    """Per sampled channel: err_inf = max|dI| / max|Pbar|, err_2 = ||dI|| / ||Pbar||."""
+    """Per sampled channel (one image each): err_inf = max|dI| / max|Pbar| and
+    err_2 = ||dI|| / ||Pbar||, reported per image (3 significant digits) and as
+    maxima over the sample."""
     import numpy as np
-    out = []
+    chans, e_inf, e_2 = [], [], []
     for c, ref, pbar in ref_images:
         d = img[c].astype(np.float64) - ref
-        out.append({"channel": c, "err_inf": float(np.abs(d).max() / np.abs(pbar).max()),
-                    "err_2": float(np.linalg.norm(d) / np.linalg.norm(pbar))})
-    return out
+        chans.append(int(c))
+        e_inf.append(float(np.abs(d).max() / np.abs(pbar).max()))
+        e_2.append(float(np.linalg.norm(d) / np.linalg.norm(pbar)))
+    sig = lambda v: float(f"{v:.3g}")
+    return {"images": len(chans), "channels": f"{chans[0]}-{chans[-1]}" if chans else "",
+            "err_inf_max": sig(max(e_inf)) if e_inf else None, "err_2_max": sig(max(e_2)) if e_2 else None,
+            "err_inf": [sig(v) for v in e_inf], "err_2": [sig(v) for v in e_2]}
 
 
 def time_plan(plan, E, gains, out, steps, warmup, tune):
