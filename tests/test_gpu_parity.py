@@ -291,3 +291,53 @@ def test_fused_image_equals_visibility_route(torch, moff, case):
     _, pbar = oracle_channels(w, range(w.geom.n_chan))
     fx = np.stack([oracle.fx_discrete_image(w.geom, w.E, w.gains, c) for c in range(w.geom.n_chan)])
     assert_image_close(got, fx, pbar, label=f"{case} vs FX route")
+
+
+def _replay_matches(torch, call, out):
+    """Capture `call(stream)` (which writes `out`) in a graph after one eager call,
+    then replay it three times with eager work and synchronisation in between;
+    every replay must reproduce the eager result exactly."""
+    call(torch.cuda.current_stream())          # allocates any workspace before capture
+    torch.cuda.synchronize()
+    eager = out.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            call(s)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        out.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), f"replay {rep} differs"
+    return eager
+
+
+@pytest.mark.parametrize("kind", ["mfma_f16", "uv_rule", "gain_adjoint"])
+def test_graph_replay_other_paths(torch, moff, kind):
+    """The matrix-core image, the uv-plane rule (zero fill, fused kernel, per-channel
+    finalisation) and the fused gain adjoint (kernel, reductions, final pass)
+    captured in HIP graphs: every replay equals the eager call."""
+    if kind == "mfma_f16":
+        w = synth.make_config(4, n_time=12, n_chan=3, grid_n=64)
+        flags = synth.MFMA_F16
+    elif kind == "uv_rule":
+        w = synth.make_config(2, n_time=12, n_chan=3)
+        flags = synth.AUTOCORR_UV
+    else:
+        w = synth.make_config(5, n_time=4, n_chan=2)
+        flags = 0
+    C, N = w.geom.n_chan, w.geom.grid_n
+    with moff.Plan.from_geometry(w.geom, device=0, extra_flags=flags) as p:
+        E = to_dev(torch, w.E)
+        g = to_dev(torch, w.gains) if w.gains is not None else None
+        if kind == "gain_adjoint":
+            R = torch.randn((C, N, N), dtype=torch.float32, device="cuda:0")
+            out = torch.empty((C, w.geom.n_ant), dtype=torch.complex64, device="cuda:0")
+            _replay_matches(torch, lambda st: p.gain_vjp(E, g, R, out=out, stream=st), out)
+        else:
+            out = torch.empty((C, N, N), dtype=torch.float32, device="cuda:0")
+            _replay_matches(torch, lambda st: p.image(E, g, out=out, stream=st), out)
