@@ -26,8 +26,14 @@
  *     on the plan's device, owned by the caller, at least 16-byte aligned.
  *   - Calls enqueue work on `hip_stream` (a hipStream_t, NULL = default stream)
  *     and return without synchronising; argument validation is synchronous.
- *   - A plan is immutable after creation; it owns its device tables and a
- *     workspace, so concurrent calls must use different plans.
+ *   - A plan's tables are fixed at creation; its only mutable state is the
+ *     launch configuration (moff_plan_autotune / moff_plan_set_config), the
+ *     timing switch and a device workspace, so concurrent calls must use
+ *     different plans.
+ *   - The workspace grows on demand: a call that needs more than the plan holds
+ *     synchronises the device and allocates.  Under stream (graph) capture, make
+ *     one eager call of the same shape first; captured calls then allocate
+ *     nothing and record no memset nodes (buffers are cleared by a kernel).
  *   - On any error status the contents of output buffers are unspecified.
  *   - NaN / Inf inputs propagate; they are not checked.
  */
