@@ -93,31 +93,23 @@ void free_device(moff_plan p) {
   if (p->ev1) (void)hipEventDestroy(p->ev1);
 }
 
-moff_status ensure_workspace(moff_plan p, size_t bytes) {
-  if (bytes <= p->ws_bytes) return MOFF_OK;
-  if (p->d_ws) {
+// Grow a plan-owned device buffer to at least `bytes` (contents are not kept;
+// the device is synchronised before an old buffer is released).
+moff_status grow(void** buf, size_t* have, size_t bytes) {
+  if (bytes <= *have) return MOFF_OK;
+  if (*buf) {
     (void)hipDeviceSynchronize();
-    (void)hipFree(p->d_ws);
-    p->d_ws = nullptr;
-    p->ws_bytes = 0;
+    (void)hipFree(*buf);
+    *buf = nullptr;
+    *have = 0;
   }
-  if (hipMalloc(&p->d_ws, bytes) != hipSuccess) return MOFF_ERR_NOMEM;
-  p->ws_bytes = bytes;
+  if (hipMalloc(buf, bytes) != hipSuccess) return MOFF_ERR_NOMEM;
+  *have = bytes;
   return MOFF_OK;
 }
 
-moff_status ensure_aux(moff_plan p, size_t bytes) {
-  if (bytes <= p->aux_bytes) return MOFF_OK;
-  if (p->d_aux) {
-    (void)hipDeviceSynchronize();
-    (void)hipFree(p->d_aux);
-    p->d_aux = nullptr;
-    p->aux_bytes = 0;
-  }
-  if (hipMalloc(&p->d_aux, bytes) != hipSuccess) return MOFF_ERR_NOMEM;
-  p->aux_bytes = bytes;
-  return MOFF_OK;
-}
+moff_status ensure_workspace(moff_plan p, size_t bytes) { return grow(&p->d_ws, &p->ws_bytes, bytes); }
+moff_status ensure_aux(moff_plan p, size_t bytes) { return grow(&p->d_aux, &p->aux_bytes, bytes); }
 
 moff_status hip_status(hipError_t e) { return e == hipSuccess ? MOFF_OK : MOFF_ERR_HIP; }
 
