@@ -76,7 +76,12 @@ enum {
                               values up to 65504 in magnitude; components below 2^-14
                               lose relative precision.  Error against the exact image:
                               of order 2^-11 relative to the image peak (stated bound
-                              16 * 2^-11 on max|dI| / max(S/T)). */
+                              16 * 2^-11 on max|dI| / max(S/T)).  The kernel keeps two
+                              buffers of samples, grid and row-stage output in LDS, so
+                              at grid_n 128 it takes about 2100 antennas (fewer with
+                              large tables); beyond that, or when the sample and tap
+                              offsets exceed 16 bits, plan creation returns
+                              MOFF_ERR_UNSUPPORTED. */
   MOFF_MFMA_BF16 = 16,     /* as MOFF_MFMA_F16 with bfloat16 (float32 range, 8-bit
                               significand; stated bound 16 * 2^-8). At most one of the
                               two MFMA flags may be set. */
@@ -191,28 +196,33 @@ moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w,
 
 /*
  * Tables of the reduced-precision (MOFF_MFMA_*) path, for host-side tests.
- * Sizes first (any pointer may be NULL): prog_len entries per thread,
- * n_threads threads, row_pitch 16-bit elements per grid row, grid_base the
- * LDS byte offset of the 16-bit aperture grid, dft_len 16-bit words of
- * phase-factor operands.
+ * Sizes first (any pointer may be NULL): prog_len entries per lane,
+ * n_threads gather lanes (the lanes of the kernel's gather waves; its matrix
+ * waves come on top), row_pitch 16-bit elements per grid row, grid_base the
+ * LDS byte offset of the first of the two 16-bit aperture grids, dft_len
+ * 16-bit words of phase-factor operands.
  *   prog : uint32 [prog_len][n_threads][2] gather entries (x, y) over the
- *          non-empty aperture cells (iy, ix), in LDS byte offsets: x low half =
- *          8 * antenna (8 * n_ant is an all-zero slot), x high half =
- *          8 * (n_ant + 1 + tap) (kernel taps of all types back to back);
+ *          non-empty aperture cells (iy, ix), in LDS byte offsets into the
+ *          first sample buffer and grid: x low half = 8 * antenna
+ *          (8 * n_ant is an all-zero slot), x high half =
+ *          16 * (n_ant + 1) + 8 * tap (kernel taps of all types back to back,
+ *          after two buffers of n_ant + 1 samples);
  *          y = 0, or on the last entry of a cell y = grid_base +
  *          2 * (iy * row_pitch + ix), where the cell's real part is stored (its
  *          imaginary part is grid_n / 2 elements further on).
- *   dft  : uint16 [2][grid_n / 32][grid_n / 16][2][64][8] binary16 or bfloat16
- *          bit patterns, indexed [stage][block][k-step][re/im][lane][slot]:
- *          stage 0 = row transform, exp(+2 pi i ix (q - N/2) / N) / (N/2) at
- *          column q = 32 block + lane % 32 and contraction index
- *          kk = 16 k-step + 8 (lane / 32) + slot (kk < N/2: real-part rows,
- *          ix = kk; else imaginary-part rows, ix = kk - N/2); stage 1 = column
- *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 block + lane % 32
- *          and iy from kk likewise.  With w the phase factor at (kk mod N/2):
- *          re/im = 0 holds Re w for kk < N/2 and -Im w above; re/im = 1 holds
- *          Im w below and Re w above, so that [Re x | Im x] times the two blocks
- *          gives Re and Im of the complex product.
+ *   dft  : uint16 [2][grid_n / 64][grid_n / 32][2][64][8] binary16 or bfloat16
+ *          bit patterns, indexed [stage][base block][k-step][part][lane][slot],
+ *          for the base half (index n < grid_n / 2) of each transform; the
+ *          other half follows by conjugation (column grid_n - n of the row
+ *          transform is the conjugate of column n, and likewise for rows of
+ *          the column transform).  Stage 0 = row transform
+ *          exp(+2 pi i ix (q - N/2) / N) / (N/2) at column q = 32 block +
+ *          lane % 32 and ix = 16 k-step + 8 (lane / 32) + slot; stage 1 = column
+ *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 block +
+ *          lane % 32 and iy likewise.  Part 0 holds the real part, part 1 the
+ *          imaginary part, except at n = 0, where part 0 holds the (real) phase
+ *          vector of n - N/2 = -N/2 and part 1 that of n - N/2 = 0 (all ones),
+ *          each with the stage's scale.
  * MOFF_ERR_UNSUPPORTED if the plan has no MFMA flag.
  */
 moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft, int32_t* prog_len,

@@ -119,7 +119,7 @@ struct GradFinalArgs {
 struct MfmaArgs {
   const void* E;               // [T][C][n_ant] c64 or ci4
   const float2* gains;         // [C][n_ant] or nullptr
-  const GatherEntry* prog;     // [prog_len][NT]
+  const GatherEntry* prog;     // [prog_len][gather lanes]
   int prog_len;
   int prog_in_lds;             // copy the program into LDS (mfma_prog_fits_lds)
   const float2* ktab;          // [n_taps] kernel taps, all types back to back
@@ -137,7 +137,6 @@ struct MfmaArgs {
   int mode;
 };
 
-constexpr size_t kMfmaProgLdsLimit = 80 * 1024;   // keeps two workgroups' LDS within one CU
 size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds);
 bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len);
 int mfma_threads(int N);

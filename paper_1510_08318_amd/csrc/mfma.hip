@@ -3,45 +3,56 @@
 // For grids of 64 and 128 the padded 2-D DFT of Sec. 3 is computed as two
 // dense complex matrix products (Sec. 6.1 counts the transform as the dominant
 // cost; at these sizes the contraction is small enough to run as plain matrix
-// products):
+// products), over the L = N/2 nonzero rows and columns of the zero-padded grid:
 //
-//   row stage     Z[iy][q] = sum_ix Eg[iy][ix] W[ix][q],  W[ix][q] = exp(+2 pi i ix (q - N/2) / N) / (N/2)
-//   column stage  Y[r][q]  = sum_iy V[r][iy] Z[iy][q],    V[r][iy] = exp(+2 pi i iy (r - N/2) / N)
+//   row stage     Z[iy][q] = sum_ix Eg[iy][ix] W[ix][q],  W[ix][q] = w^(ix (q - L)) / L
+//   column stage  Y[r][q]  = sum_iy V[r][iy] Z[iy][q],    V[r][iy] = w^(iy (r - L))
 //
-// over the L = N/2 nonzero rows and columns of the zero-padded grid, so the
-// outputs come out directly in image pixel order (index N/2 is the phase
-// centre).  Each complex product is one real product of doubled contraction
-// length: [Re x | Im x] times [[Re w, Im w], [-Im w, Re w]] gives [Re, Im] of
-// x w.  Operands are binary16 or bfloat16 (Eg rounded once when gridded, Z once
-// between the stages, W and V once from float64 phase factors); every product
-// accumulates in float32 (v_mfma_f32_32x32x16_{f16,bf16}).
+// with w = exp(2 pi i / N), so outputs come out in image pixel order (index L
+// is the phase centre).  Phase vectors come in conjugate pairs: the column
+// q' = N - q of W is the conjugate of column q, and likewise for the rows of V.
+// Each stage therefore runs only over its base half (q < L, r < L): with the
+// four real products
+//   P1 = Re x . Re u,  P2 = Im x . Im u,  P3 = Re x . Im u,  P4 = Im x . Re u
+// of the data x and the base phase vector u, the base output is
+// (P1 - P2) + i (P3 + P4) and its partner's is (P1 + P2) + i (P4 - P3): half the
+// matrix work of the plain complex product.  The two real self-conjugate
+// vectors (q - L = -L, alternating signs, and q - L = 0, all ones) share the
+// slot of index 0 as real and imaginary part, which gives them directly as
+// P1 + i P4 and P3 + i P2.
 //
-// One workgroup (2 waves at N = 64, 4 at N = 128) owns one (channel, time
-// slice) and loops over its frames; per frame:
-//   1. ingest + calibration: e = g E into LDS (float32), self power in float64
-//      (the next frame's samples are loaded during this frame's matrix work);
-//   2. gather-gridding: each lane walks its balanced slice of the cell-keyed
-//      program (no atomics) and stores finished cells as 16-bit values;
-//   3. row stage: each wave owns a 32-column block of Z (and part of its
-//      rows), with that block's W operands held in registers for the whole
-//      launch and Eg read from LDS; Z is written to LDS transposed
-//      (column-major), the layout the column stage reads;
-//   4. column stage: the same wave owns the same-numbered 32-row block of Y
-//      (and part of its columns), with that block's V operands in registers,
-//      and accumulates |Y|^2 in registers.
-// Registers are held to 256 per lane so that two workgroups share each CU:
-// their frames drift out of step, and one workgroup's matrix work overlaps the
-// other's gathering and LDS traffic (8-wave workgroups, whose waves meet at the
-// same barriers, were 15 % slower at N = 128).
-// After the last frame the accumulators go through the same epilogue modes as
-// the float32 fused kernel (per-slice partial, running sum, final image).
+// Operands are binary16 or bfloat16 (Eg rounded once when gridded, Z once
+// between the stages, phase factors once from float64); every product
+// accumulates in float32 (v_mfma_f32_32x32x16_{f16,bf16}).  The squared
+// magnitudes accumulate as S = P1^2 + P2^2 + P3^2 + P4^2 and D = P3 P4 - P1 P2,
+// so that base = S + 2 D and partner = S - 2 D (the shared slot takes S at
+// half weight and its own D).
+//
+// One workgroup owns one (channel, time slice) and streams its frames through
+// a three-deep pipeline.  Its waves have two roles:
+//   * gather waves (3 at N = 64, 4 at N = 128) ingest and calibrate frame j
+//     (e = g E into LDS as float32, self power per antenna) and grid frame
+//     j - 1: each lane walks its balanced slice of the cell-keyed program (no
+//     atomics) and stores finished cells as 16-bit values;
+//   * matrix waves (1 at N = 64, 4 at N = 128) run the column stage of frame
+//     j - 3 and the row stage of frame j - 2, each with the phase factors of
+//     its tiles held in registers for the whole launch.  Z goes through LDS
+//     transposed (column-major), the layout the column stage reads; |Y|^2
+//     accumulates in registers.
+// The samples, the grid and Z are double-buffered, so one barrier per frame
+// orders every hand-over, and the matrix pipes stay busy while the gather
+// waves, which share the SIMDs with the matrix waves, do their latency-bound
+// work.  After the last frame the accumulators go through the same epilogue
+// modes as the float32 fused kernel (per-slice partial, running sum, final
+// image).
 //
 // MFMA operand layout (32x32x16, checked on the device): lane l supplies
 // A[l % 32][8 (l / 32) + i] and B[8 (l / 32) + i][l % 32], i < 8, and receives
 // D[8 (j / 4) + 4 (l / 32) + j % 4][l % 32] in accumulator j < 16.
 //
-// LDS rows are 2L + 8 sixteen-bit elements long: the 16-byte operand reads of
-// eight consecutive rows then fall in eight different 16-byte bank groups.
+// LDS rows are 2L + 8 sixteen-bit elements long (real parts, then imaginary
+// parts): the 16-byte operand reads of eight consecutive rows then fall in
+// eight different 16-byte bank groups.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -76,29 +87,36 @@ __device__ __forceinline__ f32x16 mfma32<__bf16>(Vec<__bf16>::v8 a, Vec<__bf16>:
 template <int N>
 struct MfmaShape {
   static constexpr int L = N / 2;
-  static constexpr int NW = mfma_waves(N); // waves per workgroup
-  static constexpr int NT = NW * 64;
-  static constexpr int KS = L / 8;         // 16-deep steps over the doubled contraction 2L
-  static constexpr int NB = N / 32;        // output blocks: row-stage column blocks = column-stage row blocks
-  static constexpr int WPB = NW / NB;      // waves sharing one output block
-  static constexpr int RBW = L / 32 / WPB; // row stage: 32-row blocks per wave
-  static constexpr int CBW = NB / WPB;     // column stage: 32-column blocks per wave
-  static_assert(NW % NB == 0 && RBW >= 1 && CBW >= 1, "wave split must tile both stages");
-  static constexpr int PITCH = 2 * L + 8;  // LDS row length, 16-bit elements
-  static constexpr int EG = L * PITCH;     // Eg [L][PITCH]: real parts at ix, imaginary at L + ix
-  static constexpr int ZT = N * PITCH;     // Zt [N][PITCH]: Zt[q][iy] = Re Z, Zt[q][L + iy] = Im Z
+  static constexpr int NW = mfma_waves(N);          // matrix waves
+  static constexpr int NG = mfma_gather_waves(N);   // gather waves
+  static constexpr int NTG = NG * 64;               // gather lanes: the program's width
+  static constexpr int NT = (NW + NG) * 64;         // threads per workgroup
+  static constexpr int KS = L / 16;                 // 16-deep steps over a contraction of L
+  static constexpr int NRB = L / 32;                // base blocks of 32 (row-stage columns, column-stage rows)
+  static constexpr int NIB = L / 32;                // row-stage blocks of 32 grid rows
+  static constexpr int NQB = N / 32;                // column-stage blocks of 32 output columns
+  static constexpr int CTW = NRB * NQB / NW;        // column-stage tiles per matrix wave
+  static_assert(NIB * NRB == NW, "one row-stage tile per matrix wave");
+  static_assert(CTW * NW == NRB * NQB && NQB % CTW == 0, "column-stage tiles of a wave share one base block");
+  static constexpr int PITCH = 2 * L + 8;           // LDS row length, 16-bit elements
+  static constexpr int EG = L * PITCH;              // one Eg [L][PITCH]: real parts at ix, imaginary at L + ix
+  static constexpr int ZT = N * PITCH;              // one Zt [N][PITCH]: Zt[q][iy] = Re Z, Zt[q][L + iy] = Im Z
 };
+
+// LDS the program may take: at N = 128 one workgroup fills a compute unit (its
+// registers allow no second one); at N = 64 two workgroups share one.
+constexpr size_t mfma_prog_lds_limit(int N) { return N == 128 ? kMfmaLdsMax : kMfmaLdsMax / 2; }
 
 }  // namespace
 
 size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds) {
   const MfmaLayout m = mfma_layout(N, n_taps, n_ant);
-  const size_t prog = prog_in_lds ? sizeof(GatherEntry) * static_cast<size_t>(prog_len) * (mfma_waves(N) * 64) : 0;
+  const size_t prog = prog_in_lds ? sizeof(GatherEntry) * static_cast<size_t>(prog_len) * (mfma_gather_waves(N) * 64) : 0;
   return static_cast<size_t>(m.prog) + prog;
 }
 
 bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len) {
-  return mfma_lds_bytes(N, n_taps, n_ant, prog_len, true) <= kMfmaProgLdsLimit;
+  return mfma_lds_bytes(N, n_taps, n_ant, prog_len, true) <= mfma_prog_lds_limit(N);
 }
 
 template <int N, class H, bool CI4>
@@ -107,126 +125,287 @@ void mfma_kernel(MfmaArgs a) {
   using S = MfmaShape<N>;
   using V8 = typename Vec<H>::v8;
   using V4 = typename Vec<H>::v4;
-  constexpr int NT = S::NT, L = S::L, KS = S::KS, PITCH = S::PITCH;
+  constexpr int NT = S::NT, NTG = S::NTG, L = S::L, KS = S::KS, PITCH = S::PITCH, CTW = S::CTW;
   extern __shared__ uint4 lds_mfma[];
   __shared__ double Atot[kMaxTypesDev];
+  __shared__ double pw_part[S::NG][kMaxTypesDev];   // self power per gather wave and table type
   char* lds = reinterpret_cast<char*>(lds_mfma);
   const MfmaLayout lay = mfma_layout(N, a.n_taps, a.n_ant);
-  float2* e = reinterpret_cast<float2*>(lds + lay.e);   // [n_ant + 1], last slot stays zero
   float2* K = reinterpret_cast<float2*>(lds + lay.k);   // [n_taps]
-  H* Eg = reinterpret_cast<H*>(lds + lay.eg);
-  H* Zt = reinterpret_cast<H*>(lds + lay.zt);
+  H* Eg = reinterpret_cast<H*>(lds + lay.eg);           // [2][EG]
+  H* Zt = reinterpret_cast<H*>(lds + lay.zt);           // [2][ZT]
   float2* gl = reinterpret_cast<float2*>(lds + lay.gl); // [n_ant]
   int* ty = reinterpret_cast<int*>(lds + lay.ty);       // [n_ant]
-  // gather program [prog_len][NT], copied into LDS when it fits
+  // gather program [prog_len][NTG], copied into LDS when it fits
   GatherEntry* lprog = reinterpret_cast<GatherEntry*>(lds + lay.prog);
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  // wave w owns output block blk (its row-stage columns and column-stage rows)
-  // and part sub of that block's other dimension
-  const int blk = w / S::WPB, sub = w % S::WPB;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave index, uniform per wave
   const int item = blockIdx.x;
   if (item >= a.n_chan * a.slices) return;
   const int c = item % a.n_chan;
   const int slice = item / a.n_chan;
 
-  // phase-factor operands of this wave, resident for the whole launch
-  V8 w_re[KS], w_im[KS], v_re[KS], v_im[KS];
-  {
-    const V8* src = reinterpret_cast<const V8*>(a.dft);
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-      w_re[ks] = src[(((0 * S::NB + blk) * KS + ks) * 2 + 0) * 64 + lane];
-      w_im[ks] = src[(((0 * S::NB + blk) * KS + ks) * 2 + 1) * 64 + lane];
-      v_re[ks] = src[(((1 * S::NB + blk) * KS + ks) * 2 + 0) * 64 + lane];
-      v_im[ks] = src[(((1 * S::NB + blk) * KS + ks) * 2 + 1) * 64 + lane];
-    }
-  }
-
-  // clear the aperture grid once: cells without antennas are never written
-  for (int i = tid; i < S::EG * 2 / 16; i += NT) reinterpret_cast<uint4*>(Eg)[i] = make_uint4(0u, 0u, 0u, 0u);
+  // both grids cleared once: cells without antennas are never written
+  for (int i = tid; i < 2 * S::EG * 2 / 16; i += NT) reinterpret_cast<uint4*>(Eg)[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < a.n_taps; i += NT) K[i] = a.ktab[i];
   for (int i = tid; i < a.n_ant; i += NT) {
     ty[i] = a.ant_type[i];
     gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
   }
-  if (tid == 0) e[a.n_ant] = make_float2(0.f, 0.f);
+  if (tid < 2) reinterpret_cast<float2*>(lds + lay.e + tid * lay.e_stride)[a.n_ant] = make_float2(0.f, 0.f);
   if (a.prog_in_lds)
-    for (int i = tid; i < a.prog_len * NT; i += NT) lprog[i] = a.prog[i];
+    for (int i = tid; i < a.prog_len * NTG; i += NT) lprog[i] = a.prog[i];
 
   const int64_t T = a.n_time;
   const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
-  const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
-  const GatherEntry* prog = (a.prog_in_lds ? lprog : a.prog) + tid;
-
-  // Raw samples of the next frame are loaded into registers before the row
-  // stage and used after the column stage, so the HBM latency is hidden behind
-  // the matrix work.  The first kPrefetch * NT antennas keep their self power
-  // in a register (one slot each); antennas beyond that are loaded when used.
-  // Per-thread self-power sums are float32 (this path's error budget is set by
-  // its 16-bit operands); threads are combined in float64.
-  constexpr int kPrefetch = N == 128 ? 1 : 4;
-  float2 raw[kPrefetch];
-  float pws[kPrefetch];
-#pragma unroll
-  for (int j = 0; j < kPrefetch; ++j) pws[j] = 0.f;
-  auto load_raw = [&](int64_t t) {
-    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
-      const int i = tid + j * NT;
-      if (i < a.n_ant) raw[j] = load_sample(a.E, base + i, CI4);
-    }
-  };
-  float pwt[kMaxTypesDev] = {0.f, 0.f, 0.f, 0.f};
-  auto calibrate = [&](int i, float2 x) {
-    const float2 v = c_mul(gl[i], x);
-    e[i] = v;
-    const float p = fmaf(v.x, v.x, v.y * v.y);
-    const int tp = ty[i];
-#pragma unroll
-    for (int q = 0; q < kMaxTypesDev; ++q) pwt[q] += (tp == q) ? p : 0.f;
-  };
-  auto ingest = [&](int64_t t) {
-#pragma unroll
-    for (int j = 0; j < kPrefetch; ++j) {
-      const int i = tid + j * NT;
-      if (i < a.n_ant) {
-        const float2 v = c_mul(gl[i], raw[j]);
-        e[i] = v;
-        pws[j] += fmaf(v.x, v.x, v.y * v.y);
-      }
-    }
-    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-    for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) calibrate(i, load_sample(a.E, base + i, CI4));
-  };
-
-  float acc[S::CBW][16];
-#pragma unroll
-  for (int cb = 0; cb < S::CBW; ++cb)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) acc[cb][j] = 0.f;
+  const int64_t nf = t1 - t0;
+  // iteration j: gather waves ingest frame j and grid frame j - 1; matrix
+  // waves run the column stage of frame j - 3 and the row stage of frame j - 2
+  const int64_t n_iter = nf > 0 ? nf + 3 : 0;
   const int row = lane & 31, half = lane >> 5;
   __syncthreads();   // tables in LDS
-  if (t0 < t1) load_raw(t0);
-  for (int64_t t = t0; t < t1; ++t) {
-    // 1. ingest + calibration (samples loaded during the previous frame); e[] was
-    //    last read by the previous frame's gather, finished before its row stage
-    ingest(t);
-    __syncthreads();
 
-    // 2. gather-gridding into 16-bit cells
+  if (w < S::NW) {
+    // ---- matrix waves ----
+    // row-stage tile: grid rows 32 ib .. +32, base columns 32 qb .. +32
+    const int ib = w % S::NIB, qb = w / S::NIB;
+    // column-stage tiles: base rows 32 rb .. +32, output column blocks qc0 .. qc0 + CTW - 1
+    const int rb = (w * CTW) / S::NQB, qc0 = (w * CTW) % S::NQB;
+    // phase factors (real, imaginary part) of both tiles, resident for the whole launch
+    V8 wc[KS], wd[KS], vc[KS], vd[KS];
     {
+      const V8* src = reinterpret_cast<const V8*>(a.dft);
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        wc[ks] = src[(((0 * S::NRB + qb) * KS + ks) * 2 + 0) * 64 + lane];
+        wd[ks] = src[(((0 * S::NRB + qb) * KS + ks) * 2 + 1) * 64 + lane];
+        vc[ks] = src[(((1 * S::NRB + rb) * KS + ks) * 2 + 0) * 64 + lane];
+        vd[ks] = src[(((1 * S::NRB + rb) * KS + ks) * 2 + 1) * 64 + lane];
+      }
+    }
+    // index 0 of a base block 0 is the shared slot of the two real phase vectors
+    const bool sp_col = qb == 0 && row == 0;   // row stage: this lane's column q = 0
+    const bool sp_row = rb == 0 && half == 0;  // column stage: accumulator 0 is row r = 0
+    const float s_col = sp_col ? 0.f : 1.f;
+    const int q_base = 32 * qb + row;
+    const int q_part = sp_col ? L : N - q_base;
+    // S in acc_s, D in acc_d: base = S + 2 D, partner = S - 2 D.  For the shared
+    // slot (lanes with sp_row, accumulator 0) S is taken at half weight and D
+    // as (P1^2 + P4^2 - P2^2 - P3^2) / 4, which makes the same two formulas give
+    // |P1 + i P4|^2 and |P3 + i P2|^2.
+    float acc_s[CTW][16], acc_d[CTW][16];
+#pragma unroll
+    for (int t = 0; t < CTW; ++t)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc_s[t][j] = acc_d[t][j] = 0.f;
+    // Each stage walks its steps as one stream with the LDS operands read
+    // kRing steps (of four matrix products each) ahead of their use.
+    constexpr int kRing = 1;
+    static_assert(kRing <= KS * CTW && kRing <= KS, "operand ring deeper than the stream");
+
+    for (int64_t j = 0; j < n_iter; ++j) {
+      if (j >= 3) {
+        // column stage of frame j - 3: B operands Re Z, Im Z from LDS, A = V in registers
+        const H* zt = Zt + ((j - 3) & 1) * S::ZT;
+        constexpr int NS = CTW * KS;
+        auto b_src = [&](int u, int part) {
+          return reinterpret_cast<const V8*>(zt + (32 * (qc0 + u / KS) + row) * PITCH + part * L + 16 * (u % KS) +
+                                             8 * half);
+        };
+        V8 ra[kRing], rb_[kRing];
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+          ra[u] = *b_src(u, 0);
+          rb_[u] = *b_src(u, 1);
+        }
+        f32x16 p1 = {}, p2 = {}, p3 = {}, p4 = {};
+#pragma unroll
+        for (int u = 0; u < NS; ++u) {
+          const int ks = u % KS;
+          const V8 za = ra[u % kRing], zb = rb_[u % kRing];
+          if (u + kRing < NS) {
+            ra[u % kRing] = *b_src(u + kRing, 0);
+            rb_[u % kRing] = *b_src(u + kRing, 1);
+          }
+          p1 = mfma32<H>(vc[ks], za, p1);
+          p2 = mfma32<H>(vd[ks], zb, p2);
+          p3 = mfma32<H>(vd[ks], za, p3);
+          p4 = mfma32<H>(vc[ks], zb, p4);
+          __builtin_amdgcn_sched_barrier(0);
+          if (ks == KS - 1) {
+            const int t = u / KS;
+            {
+              // accumulator 0 may be the shared slot: base |P1 + i P4|^2, partner |P3 + i P2|^2
+              const float sq = fmaf(p1[0], p1[0], fmaf(p2[0], p2[0], fmaf(p3[0], p3[0], p4[0] * p4[0])));
+              const float d = fmaf(p3[0], p4[0], -p1[0] * p2[0]);
+              const float ds = 0.25f * (fmaf(p1[0], p1[0], p4[0] * p4[0]) - fmaf(p2[0], p2[0], p3[0] * p3[0]));
+              acc_s[t][0] = fmaf(sp_row ? 0.5f : 1.f, sq, acc_s[t][0]);
+              acc_d[t][0] += sp_row ? ds : d;
+            }
+#pragma unroll
+            for (int k = 1; k < 16; ++k) {
+              acc_s[t][k] = fmaf(p1[k], p1[k], fmaf(p2[k], p2[k], fmaf(p3[k], p3[k], fmaf(p4[k], p4[k], acc_s[t][k]))));
+              acc_d[t][k] = fmaf(p3[k], p4[k], fmaf(-p1[k], p2[k], acc_d[t][k]));
+            }
+            p1 = f32x16{};
+            p2 = f32x16{};
+            p3 = f32x16{};
+            p4 = f32x16{};
+          }
+        }
+      }
+      if (j >= 2 && j - 2 < nf) {
+        // row stage of frame j - 2: A operands Re Eg, Im Eg from LDS, B = W in registers
+        const H* eg = Eg + ((j - 2) & 1) * S::EG;
+        H* zt = Zt + ((j - 2) & 1) * S::ZT;
+        auto a_src = [&](int ks, int part) {
+          return reinterpret_cast<const V8*>(eg + (32 * ib + row) * PITCH + part * L + 16 * ks + 8 * half);
+        };
+        V8 ra[kRing], rb_[kRing];
+#pragma unroll
+        for (int u = 0; u < kRing; ++u) {
+          ra[u] = *a_src(u, 0);
+          rb_[u] = *a_src(u, 1);
+        }
+        f32x16 p1 = {}, p2 = {}, p3 = {}, p4 = {};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+          const V8 ea = ra[ks % kRing], eb = rb_[ks % kRing];
+          if (ks + kRing < KS) {
+            ra[ks % kRing] = *a_src(ks + kRing, 0);
+            rb_[ks % kRing] = *a_src(ks + kRing, 1);
+          }
+          p1 = mfma32<H>(ea, wc[ks], p1);
+          p2 = mfma32<H>(eb, wd[ks], p2);
+          p3 = mfma32<H>(ea, wd[ks], p3);
+          p4 = mfma32<H>(eb, wc[ks], p4);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+        // lane holds grid rows iy = 32 ib + 8 g + 4 half + (0..3) of base column
+        // q_base and of its partner q_part
+        H* zb = zt + q_base * PITCH + 32 * ib + 4 * half;
+        H* zp = zt + q_part * PITCH + 32 * ib + 4 * half;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          V4 br, bi, pr, pi;
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            br[i] = static_cast<H>(fmaf(-s_col, p2[k], p1[k]));
+            bi[i] = static_cast<H>(fmaf(s_col, p3[k], p4[k]));
+            pr[i] = static_cast<H>(sp_col ? p3[k] : p1[k] + p2[k]);
+            pi[i] = static_cast<H>(sp_col ? p2[k] : p4[k] - p3[k]);
+          }
+          *reinterpret_cast<V4*>(zb + 8 * g) = br;
+          *reinterpret_cast<V4*>(zb + 8 * g + L) = bi;
+          *reinterpret_cast<V4*>(zp + 8 * g) = pr;
+          *reinterpret_cast<V4*>(zp + 8 * g + L) = pi;
+        }
+      }
+      __syncthreads();
+    }
+    __syncthreads();   // self-power partials of the gather waves are in LDS
+    if (tid < kMaxTypesDev) {
+      double s = 0.0;
+      for (int g = 0; g < S::NG; ++g) s += pw_part[g][tid];
+      Atot[tid] = s;
+    }
+    __syncthreads();   // Atot complete (the gather waves take part in every barrier)
+
+    // epilogue: the row stage carried a factor 1 / L, so |Y|^2 is scaled back by L^2 (exact)
+    const size_t img_stride = static_cast<size_t>(N) * N;
+    constexpr float kBack = static_cast<float>(L) * static_cast<float>(L);
+    auto put = [&](int r, int q, float v) {
+      const size_t pix = static_cast<size_t>(r) * N + q;
+      const float s = v * kBack;
+      if (a.mode == kModePartial) {
+        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = s;
+      } else if (a.mode == kModeAccum) {
+        a.out[static_cast<size_t>(c) * img_stride + pix] += s;
+      } else {
+        double x = s;
+        if (a.subtract)
+          for (int p = 0; p < a.n_types; ++p) x -= Atot[p] * a.Pp[p * img_stride + pix];
+        a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(x * a.scale);
+      }
+    };
+#pragma unroll
+    for (int t = 0; t < CTW; ++t)
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const int r = 32 * rb + 8 * (k / 4) + 4 * half + (k % 4);
+        const int q = 32 * (qc0 + t) + row;
+        const int rp = r == 0 ? L : N - r;
+        put(r, q, fmaf(2.f, acc_d[t][k], acc_s[t][k]));
+        put(rp, q, fmaf(-2.f, acc_d[t][k], acc_s[t][k]));
+      }
+    if (tid < a.n_types) {
+      if (a.mode == kModePartial) {
+        a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
+      } else if (a.mode == kModeAccum) {
+        a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
+      }
+    }
+  } else {
+    // ---- gather waves ----
+    const int gt = tid - S::NW * 64;   // gather lane, 0 .. NTG - 1 (the matrix waves come first)
+    const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
+    // Raw samples of the next frame are loaded one iteration ahead, so the
+    // HBM latency is hidden behind this iteration's gridding.  The first
+    // kPrefetch * NTG antennas keep their self power in a register (one slot
+    // each); antennas beyond that are loaded when used.  Per-lane self-power
+    // sums are float32 (this path's error budget is set by its 16-bit
+    // operands); lanes are combined in float64.
+    constexpr int kPrefetch = 4;
+    float2 raw[kPrefetch];
+    float pws[kPrefetch];
+#pragma unroll
+    for (int q = 0; q < kPrefetch; ++q) pws[q] = 0.f;
+    float pwt[kMaxTypesDev] = {0.f, 0.f, 0.f, 0.f};
+    auto load_raw = [&](int64_t t) {
+      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        const int i = gt + q * NTG;
+        if (i < a.n_ant) raw[q] = load_sample(a.E, base + i, CI4);
+      }
+    };
+    auto ingest = [&](int64_t t, float2* e) {
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        const int i = gt + q * NTG;
+        if (i < a.n_ant) {
+          const float2 v = c_mul(gl[i], raw[q]);
+          e[i] = v;
+          pws[q] += fmaf(v.x, v.x, v.y * v.y);
+        }
+      }
+      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+      for (int i = gt + kPrefetch * NTG; i < a.n_ant; i += NTG) {
+        const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+        e[i] = v;
+        const float p = fmaf(v.x, v.x, v.y * v.y);
+        const int tp = ty[i];
+#pragma unroll
+        for (int q = 0; q < kMaxTypesDev; ++q) pwt[q] += (tp == q) ? p : 0.f;
+      }
+    };
+    // entry: x = byte offsets of e[ant] (low half, buffer 0) and K[tap] (high
+    // half), y = byte address of the finished cell's real part in grid 0, or 0.
+    // The program pointer is either LDS or global memory, never a select of
+    // the two: a pointer of unknown address space compiles to flat loads, whose
+    // waits also drain the (in-order) global-load counter and so would stall
+    // every batch on the next frame's samples.
+    auto gather = [&](const GatherEntry* prog, int eoff, int goff) {
       float2 g = make_float2(0.f, 0.f);
-      // entry: x = byte offsets of e[ant] (low half) and K[tap] (high half),
-      // y = byte address of the finished cell's real part, or 0
       auto step = [&](GatherEntry en) {
-        const float2 ev = *reinterpret_cast<const float2*>(lds + (en.x & 0xFFFFu));
+        const float2 ev = *reinterpret_cast<const float2*>(lds + eoff + (en.x & 0xFFFFu));
         const float2 kv = *reinterpret_cast<const float2*>(lds + (en.x >> 16));
         g.x = fmaf(ev.x, kv.x, fmaf(-ev.y, kv.y, g.x));
         g.y = fmaf(ev.x, kv.y, fmaf(ev.y, kv.x, g.y));
         if (en.y != 0u) {
-          H* cell = reinterpret_cast<H*>(lds + en.y);
+          H* cell = reinterpret_cast<H*>(lds + goff + en.y);
           cell[0] = static_cast<H>(g.x);
           cell[L] = static_cast<H>(g.y);
           g = make_float2(0.f, 0.f);
@@ -236,102 +415,91 @@ void mfma_kernel(MfmaArgs a) {
       for (; k + 4 <= a.prog_len; k += 4) {
         GatherEntry en[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) en[i] = prog[static_cast<size_t>(k + i) * NT];
+        for (int i = 0; i < 4; ++i) en[i] = prog[static_cast<size_t>(k + i) * NTG];
 #pragma unroll
         for (int i = 0; i < 4; ++i) step(en[i]);
       }
-      for (; k < a.prog_len; ++k) step(prog[static_cast<size_t>(k) * NT]);
-    }
-    __syncthreads();
-    if (t + 1 < t1) load_raw(t + 1);
+      for (; k < a.prog_len; ++k) step(prog[static_cast<size_t>(k) * NTG]);
+    };
 
-    // 3. row stage: Z = Eg W for the 32 output columns of block blk
+    // The program does not change from frame to frame: when it is short
+    // enough, each lane keeps its entries and their tap values in registers
+    // (the matrix waves set the register allocation, so the gather waves have
+    // room), and a frame costs one batch of sample reads from LDS.
+    constexpr int kProgRegs = 16;
+    const bool prog_in_regs = a.prog_len <= kProgRegs;
+    uint32_t r_e[kProgRegs], r_cell[kProgRegs];
+    float2 r_k[kProgRegs];
+    if (prog_in_regs) {
 #pragma unroll
-    for (int i_rb = 0; i_rb < S::RBW; ++i_rb) {
-      const int rb = sub * S::RBW + i_rb;
-      f32x16 zr = {}, zi = {};
-      const H* arow = Eg + (32 * rb + row) * PITCH + 8 * half;
-#pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const V8 av = *reinterpret_cast<const V8*>(arow + 16 * ks);
-        zr = mfma32<H>(av, w_re[ks], zr);
-        zi = mfma32<H>(av, w_im[ks], zi);
+      for (int k = 0; k < kProgRegs; ++k) {
+        GatherEntry en = {static_cast<uint32_t>(lay.e + 8 * a.n_ant) | (static_cast<uint32_t>(lay.k) << 16), 0u};
+        if (k < a.prog_len) en = a.prog_in_lds ? lprog[k * NTG + gt] : a.prog[static_cast<size_t>(k) * NTG + gt];
+        r_e[k] = en.x & 0xFFFFu;
+        r_cell[k] = en.y;
+        r_k[k] = *reinterpret_cast<const float2*>(lds + (en.x >> 16));
       }
-      // lane holds rows iy = 32 rb + 8 g + 4 half + (0..3) of column q = 32 blk + row
-      H* zcol = Zt + (32 * blk + row) * PITCH + 32 * rb + 4 * half;
+    }
+    // Entries past the program's end are padding (the zero sample, no store),
+    // so the loops have no trip-count branches.
+    auto gather_regs = [&](int eoff, int goff) {
+      float2 ev[kProgRegs];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        V4 vr, vi;
+      for (int k = 0; k < kProgRegs; ++k) ev[k] = *reinterpret_cast<const float2*>(lds + eoff + r_e[k]);
+      float2 g = make_float2(0.f, 0.f);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          vr[i] = static_cast<H>(zr[4 * g + i]);
-          vi[i] = static_cast<H>(zi[4 * g + i]);
+      for (int k = 0; k < kProgRegs; ++k) {
+        g.x = fmaf(ev[k].x, r_k[k].x, fmaf(-ev[k].y, r_k[k].y, g.x));
+        g.y = fmaf(ev[k].x, r_k[k].y, fmaf(ev[k].y, r_k[k].x, g.y));
+        if (r_cell[k] != 0u) {
+          H* cell = reinterpret_cast<H*>(lds + goff + r_cell[k]);
+          cell[0] = static_cast<H>(g.x);
+          cell[L] = static_cast<H>(g.y);
+          g = make_float2(0.f, 0.f);
         }
-        *reinterpret_cast<V4*>(zcol + 8 * g) = vr;
-        *reinterpret_cast<V4*>(zcol + 8 * g + L) = vi;
+      }
+    };
+
+    // The samples of frame j + 1 are requested after frame j - 1 is gridded,
+    // so no wait of the gridding covers them.
+    if (nf > 0) load_raw(t0);
+    for (int64_t j = 0; j < n_iter; ++j) {
+      if (j < nf) ingest(t0 + j, reinterpret_cast<float2*>(lds + lay.e + (j & 1) * lay.e_stride));
+      if (j >= 1 && j - 1 < nf) {
+        const int eoff = ((j - 1) & 1) * lay.e_stride, goff = ((j - 1) & 1) * lay.eg_stride;
+        if (prog_in_regs)
+          gather_regs(eoff, goff);
+        else if (a.prog_in_lds)
+          gather(lprog + gt, eoff, goff);
+        else
+          gather(a.prog + gt, eoff, goff);
+      }
+      if (j + 1 < nf) load_raw(t0 + j + 1);
+      __syncthreads();
+    }
+
+    // self power per table type: lanes in float64, then one partial per wave
+    double pw[kMaxTypesDev];
+#pragma unroll
+    for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = pwt[q];
+#pragma unroll
+    for (int q = 0; q < kPrefetch; ++q) {
+      const int i = gt + q * NTG;
+      if (i < a.n_ant) {
+        const int tp = ty[i];
+#pragma unroll
+        for (int p = 0; p < kMaxTypesDev; ++p) pw[p] += (tp == p) ? static_cast<double>(pws[q]) : 0.0;
       }
     }
-    __syncthreads();
-
-    // 4. column stage: Y = V Z for the 32 output rows of block blk, |Y|^2 accumulated
 #pragma unroll
-    for (int i_cb = 0; i_cb < S::CBW; ++i_cb) {
-      const int cb = sub * S::CBW + i_cb;
-      f32x16 yr = {}, yi = {};
-      const H* bcol = Zt + (32 * cb + row) * PITCH + 8 * half;
+    for (int p = 0; p < kMaxTypesDev; ++p) {
+      double x = pw[p];
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        const V8 bv = *reinterpret_cast<const V8*>(bcol + 16 * ks);
-        yr = mfma32<H>(v_re[ks], bv, yr);
-        yi = mfma32<H>(v_im[ks], bv, yi);
-      }
-#pragma unroll
-      for (int j = 0; j < 16; ++j) acc[i_cb][j] = fmaf(yr[j], yr[j], fmaf(yi[j], yi[j], acc[i_cb][j]));
+      for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+      if (lane == 0) pw_part[w - S::NW][p] = x;
     }
-  }
-
-  double pw[kMaxTypesDev];
-#pragma unroll
-  for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = pwt[q];
-#pragma unroll
-  for (int j = 0; j < kPrefetch; ++j) {
-    const int i = tid + j * NT;
-    if (i < a.n_ant) {
-      const int tp = ty[i];
-#pragma unroll
-      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? static_cast<double>(pws[j]) : 0.0;
-    }
-  }
-  block_sum4<NT>(pw, Atot);
-
-  // epilogue: the row stage carried a factor 1 / L, so |Y|^2 is scaled back by L^2 (exact)
-  const size_t img_stride = static_cast<size_t>(N) * N;
-  constexpr float kBack = static_cast<float>(L) * static_cast<float>(L);
-#pragma unroll
-  for (int i_cb = 0; i_cb < S::CBW; ++i_cb)
-#pragma unroll
-    for (int j = 0; j < 16; ++j) {
-      const int r = 32 * blk + 8 * (j / 4) + 4 * half + (j % 4);
-      const int q = 32 * (sub * S::CBW + i_cb) + row;
-      const size_t pix = static_cast<size_t>(r) * N + q;
-      const float s = acc[i_cb][j] * kBack;
-      if (a.mode == kModePartial) {
-        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = s;
-      } else if (a.mode == kModeAccum) {
-        a.out[static_cast<size_t>(c) * img_stride + pix] += s;
-      } else {
-        double v = s;
-        if (a.subtract)
-          for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
-        a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
-      }
-    }
-  if (tid < a.n_types) {
-    if (a.mode == kModePartial) {
-      a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
-    } else if (a.mode == kModeAccum) {
-      a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
-    }
+    __syncthreads();   // partials visible to the matrix waves
+    __syncthreads();   // matrix waves have read them (Atot)
   }
 }
 

@@ -74,17 +74,22 @@ long long balanced_split(const std::vector<int>& cost, int lanes) {
   return lo;
 }
 
-// Tables of the reduced-precision transform: the gather program over the
-// non-empty aperture cells (the LDS grid is cleared once per workgroup, so empty
-// cells are never written) and the phase-factor operands of both DFT stages in
-// the register order of the kernel.  The row stage is scaled by 1 / (N/2), a
-// power of two, so that its rounded output cannot exceed the largest gridded
-// value; the kernel multiplies |Y|^2 back by (N/2)^2 exactly.
+// Tables of the reduced-precision (matrix-core) path.  The gather program is
+// the cell-keyed CSR split into balanced per-lane slices for the gather waves,
+// encoded in LDS byte offsets.  The phase-factor operands are those of the
+// base half of each transform: the row stage's output columns q < N/2 and the
+// column stage's output rows r < N/2, whose partners N - q and N - r follow by
+// conjugation.  Index 0 carries the two real self-conjugate phase vectors
+// (q - N/2 = -N/2 and 0) as real and imaginary part of one slot.  Values are
+// correctly rounded from float64 to binary16 or bfloat16, laid out in the
+// register order of the kernel.  The row stage is scaled by 1 / (N/2), a power
+// of two, so that its rounded output cannot exceed the largest gridded value;
+// the kernel multiplies |Y|^2 back by (N/2)^2 exactly.
 moff_status build_mfma_tables(HostPlan& P, std::string* why) {
-  const int N = P.N, L = P.L, NB = N / 32, KS = L / 8;
+  const int N = P.N, L = P.L, NRB = L / 32, KS = L / 16;
   HostPlan::Mfma& T = P.mfma;
   T.prec = (P.flags & MOFF_MFMA_BF16) ? 2 : 1;
-  T.NT = mfma_waves(N) * 64;
+  T.NT = mfma_gather_waves(N) * 64;   // gather lanes
   T.pitch = mfma_layout(N, P.n_taps, P.n_ant).pitch;
   std::vector<int> cells, cost;
   for (int i = 0; i < L * L; ++i) {
@@ -98,6 +103,8 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
   if (B > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
   if (mfma_layout(N, P.n_taps, P.n_ant).eg > 0xFFFF)
     return fail(why, MOFF_ERR_UNSUPPORTED, "too many antennas and taps for the gather encoding");
+  if (mfma_layout(N, P.n_taps, P.n_ant).prog > kMfmaLdsMax)
+    return fail(why, MOFF_ERR_UNSUPPORTED, "too many antennas for the matrix-core kernel's LDS");
   T.prog_len = static_cast<int>(B);
   const MfmaLayout lay = mfma_layout(N, P.n_taps, P.n_ant);
   T.grid_base = lay.eg;
@@ -124,23 +131,31 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
     T.prog[static_cast<size_t>(k - 1) * T.NT + lane].y = static_cast<uint32_t>(lay.eg + 2 * (iy * T.pitch + ix));
   }
 
+  // [stage][base block][k-step][part][lane][slot]: stage 0 = row transform, the
+  // B operand W[ix][q] at contraction index ix = 16 k-step + 8 (lane / 32) + slot
+  // and column q = 32 block + lane % 32; stage 1 = column transform, the A
+  // operand V[r][iy] at row r = 32 block + lane % 32 and iy likewise.  Part 0
+  // holds the real, part 1 the imaginary part; at q = 0 (r = 0) they hold the
+  // real phase vectors of q - N/2 = -N/2 and of q - N/2 = 0.
   auto enc = [&](double v) { return T.prec == 2 ? to_bfloat16(v) : to_binary16(v); };
-  T.dft.assign(static_cast<size_t>(2) * NB * KS * 2 * 64 * 8, 0);
+  T.dft.assign(static_cast<size_t>(2) * NRB * KS * 2 * 64 * 8, 0);
   const double s1 = 1.0 / L;
   for (int st = 0; st < 2; ++st)
-    for (int w = 0; w < NB; ++w)
+    for (int b = 0; b < NRB; ++b)
       for (int ks = 0; ks < KS; ++ks)
-        for (int ri = 0; ri < 2; ++ri)
+        for (int part = 0; part < 2; ++part)
           for (int ln = 0; ln < 64; ++ln)
             for (int i = 0; i < 8; ++i) {
-              const int kk = 16 * ks + 8 * (ln / 32) + i;
-              const int n = 32 * w + ln % 32;   // output column q (stage 0) or row r (stage 1)
-              const int j = kk % L;              // ix (stage 0) or iy (stage 1)
-              const bool upper = kk >= L;        // imaginary-part rows of the contraction
-              std::complex<double> f = unit_root(static_cast<long long>(j) * (n - N / 2), N);
+              const int j = 16 * ks + 8 * (ln / 32) + i;   // ix (stage 0) or iy (stage 1)
+              const int n = 32 * b + ln % 32;              // base column q (stage 0) or row r (stage 1)
+              std::complex<double> f;
+              if (n == 0)
+                f = std::complex<double>(unit_root(static_cast<long long>(j) * (-L), N).real(), 1.0);
+              else
+                f = unit_root(static_cast<long long>(j) * (n - L), N);
               if (st == 0) f *= s1;
-              const double v = ri == 0 ? (upper ? -f.imag() : f.real()) : (upper ? f.real() : f.imag());
-              T.dft[((((static_cast<size_t>(st) * NB + w) * KS + ks) * 2 + ri) * 64 + ln) * 8 + i] = enc(v);
+              const double v = part == 0 ? f.real() : f.imag();
+              T.dft[((((static_cast<size_t>(st) * NRB + b) * KS + ks) * 2 + part) * 64 + ln) * 8 + i] = enc(v);
             }
   return MOFF_OK;
 }

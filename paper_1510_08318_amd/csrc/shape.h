@@ -35,17 +35,24 @@ constexpr FrameShape frame_shape(int N, int V = 0) {
                   : FrameShape{};
 }
 
-// Waves per workgroup of the reduced-precision (matrix-core) frame transform.
-constexpr int mfma_waves(int N) { return N == 128 ? 4 : 2; }
+// Waves per workgroup of the reduced-precision (matrix-core) frame transform:
+// matrix waves run the two transform stages, gather waves ingest and grid.
+constexpr int mfma_waves(int N) { return N == 128 ? 4 : 1; }
+constexpr int mfma_gather_waves(int N) { return N == 128 ? 4 : 3; }
 
-// Dynamic-LDS layout of the reduced-precision kernel, byte offsets.  The
-// calibrated samples e[n_ant + 1] (last slot zero) and the kernel taps come
-// first so that gather entries can address them with 16-bit byte offsets; the
-// 16-bit grid Eg [N/2][pitch] and the transposed row-stage output Zt [N][pitch]
-// follow, then per-antenna gains and types, then (optionally) the program.
+// LDS of one compute unit, the most one workgroup can take.
+constexpr int kMfmaLdsMax = 160 * 1024;
+
+// Dynamic-LDS layout of the reduced-precision kernel, byte offsets.  The two
+// buffers of calibrated samples e[n_ant + 1] (last slot zero) and the kernel
+// taps come first so that gather entries can address them with 16-bit byte
+// offsets; the two 16-bit grids Eg [N/2][pitch] and the two transposed
+// row-stage outputs Zt [N][pitch] follow, then per-antenna gains and types,
+// then (optionally) the program.  Gather entries address buffer 0; buffer 1
+// of each pair lies one *_stride further on.
 struct MfmaLayout {
   int pitch;   // 16-bit elements per Eg / Zt row
-  int e, k, eg, zt, gl, ty, prog;
+  int e, e_stride, k, eg, eg_stride, zt, zt_stride, gl, ty, prog;
 };
 
 constexpr int align_up(int x, int a) { return (x + a - 1) / a * a; }
@@ -55,10 +62,13 @@ constexpr MfmaLayout mfma_layout(int N, int n_taps, int n_ant) {
   MfmaLayout m{};
   m.pitch = pitch;
   m.e = 0;
-  m.k = 8 * (n_ant + 1);
+  m.e_stride = 8 * (n_ant + 1);
+  m.k = 2 * m.e_stride;
   m.eg = align_up(m.k + 8 * n_taps, 16);
-  m.zt = m.eg + 2 * L * pitch;
-  m.gl = m.zt + 2 * N * pitch;
+  m.eg_stride = 2 * L * pitch;
+  m.zt = m.eg + 2 * m.eg_stride;
+  m.zt_stride = 2 * N * pitch;
+  m.gl = m.zt + 2 * m.zt_stride;
   m.ty = m.gl + 8 * n_ant;
   m.prog = align_up(m.ty + 4 * n_ant, 16);
   return m;

@@ -43,9 +43,9 @@ def close(got, w, channels, tol=TOL, tol_2=None):
         assert ei <= tol and e2 <= tol_2, (c, ei, e2)
 
 
-def max_antennas(N, cell):
+def max_antennas(N, cell, n_ant=4000):
     rng = np.random.default_rng(40)
-    return synth.random_case(41, 4000, N, 2, 3, [synth.random_kernel(rng, 3), synth.random_kernel(rng, 1)],
+    return synth.random_case(41, n_ant, N, 2, 3, [synth.random_kernel(rng, 3), synth.random_kernel(rng, 1)],
                              extent_m=(N // 2 - 4) * cell, cell_m=cell)
 
 
@@ -61,8 +61,12 @@ def test_max_antennas_fused_staged_tuned(torch, moff):
         close(o.cpu().numpy(), w, [0, 1])
 
 
-def test_max_antennas_reduced_precision(torch, moff):
-    w = max_antennas(128, 0.8)
+@pytest.mark.parametrize("N,n_ant", [(64, 4000), (128, 2000)])
+def test_max_antennas_reduced_precision(torch, moff, N, n_ant):
+    """The matrix-core kernel double-buffers the samples, the grid and the
+    transposed row-stage output in LDS: every count the plan accepts runs on
+    the 64 grid, and on the 128 grid about 2100 antennas fit (these tables)."""
+    w = max_antennas(N, 0.8 if N == 128 else 1.6, n_ant)
     with moff.Plan.from_geometry(w.geom, device=0, extra_flags=synth.MFMA_BF16) as p:
         got = p.image(dev(torch, w.E), dev(torch, w.gains))
         torch.cuda.synchronize()

@@ -130,12 +130,13 @@ def test_mfma_image_vs_oracle(torch, moff, case):
 def test_mfma_slicing_and_accumulate(torch, moff):
     """Time slices (per-slice partial sums + ordered reduction) and split
     accumulation agree with one pass to float32 rounding: the transform of a
-    frame does not depend on how frames are grouped."""
+    frame does not depend on how frames are grouped.  Slices of one and two
+    frames run the kernel's frame pipeline shorter than its depth."""
     w = synth.make_config(4, n_time=9, n_chan=3, grid_n=64)
     flag = synth.MFMA_F16
     base = run_image(torch, moff, w, flag, slices=1)
     scale = np.abs(base).max()
-    for sl in (2, 3, 9):
+    for sl in (2, 3, 4, 5, 9):
         got = run_image(torch, moff, w, flag, slices=sl)
         assert np.abs(got - base).max() <= 1e-5 * scale, sl
     import torch as t
@@ -163,7 +164,7 @@ def test_mfma_autotune(torch, moff):
     with moff.Plan.from_geometry(w.geom, device=0, extra_flags=synth.MFMA_F16) as p:
         E = to_dev(torch, w.E)
         cfg = p.autotune(E)
-        assert cfg["tuned"] and cfg["threads"] == 128 and cfg["n_variants"] == 1
+        assert cfg["tuned"] and cfg["threads"] == 256 and cfg["n_variants"] == 1   # 2 matrix + 2 gather waves
         out = p.image(E)
         torch.cuda.synchronize()
         img = out.cpu().numpy()

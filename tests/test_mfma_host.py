@@ -30,6 +30,22 @@ def _case(name):
     return synth.make_config(5, n_time=1, n_chan=1, grid_n=128)
 
 
+def test_lds_bound_on_antennas(moff):
+    """On the 128 grid the double-buffered LDS layout bounds the antenna count:
+    4000 antennas are rejected at plan creation (MOFF_ERR_UNSUPPORTED), 2000 fit."""
+    rng = np.random.default_rng(40)
+    tabs = [synth.random_kernel(rng, 3), synth.random_kernel(rng, 1)]
+    for n_ant, ok in ((4000, False), (2000, True)):
+        w = synth.random_case(41, n_ant, 128, 1, 2, tabs, extent_m=60 * 0.8, cell_m=0.8)
+        if ok:
+            with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16):
+                pass
+        else:
+            with pytest.raises(moff.MoffError) as ei:
+                moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16)
+            assert ei.value.status == 4
+
+
 def test_plan_validation(moff):
     w = synth.make_config(1, n_time=2)       # grid_n 32
     with pytest.raises(moff.MoffError) as ei:
@@ -56,13 +72,13 @@ def test_mfma_gather_program_replays_oracle_grid(moff, name):
     with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16) as p:
         prog, _, info = p.mfma_tables()
     pitch, base, na = info["row_pitch"], info["grid_base"], w.geom.n_ant
-    assert info["n_threads"] == (256 if N == 128 else 128) and pitch == 2 * L + 8
-    assert base % 16 == 0 and base >= 8 * (na + 1 + len(taps))
+    assert info["n_threads"] == (256 if N == 128 else 192) and pitch == 2 * L + 8   # gather lanes
+    assert base % 16 == 0 and base >= 8 * (2 * (na + 1) + len(taps))
     x = prog[..., 0].astype(np.int64)
     y = prog[..., 1].astype(np.int64)
     eoff, koff = x & 0xFFFF, x >> 16
     assert (eoff % 8 == 0).all() and (koff % 8 == 0).all()
-    ant, tap = eoff // 8, koff // 8 - (na + 1)
+    ant, tap = eoff // 8, koff // 8 - 2 * (na + 1)   # taps follow two sample buffers
     st = y != 0
     assert ant.max() <= na and tap.min() >= 0 and tap.max() < len(taps)
     slot = (y - base) // 2
@@ -99,15 +115,46 @@ def _phase(j, n, N):
 
 
 def _expected_operands(N):
-    """float64 [2, N/32, N/16, 2, 64, 8] operand values by their definition."""
-    L, NW, KS = N // 2, N // 32, N // 16
-    st, wv, ks, ri, ln, i = np.meshgrid(np.arange(2), np.arange(NW), np.arange(KS), np.arange(2), np.arange(64),
-                                        np.arange(8), indexing="ij")
-    kk = 16 * ks + 8 * (ln // 32) + i
-    n = 32 * wv + ln % 32
-    f = _phase(kk % L, n, N) * np.where(st == 0, 1.0 / L, 1.0)
-    upper = kk >= L
-    return np.where(ri == 0, np.where(upper, -f.imag, f.real), np.where(upper, f.real, f.imag))
+    """float64 [2, N/64, N/32, 2, 64, 8] operand values by their definition: the
+    base half (index n < N/2) of each transform's phase vectors, real part then
+    imaginary part; index 0 carries the two real self-conjugate vectors, of
+    n - N/2 = -N/2 (real part) and of n - N/2 = 0 (imaginary part)."""
+    L, NRB, KS = N // 2, N // 64, N // 32
+    st, b, ks, part, ln, i = np.meshgrid(np.arange(2), np.arange(NRB), np.arange(KS), np.arange(2), np.arange(64),
+                                         np.arange(8), indexing="ij")
+    j = 16 * ks + 8 * (ln // 32) + i
+    n = 32 * b + ln % 32
+    f = _phase(j, n, N)
+    shared = _phase(j, 0, N).real + 1j * _phase(j, L, N).real
+    f = np.where(n == 0, shared, f) * np.where(st == 0, 1.0 / L, 1.0)
+    return np.where(part == 0, f.real, f.imag)
+
+
+def test_conjugate_pairs_give_the_full_transform():
+    """The pairing the tables rely on, checked in float64 on a random input: the
+    four real products of the base half reproduce the full complex matrix
+    product for the base rows, their conjugate partners N - n, and the two real
+    self-conjugate rows through the shared slot."""
+    rng = np.random.default_rng(5)
+    for N in (64, 128):
+        L = N // 2
+        j = np.arange(L)
+        full = np.stack([_phase(j, n, N) for n in range(N)])                 # [n][j]
+        x = rng.standard_normal(L) + 1j * rng.standard_normal(L)
+        want = full @ x
+        ops = _expected_operands(N)[1]                                       # column stage, scale 1
+        u = np.zeros((L, L), complex)
+        for b in range(N // 64):
+            for ks in range(N // 32):
+                for ln in range(64):
+                    for i in range(8):
+                        u[32 * b + ln % 32, 16 * ks + 8 * (ln // 32) + i] = ops[b, ks, 0, ln, i] + 1j * ops[b, ks, 1, ln, i]
+        P1, P2 = u.real @ x.real, u.imag @ x.imag
+        P3, P4 = u.imag @ x.real, u.real @ x.imag
+        base, part = (P1 - P2) + 1j * (P3 + P4), (P1 + P2) + 1j * (P4 - P3)
+        assert np.allclose(base[1:], want[1:L], atol=1e-9)
+        assert np.allclose(part[1:], want[N - np.arange(1, L)], atol=1e-9)
+        assert np.isclose(P1[0] + 1j * P4[0], want[0]) and np.isclose(P3[0] + 1j * P2[0], want[L])
 
 
 def _bf16_decode(bits):
