@@ -35,7 +35,7 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "028d480c28856ed9"
+TRAFFIC_SOURCES_SHA = "3199dbac259337b4"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
     (2, "f32", 0, 256): (32945, 16384),
@@ -57,14 +57,14 @@ TRAFFIC_KIB = {
     (2, "f32", 1, 2048): (16594, 131136),
     (2, "f32", 1, 4096): (16598, 262272),
     (2, "f32", 1, 8192): (16594, 524544),
-    (4, "f16", 0, 128): (129564, 8192),
-    (4, "f16", 0, 256): (128957, 16393),
-    (4, "f16", 0, 512): (128961, 32784),
-    (4, "f16", 0, 1024): (129855, 65568),
-    (4, "f16", 0, 1536): (130538, 98352),
-    (4, "f16", 0, 2048): (131112, 131136),
-    (4, "f16", 0, 4096): (130815, 262272),
-    (4, "f16", 0, 8192): (129610, 524544),
+    (4, "f16", 0, 128): (129218, 8192),
+    (4, "f16", 0, 256): (128546, 16392),
+    (4, "f16", 0, 512): (128758, 32785),
+    (4, "f16", 0, 768): (128971, 49176),
+    (4, "f16", 0, 1024): (129183, 65569),
+    (4, "f16", 0, 2048): (129631, 131136),
+    (4, "f16", 0, 4096): (129609, 262272),
+    (4, "f16", 0, 8192): (130448, 524544),
 }
 
 
@@ -102,9 +102,17 @@ def frame_flops(N, nnz):
 
 
 def mfma_frame_flops(N):
-    """Matrix-core work per frame of the dense-DFT path: the row stage multiplies
-    an L x 2L real block by 2L x 2N ([Re | Im] of N columns), the column stage a
-    2N x 2L block by 2L x N, with L = N / 2: 8 L N (L + N) flops."""
+    """Matrix-core work per frame of the reduced-precision path, L = N / 2.  Each
+    stage runs over the base half of its phase vectors (the other half are
+    their conjugates) as four real products: the row stage 4 x (L x L by L x L),
+    the column stage 4 x (L x L by L x N), 8 L^2 (L + N) flops."""
+    L = N // 2
+    return 8 * L * L * (L + N)
+
+
+def dense_dft_frame_flops(N):
+    """The same transform as plain complex matrix products over the padded grid's
+    nonzero half (no conjugate pairing): 8 L N (L + N) flops, L = N / 2."""
     L = N // 2
     return 8 * L * N * (L + N)
 
@@ -253,6 +261,7 @@ def main():
     else:
         extra["mfma_flops_per_frame"] = mfma_frame_flops(N)
         achieved = mfma_frame_flops(N) * frames / (k_ms / 1e3) / 1e12
+        extra["dense_dft_equivalent_tflops"] = round(dense_dft_frame_flops(N) * frames / (k_ms / 1e3) / 1e12, 1)
         roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_MFMA_16BIT_TFLOPS, "unit": "TFLOP/s",
                     "frac": achieved / PEAK_MFMA_16BIT_TFLOPS, "traffic": traffic}
         plan32 = moff.Plan.from_geometry(w.geom, device=0)
