@@ -49,12 +49,17 @@ def to_dev(torch, a):
 
 
 def oracle_channels(w, channels):
+    """Oracle images and the reference scale of the error metric, Pbar = S / T,
+    carrying the image's own pair normalisation 1 / (N_a (N_a - 1)) when that
+    flag is set (Sec. 4), so the metric is relative to the image's scale."""
     P = oracle.plan(w.geom)
+    na = w.geom.n_ant
+    norm = 1.0 / (na * (na - 1)) if int(w.geom.flags) & synth.NORM_PAIRS else 1.0
     imgs, pbar = [], []
     for c in channels:
         img, parts = oracle.moff_channel(w.geom, w.E, w.gains, c, P, keep=True)
         imgs.append(img)
-        pbar.append(parts["S"] / w.E.shape[0])
+        pbar.append(parts["S"] / w.E.shape[0] * norm)
     return np.stack(imgs), np.stack(pbar)
 
 

@@ -36,12 +36,16 @@ def dev(torch, a):
 
 
 def oracle_uv(w, channels):
+    """Oracle images and the error metric's reference scale Pbar = S / T, with
+    the image's pair normalisation 1 / (N_a (N_a - 1)) when that flag is set."""
     P = oracle.plan(w.geom)
+    na = w.geom.n_ant
+    norm = 1.0 / (na * (na - 1)) if int(w.geom.flags) & synth.NORM_PAIRS else 1.0
     imgs, pbars = [], []
     for c in channels:
         img, parts = uv_autocorr.uv_channel(w.geom, w.E, w.gains, c, P, keep=True)
         imgs.append(img)
-        pbars.append(parts["Pbar"])
+        pbars.append(parts["Pbar"] * norm)
     return np.stack(imgs), np.stack(pbars)
 
 
