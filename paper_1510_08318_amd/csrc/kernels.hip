@@ -34,17 +34,24 @@ __device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
 // Gather-gridding of one frame into the folded grid: each lane walks its slice
 // of the cell-keyed program, multiplies the calibrated antenna field by the
 // tap weight, and stores each finished cell sum.  Every folded cell is written.
-template <int NT>
+// The program sits in global memory (L2-resident: it is the same for every
+// frame), so its entries are read B at a time in one batch of loads, not one
+// dependent round trip per few entries; entries past the program's end read as
+// padding (the zero sample, no store), so the batch has no trip-count branches.
+template <int NT, int B>
 __device__ __forceinline__ void gather_frame(const GatherEntry* __restrict__ prog, int prog_len,
-                                             const float2* e, const float2* W, float2* G) {
+                                             const float2* e, const float2* W, float2* G, uint32_t zero_entry) {
   float2 acc = make_float2(0.f, 0.f);
-  int k = 0;
-  for (; k + 4 <= prog_len; k += 4) {
-    GatherEntry ent[4];
+  for (int k0 = 0; k0 < prog_len; k0 += B) {
+    GatherEntry ent[B];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ent[i] = prog[static_cast<size_t>(k + i) * NT];
+    for (int i = 0; i < B; ++i) {
+      const int k = min(k0 + i, prog_len - 1);
+      ent[i] = prog[static_cast<size_t>(k) * NT];
+      if (k0 + i >= prog_len) ent[i].x = zero_entry;
+    }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < B; ++i) {
       const float2 ev = e[ent[i].x & 0xFFFu];
       const float2 wv = W[(ent[i].x >> 12) & 0x7FFu];
       acc.x = fmaf(ev.x, wv.x, fmaf(-ev.y, wv.y, acc.x));
@@ -55,17 +62,16 @@ __device__ __forceinline__ void gather_frame(const GatherEntry* __restrict__ pro
       }
     }
   }
-  for (; k < prog_len; ++k) {
-    const GatherEntry en = prog[static_cast<size_t>(k) * NT];
-    const float2 ev = e[en.x & 0xFFFu];
-    const float2 wv = W[(en.x >> 12) & 0x7FFu];
-    acc.x = fmaf(ev.x, wv.x, fmaf(-ev.y, wv.y, acc.x));
-    acc.y = fmaf(ev.x, wv.y, fmaf(ev.y, wv.x, acc.y));
-    if (en.x & kStoreBit) {
-      G[en.y] = acc;
-      acc = make_float2(0.f, 0.f);
-    }
-  }
+}
+
+// Entries per batch of program reads.  At N = 128 the program (about 20
+// entries per lane) fits one batch, and the registers it takes are free during
+// the gridding (the transform's temporaries are not live then).  Elsewhere
+// batches of 4 measured faster: at N = 256 the programs are 70-90 entries long
+// and large batches raised register pressure in kernels already at 256 VGPRs.
+template <int N>
+constexpr int gather_batch() {
+  return N == 128 ? 24 : 4;
 }
 
 }  // namespace
@@ -137,7 +143,7 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
         for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
       }
       __syncthreads();
-      gather_frame<NT>(prog, a.prog_len, e, W, G);
+      gather_frame<NT, gather_batch<N>()>(prog, a.prog_len, e, W, G, static_cast<uint32_t>(a.n_ant));
       __syncthreads();
       row_stage<N, V>(G, twr, fin);
       __syncthreads();
@@ -246,7 +252,7 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void adjoint_fused_kernel(AdjFusedA
       Er[s] = ant != kAdjEmpty ? load_sample(a.E, base + ant, CI4) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    gather_frame<NT>(prog, a.prog_len, e, W, G);
+    gather_frame<NT, gather_batch<N>()>(prog, a.prog_len, e, W, G, static_cast<uint32_t>(a.n_ant));
     __syncthreads();
     row_stage<N, V>(G, twr, fin);
     __syncthreads();
