@@ -35,36 +35,33 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "3199dbac259337b4"
+TRAFFIC_SOURCES_SHA = "abaa681d70ce66b7"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (32945, 16384),
-    (2, "f32", 0, 512): (32400, 32776),
-    (2, "f32", 0, 768): (32401, 49164),
-    (2, "f32", 0, 1024): (32410, 65552),
-    (2, "f32", 0, 1536): (32408, 98328),
-    (2, "f32", 0, 2048): (32404, 131104),
-    (2, "f32", 0, 2304): (32403, 147492),
-    (2, "f32", 0, 3072): (32402, 196656),
-    (2, "f32", 0, 4096): (32402, 262208),
-    (2, "f32", 0, 8192): (32402, 524416),
-    (2, "f32", 0, 16384): (32402, 1048832),
-    (2, "f32", 1, 128): (17170, 8192),
-    (2, "f32", 1, 256): (16593, 16392),
-    (2, "f32", 1, 512): (16593, 32785),
-    (2, "f32", 1, 1024): (16598, 65569),
-    (2, "f32", 1, 1536): (16599, 98352),
-    (2, "f32", 1, 2048): (16594, 131136),
-    (2, "f32", 1, 4096): (16598, 262272),
-    (2, "f32", 1, 8192): (16594, 524544),
+    (2, "f32", 0, 256): (32979, 16384),
+    (2, "f32", 0, 512): (32434, 32776),
+    (2, "f32", 0, 1024): (32434, 65552),
+    (2, "f32", 0, 2048): (32449, 131104),
+    (2, "f32", 0, 3072): (32440, 196656),
+    (2, "f32", 0, 4096): (32440, 262208),
+    (2, "f32", 0, 8192): (32439, 524416),
+    (2, "f32", 0, 16384): (32439, 1048832),
+    (2, "f32", 1, 128): (17197, 8192),
+    (2, "f32", 1, 256): (16616, 16393),
+    (2, "f32", 1, 512): (16616, 32785),
+    (2, "f32", 1, 1024): (16624, 65569),
+    (2, "f32", 1, 1536): (16624, 98352),
+    (2, "f32", 1, 2048): (16616, 131136),
+    (2, "f32", 1, 4096): (16624, 262272),
+    (2, "f32", 1, 8192): (16620, 524544),
     (4, "f16", 0, 128): (129218, 8192),
     (4, "f16", 0, 256): (128546, 16392),
     (4, "f16", 0, 512): (128758, 32785),
-    (4, "f16", 0, 768): (128971, 49176),
+    (4, "f16", 0, 768): (128971, 49177),
     (4, "f16", 0, 1024): (129183, 65569),
     (4, "f16", 0, 2048): (129631, 131136),
-    (4, "f16", 0, 4096): (129609, 262272),
-    (4, "f16", 0, 8192): (130448, 524544),
+    (4, "f16", 0, 4096): (129551, 262272),
+    (4, "f16", 0, 8192): (130627, 524544),
 }
 
 
