@@ -78,7 +78,7 @@ enum {
                               of order 2^-11 relative to the image peak (stated bound
                               16 * 2^-11 on max|dI| / max(S/T)).  The kernel keeps two
                               buffers of samples, grid and row-stage output in LDS, so
-                              at grid_n 128 it takes about 2100 antennas (fewer with
+                              at grid_n 128 it takes about 1490 antennas (fewer with
                               large tables); beyond that, or when the sample and tap
                               offsets exceed 16 bits, plan creation returns
                               MOFF_ERR_UNSUPPORTED. */
@@ -210,16 +210,17 @@ moff_status moff_plan_gather_program(moff_plan plan, int32_t variant, int32_t w,
  *          y = 0, or on the last entry of a cell y = grid_base +
  *          2 * (iy * row_pitch + ix), where the cell's real part is stored (its
  *          imaginary part is grid_n / 2 elements further on).
- *   dft  : uint16 [2][grid_n / 64][grid_n / 32][2][64][8] binary16 or bfloat16
- *          bit patterns, indexed [stage][base block][k-step][part][lane][slot],
- *          for the base half (index n < grid_n / 2) of each transform; the
- *          other half follows by conjugation (column grid_n - n of the row
- *          transform is the conjugate of column n, and likewise for rows of
- *          the column transform).  Stage 0 = row transform
- *          exp(+2 pi i ix (q - N/2) / N) / (N/2) at column q = 32 block +
- *          lane % 32 and ix = 16 k-step + 8 (lane / 32) + slot; stage 1 = column
- *          transform exp(+2 pi i iy (r - N/2) / N) at row r = 32 block +
- *          lane % 32 and iy likewise.  Part 0 holds the real part, part 1 the
+ *   dft  : uint16 [2][grid_n / 64][2][grid_n / 64][2][64][8] binary16 or
+ *          bfloat16 bit patterns, indexed
+ *          [stage][base block][half][k-step][part][lane][slot], for the base
+ *          half (index n < grid_n / 2) of each transform; the other half
+ *          follows by conjugation (column grid_n - n of the row transform is
+ *          the conjugate of column n, and likewise for rows of the column
+ *          transform).  Stage 0 = row transform exp(+2 pi i ix (q - N/2) / N) /
+ *          (N/2) at column q = 32 block + 16 half + lane % 16 and
+ *          ix = 32 k-step + 8 (lane / 16) + slot; stage 1 = column transform
+ *          exp(+2 pi i iy (r - N/2) / N) at row r = 32 block + 16 half +
+ *          lane % 16 and iy likewise.  Part 0 holds the real part, part 1 the
  *          imaginary part, except at n = 0, where part 0 holds the (real) phase
  *          vector of n - N/2 = -N/2 and part 1 that of n - N/2 = 0 (all ones),
  *          each with the stage's scale.

@@ -130,7 +130,7 @@ class Plan:
 
     def mfma_tables(self):
         """(gather entries uint32 [prog_len, n_threads, 2], phase-factor operand bit
-        patterns uint16 [2, N/64, N/32, 2, 64, 8], sizes) of a MOFF_MFMA_* plan."""
+        patterns uint16 [2, N/64, 2, N/64, 2, 64, 8], sizes) of a MOFF_MFMA_* plan."""
         sizes = [ctypes.c_int32() for _ in range(5)]
         _lib.moff_plan_mfma_tables(self.handle, None, None, *[ctypes.byref(s) for s in sizes])
         plen, nt, pitch, base, ndft = (s.value for s in sizes)
@@ -139,7 +139,7 @@ class Plan:
         _lib.moff_plan_mfma_tables(self.handle, _ptr(prog, ctypes.c_uint32), _ptr(dft, ctypes.c_uint16),
                                    *[ctypes.byref(s) for s in sizes])
         N = self.N
-        return prog, dft.reshape(2, N // 64, N // 32, 2, 64, 8), dict(prog_len=plen, n_threads=nt, row_pitch=pitch,
+        return prog, dft.reshape(2, N // 64, 2, N // 64, 2, 64, 8), dict(prog_len=plen, n_threads=nt, row_pitch=pitch,
                                                                      grid_base=base)
 
     def autotune(self, E, gains=None, stream=None):

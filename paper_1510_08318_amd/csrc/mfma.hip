@@ -23,39 +23,45 @@
 //
 // Operands are binary16 or bfloat16 (Eg rounded once when gridded, Z once
 // between the stages, phase factors once from float64); every product
-// accumulates in float32 (v_mfma_f32_32x32x16_{f16,bf16}).  The squared
+// accumulates in float32 (v_mfma_f32_16x16x32_{f16,bf16}).  The squared
 // magnitudes accumulate as S = P1^2 + P2^2 + P3^2 + P4^2 and D = P3 P4 - P1 P2,
 // so that base = S + 2 D and partner = S - 2 D (the shared slot takes S at
 // half weight and its own D).
 //
 // One workgroup owns one (channel, time slice) and streams its frames through
 // a three-deep pipeline.  Its waves have two roles:
-//   * gather waves (3 at N = 64, 4 at N = 128) ingest and calibrate frame j
-//     (e = g E into LDS as float32, self power per antenna) and grid frame
-//     j - 1: each lane walks its balanced slice of the cell-keyed program (no
-//     atomics) and stores finished cells as 16-bit values;
-//   * matrix waves (1 at N = 64, 4 at N = 128) run the column stage of frame
-//     j - 3 and the row stage of frame j - 2, each with the phase factors of
-//     its tiles held in registers for the whole launch.  Z goes through LDS
-//     transposed (column-major), the layout the column stage reads; |Y|^2
-//     accumulates in registers.
-// The samples, the grid and Z are double-buffered, so one barrier per frame
-// orders every hand-over, and the matrix pipes stay busy while the gather
-// waves, which share the SIMDs with the matrix waves, do their latency-bound
-// work.  After the last frame the accumulators go through the same epilogue
-// modes as the float32 fused kernel (per-slice partial, running sum, final
-// image).
+//   * gather waves (2 at N = 64, 4 at N = 128) grid frame j - 1: each lane
+//     walks its balanced slice of the cell-keyed program (no atomics) and
+//     stores finished cells as 16-bit values;
+//   * matrix waves (2 at N = 64, 8 at N = 128) ingest and calibrate frame j
+//     (e = g E into LDS as float32, self power per antenna), and each runs one
+//     row-stage panel of frame j - 2 (16 grid rows x 32 base columns) and one
+//     column-stage tile of frame j - 3 (32 base rows x 32 columns).  The
+//     column stage's phase factors stay in registers for the whole launch,
+//     the row stage's are read from LDS.  Z goes through LDS transposed
+//     (column-major), the layout the column stage reads; |Y|^2 accumulates in
+//     registers.
+// A wave issues its matrix products and its vector work (the pair
+// combinations, the conversion of Z, the squared magnitudes) one after the
+// other; two matrix waves per SIMD let one's vector work run beside the
+// other's products, and the gather waves' latency-bound gridding runs beside
+// both.  The samples, the grid and Z are double-buffered, so one
+// barrier per frame orders every hand-over.  Every iteration runs both stages:
+// the fill iterations transform the cleared buffers and add exact zeros.
+// After the last frame the accumulators go through the same epilogue modes as
+// the float32 fused kernel (per-slice partial, running sum, final image).
 //
-// MFMA operand layout (32x32x16, checked on the device): lane l supplies
-// A[l % 32][8 (l / 32) + i] and B[8 (l / 32) + i][l % 32], i < 8, and receives
-// D[8 (j / 4) + 4 (l / 32) + j % 4][l % 32] in accumulator j < 16.
+// MFMA operand layout (16x16x32): lane l supplies A[l % 16][8 (l / 16) + i] and
+// B[8 (l / 16) + i][l % 16], i < 8, and receives D[4 (l / 16) + j][l % 16] in
+// accumulator j < 4.
 //
 // LDS rows are 2L + 8 sixteen-bit elements long (real parts, then imaginary
-// parts): the 16-byte operand reads of eight consecutive rows then fall in
-// eight different 16-byte bank groups.
+// parts): the 16-byte operand reads of consecutive rows then fall in different
+// 16-byte bank groups.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "dft.h"
 #include "ingest.h"
@@ -70,18 +76,18 @@ struct Vec {
   typedef H v8 __attribute__((ext_vector_type(8)));
   typedef H v4 __attribute__((ext_vector_type(4)));
 };
-typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <class H>
-__device__ __forceinline__ f32x16 mfma32(typename Vec<H>::v8 a, typename Vec<H>::v8 b, f32x16 c);
+__device__ __forceinline__ f32x4 mfma16(typename Vec<H>::v8 a, typename Vec<H>::v8 b, f32x4 c);
 
 template <>
-__device__ __forceinline__ f32x16 mfma32<_Float16>(Vec<_Float16>::v8 a, Vec<_Float16>::v8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma16<_Float16>(Vec<_Float16>::v8 a, Vec<_Float16>::v8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 template <>
-__device__ __forceinline__ f32x16 mfma32<__bf16>(Vec<__bf16>::v8 a, Vec<__bf16>::v8 b, f32x16 c) {
-  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+__device__ __forceinline__ f32x4 mfma16<__bf16>(Vec<__bf16>::v8 a, Vec<__bf16>::v8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
 template <int N>
@@ -91,13 +97,13 @@ struct MfmaShape {
   static constexpr int NG = mfma_gather_waves(N);   // gather waves
   static constexpr int NTG = NG * 64;               // gather lanes: the program's width
   static constexpr int NT = (NW + NG) * 64;         // threads per workgroup
-  static constexpr int KS = L / 16;                 // 16-deep steps over a contraction of L
+  static constexpr int WPE = N == 128 ? 3 : 2;      // waves per SIMD the registers are sized for
+  static constexpr int KS2 = L / 32;                // 32-deep steps over a contraction of L
   static constexpr int NRB = L / 32;                // base blocks of 32 (row-stage columns, column-stage rows)
   static constexpr int NIB = L / 32;                // row-stage blocks of 32 grid rows
   static constexpr int NQB = N / 32;                // column-stage blocks of 32 output columns
-  static constexpr int CTW = NRB * NQB / NW;        // column-stage tiles per matrix wave
-  static_assert(NIB * NRB == NW, "one row-stage tile per matrix wave");
-  static_assert(CTW * NW == NRB * NQB && NQB % CTW == 0, "column-stage tiles of a wave share one base block");
+  static_assert(NW == 2 * NIB * NRB, "one row-stage panel (half a 32 x 32 tile) per matrix wave");
+  static_assert(NW == NRB * NQB, "one column-stage tile per matrix wave");
   static constexpr int PITCH = 2 * L + 8;           // LDS row length, 16-bit elements
   static constexpr int EG = L * PITCH;              // one Eg [L][PITCH]: real parts at ix, imaginary at L + ix
   static constexpr int ZT = N * PITCH;              // one Zt [N][PITCH]: Zt[q][iy] = Re Z, Zt[q][L + iy] = Im Z
@@ -120,15 +126,15 @@ bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len) {
 }
 
 template <int N, class H, bool CI4>
-__global__ __launch_bounds__((MfmaShape<N>::NT)) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ __launch_bounds__((MfmaShape<N>::NT)) __attribute__((amdgpu_waves_per_eu(MfmaShape<N>::WPE)))
 void mfma_kernel(MfmaArgs a) {
   using S = MfmaShape<N>;
   using V8 = typename Vec<H>::v8;
   using V4 = typename Vec<H>::v4;
-  constexpr int NT = S::NT, NTG = S::NTG, L = S::L, KS = S::KS, PITCH = S::PITCH, CTW = S::CTW;
+  constexpr int NT = S::NT, NTG = S::NTG, L = S::L, KS2 = S::KS2, PITCH = S::PITCH;
   extern __shared__ uint4 lds_mfma[];
   __shared__ double Atot[kMaxTypesDev];
-  __shared__ double pw_part[S::NG][kMaxTypesDev];   // self power per gather wave and table type
+  __shared__ double pw_part[S::NW][kMaxTypesDev];   // self power per matrix wave and table type
   char* lds = reinterpret_cast<char*>(lds_mfma);
   const MfmaLayout lay = mfma_layout(N, a.n_taps, a.n_ant);
   float2* K = reinterpret_cast<float2*>(lds + lay.k);   // [n_taps]
@@ -146,169 +152,229 @@ void mfma_kernel(MfmaArgs a) {
   const int c = item % a.n_chan;
   const int slice = item / a.n_chan;
 
-  // both grids cleared once: cells without antennas are never written
-  for (int i = tid; i < 2 * S::EG * 2 / 16; i += NT) reinterpret_cast<uint4*>(Eg)[i] = make_uint4(0u, 0u, 0u, 0u);
+  // Both grids and both row-stage outputs cleared once: grid cells without
+  // antennas are never written, and the pipeline's fill iterations transform
+  // these zeros (an exact no-op for the accumulators).  Eg and Zt are adjacent.
+  static_assert((2 * S::EG * 2) % 16 == 0 && (2 * S::ZT * 2) % 16 == 0, "buffers of whole 16-byte words");
+  for (int i = tid; i < 2 * (S::EG + S::ZT) * 2 / 16; i += NT) reinterpret_cast<uint4*>(Eg)[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int i = tid; i < a.n_taps; i += NT) K[i] = a.ktab[i];
   for (int i = tid; i < a.n_ant; i += NT) {
     ty[i] = a.ant_type[i];
     gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
   }
   if (tid < 2) reinterpret_cast<float2*>(lds + lay.e + tid * lay.e_stride)[a.n_ant] = make_float2(0.f, 0.f);
+  {
+    // the row stage's phase-factor operands (stage 0 of the table)
+    constexpr int n_wt = S::NRB * 2 * KS2 * 2 * 64;   // 16-byte operands
+    const uint4* src = reinterpret_cast<const uint4*>(a.dft);
+    for (int i = tid; i < n_wt; i += NT) reinterpret_cast<uint4*>(lds + lay.wt)[i] = src[i];
+  }
   if (a.prog_in_lds)
     for (int i = tid; i < a.prog_len * NTG; i += NT) lprog[i] = a.prog[i];
 
   const int64_t T = a.n_time;
   const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
   const int64_t nf = t1 - t0;
-  // iteration j: gather waves ingest frame j and grid frame j - 1; matrix
-  // waves run the column stage of frame j - 3 and the row stage of frame j - 2
+  // iteration j: matrix waves ingest frame j and run the row stage of frame
+  // j - 2 and the column stage of frame j - 3; gather waves grid frame j - 1
   const int64_t n_iter = nf > 0 ? nf + 3 : 0;
   const int row = lane & 31, half = lane >> 5;
   __syncthreads();   // tables in LDS
 
   if (w < S::NW) {
     // ---- matrix waves ----
-    // row-stage tile: grid rows 32 ib .. +32, base columns 32 qb .. +32
-    const int ib = w % S::NIB, qb = w / S::NIB;
-    // column-stage tiles: base rows 32 rb .. +32, output column blocks qc0 .. qc0 + CTW - 1
-    const int rb = (w * CTW) / S::NQB, qc0 = (w * CTW) % S::NQB;
-    // phase factors (real, imaginary part) of both tiles, resident for the whole launch
-    V8 wc[KS], wd[KS], vc[KS], vd[KS];
+    // row-stage panel: grid rows 32 ib + 16 pm .. +16, base columns 32 qb .. +32
+    const int pm = w % 2, ib = (w / 2) % S::NIB, qb = (w / 2) / S::NIB;
+    // column-stage tile: base rows 32 rb .. +32, output columns 32 qc .. +32
+    const int rb = w / S::NQB, qc = w % S::NQB;
+    const int l16 = lane & 15, g16 = lane >> 4;
+    // Phase factors (real, imaginary part): V, the column stage's A operand per
+    // 16-row half, is resident in registers for the whole launch; W, the row
+    // stage's B operand per 16-column half, is read from LDS one step at a
+    // time (it is used once per frame, and registers are what bound this role).
+    V8 vc[2][KS2], vd[2][KS2];
     {
       const V8* src = reinterpret_cast<const V8*>(a.dft);
+      auto at = [&](int st, int blk, int hf, int ks, int part) {
+        return src[((((st * S::NRB + blk) * 2 + hf) * KS2 + ks) * 2 + part) * 64 + lane];
+      };
 #pragma unroll
-      for (int ks = 0; ks < KS; ++ks) {
-        wc[ks] = src[(((0 * S::NRB + qb) * KS + ks) * 2 + 0) * 64 + lane];
-        wd[ks] = src[(((0 * S::NRB + qb) * KS + ks) * 2 + 1) * 64 + lane];
-        vc[ks] = src[(((1 * S::NRB + rb) * KS + ks) * 2 + 0) * 64 + lane];
-        vd[ks] = src[(((1 * S::NRB + rb) * KS + ks) * 2 + 1) * 64 + lane];
-      }
+      for (int hf = 0; hf < 2; ++hf)
+#pragma unroll
+        for (int ks = 0; ks < KS2; ++ks) {
+          vc[hf][ks] = at(1, rb, hf, ks, 0);
+          vd[hf][ks] = at(1, rb, hf, ks, 1);
+        }
     }
-    // index 0 of a base block 0 is the shared slot of the two real phase vectors
-    const bool sp_col = qb == 0 && row == 0;   // row stage: this lane's column q = 0
-    const bool sp_row = rb == 0 && half == 0;  // column stage: accumulator 0 is row r = 0
+    const V8* wt = reinterpret_cast<const V8*>(lds + lay.wt);
+    auto w_op = [&](int hf, int ks, int part) { return wt[(((qb * 2 + hf) * KS2 + ks) * 2 + part) * 64 + lane]; };
+    // index 0 of base block 0 is the shared slot of the two real phase vectors
+    const bool sp_row = rb == 0 && g16 == 0;   // column stage: accumulator (half 0, j 0) is row r = 0
+    const bool sp_col = qb == 0 && l16 == 0;   // row stage: this lane's half-0 column is q = 0
     const float s_col = sp_col ? 0.f : 1.f;
-    const int q_base = 32 * qb + row;
-    const int q_part = sp_col ? L : N - q_base;
-    // S in acc_s, D in acc_d: base = S + 2 D, partner = S - 2 D.  For the shared
-    // slot (lanes with sp_row, accumulator 0) S is taken at half weight and D
-    // as (P1^2 + P4^2 - P2^2 - P3^2) / 4, which makes the same two formulas give
-    // |P1 + i P4|^2 and |P3 + i P2|^2.
-    float acc_s[CTW][16], acc_d[CTW][16];
+    // S in acc_s, D in acc_d per column-stage half h and accumulator e = 4 m + j:
+    // base = S + 2 D, partner = S - 2 D.  For the shared slot S is taken at half
+    // weight and D as (P1^2 + P4^2 - P2^2 - P3^2) / 4, which makes the same two
+    // formulas give |P1 + i P4|^2 and |P3 + i P2|^2.
+    float acc_s[2][8], acc_d[2][8];
 #pragma unroll
-    for (int t = 0; t < CTW; ++t)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int j = 0; j < 16; ++j) acc_s[t][j] = acc_d[t][j] = 0.f;
-    // Each stage walks its steps as one stream with the LDS operands read
-    // kRing steps (of four matrix products each) ahead of their use.
-    constexpr int kRing = 1;
-    static_assert(kRing <= KS * CTW && kRing <= KS, "operand ring deeper than the stream");
+      for (int e = 0; e < 8; ++e) acc_s[h][e] = acc_d[h][e] = 0.f;
+
+    // Ingest and calibration of frame j (e = g E into LDS as float32, self
+    // power per antenna), one antenna per matrix lane and prefetch slot.  Raw
+    // samples of the next frame are loaded one iteration ahead, so the HBM
+    // latency is hidden behind this iteration's matrix work; antennas beyond
+    // the prefetch slots are loaded when used.  Per-lane self-power sums are
+    // float32 (this path's error budget is set by its 16-bit operands); lanes
+    // are combined in float64.
+    constexpr int NI = S::NW * 64, kPrefetch = N == 128 ? 1 : 2;
+    const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
+    float2 raw[kPrefetch];
+    float pws[kPrefetch];
+#pragma unroll
+    for (int q = 0; q < kPrefetch; ++q) pws[q] = 0.f;
+    float pwt[kMaxTypesDev] = {0.f, 0.f, 0.f, 0.f};
+    auto load_raw = [&](int64_t t) {
+      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        const int i = tid + q * NI;
+        if (i < a.n_ant) raw[q] = load_sample(a.E, base + i, CI4);
+      }
+    };
+    auto ingest = [&](int64_t t, float2* e) {
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        const int i = tid + q * NI;
+        if (i < a.n_ant) {
+          const float2 v = c_mul(gl[i], raw[q]);
+          e[i] = v;
+          pws[q] += fmaf(v.x, v.x, v.y * v.y);
+        }
+      }
+      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+      for (int i = tid + kPrefetch * NI; i < a.n_ant; i += NI) {
+        const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+        e[i] = v;
+        const float p = fmaf(v.x, v.x, v.y * v.y);
+        const int tp = ty[i];
+#pragma unroll
+        for (int q = 0; q < kMaxTypesDev; ++q) pwt[q] += (tp == q) ? p : 0.f;
+      }
+    };
+    if (nf > 0) load_raw(t0);
 
     for (int64_t j = 0; j < n_iter; ++j) {
-      if (j >= 3) {
-        // column stage of frame j - 3: B operands Re Z, Im Z from LDS, A = V in registers
-        const H* zt = Zt + ((j - 3) & 1) * S::ZT;
-        constexpr int NS = CTW * KS;
-        auto b_src = [&](int u, int part) {
-          return reinterpret_cast<const V8*>(zt + (32 * (qc0 + u / KS) + row) * PITCH + part * L + 16 * (u % KS) +
-                                             8 * half);
-        };
-        V8 ra[kRing], rb_[kRing];
+      if (j < nf) ingest(t0 + j, reinterpret_cast<float2*>(lds + lay.e + (j & 1) * lay.e_stride));
+      // row stage of frame j - 2, then column stage of frame j - 3
+      const H* eg = Eg + ((j - 2) & 1) * S::EG;
+      H* zw = Zt + ((j - 2) & 1) * S::ZT;
+      const H* zr = Zt + ((j - 3) & 1) * S::ZT;
+      // operands of the three panels: [panel][k-step][real, imaginary part]
+      auto src = [&](int p, int ks, int part) {
+        const H* base = p == 0 ? eg + (32 * ib + 16 * pm + l16) * PITCH : zr + (32 * qc + 16 * (p - 1) + l16) * PITCH;
+        return reinterpret_cast<const V8*>(base + part * L + 32 * ks + 8 * g16);
+      };
 #pragma unroll
-        for (int u = 0; u < kRing; ++u) {
-          ra[u] = *b_src(u, 0);
-          rb_[u] = *b_src(u, 1);
-        }
-        f32x16 p1 = {}, p2 = {}, p3 = {}, p4 = {};
+      for (int p = 0; p < 3; ++p) {
+        // this panel's operands (the other matrix wave on the SIMD covers their latency)
+        V8 op[KS2][2];
 #pragma unroll
-        for (int u = 0; u < NS; ++u) {
-          const int ks = u % KS;
-          const V8 za = ra[u % kRing], zb = rb_[u % kRing];
-          if (u + kRing < NS) {
-            ra[u % kRing] = *b_src(u + kRing, 0);
-            rb_[u % kRing] = *b_src(u + kRing, 1);
+        for (int ks = 0; ks < KS2; ++ks)
+#pragma unroll
+          for (int part = 0; part < 2; ++part) op[ks][part] = *src(p, ks, part);
+#pragma unroll
+        for (int hf = 0; hf < 2; ++hf) {
+          // one 16-wide half of the panel: four products over the contraction
+          f32x4 Q[4];
+#pragma unroll
+          for (int ks = 0; ks < KS2; ++ks) {
+            const V8 xa = op[ks][0], xb = op[ks][1];
+            const f32x4 z = {};
+            if (p == 0) {   // row stage: A = Eg (real, imaginary part), B = W half hf
+              const V8 wr = w_op(hf, ks, 0), wi = w_op(hf, ks, 1);
+              Q[0] = mfma16<H>(xa, wr, ks ? Q[0] : z);
+              Q[1] = mfma16<H>(xb, wi, ks ? Q[1] : z);
+              Q[2] = mfma16<H>(xa, wi, ks ? Q[2] : z);
+              Q[3] = mfma16<H>(xb, wr, ks ? Q[3] : z);
+            } else {        // column stage: A = V half hf, B = Z (real, imaginary part)
+              Q[0] = mfma16<H>(vc[hf][ks], xa, ks ? Q[0] : z);
+              Q[1] = mfma16<H>(vd[hf][ks], xb, ks ? Q[1] : z);
+              Q[2] = mfma16<H>(vd[hf][ks], xa, ks ? Q[2] : z);
+              Q[3] = mfma16<H>(vc[hf][ks], xb, ks ? Q[3] : z);
+            }
           }
-          p1 = mfma32<H>(vc[ks], za, p1);
-          p2 = mfma32<H>(vd[ks], zb, p2);
-          p3 = mfma32<H>(vd[ks], za, p3);
-          p4 = mfma32<H>(vc[ks], zb, p4);
-          __builtin_amdgcn_sched_barrier(0);
-          if (ks == KS - 1) {
-            const int t = u / KS;
-            {
-              // accumulator 0 may be the shared slot: base |P1 + i P4|^2, partner |P3 + i P2|^2
-              const float sq = fmaf(p1[0], p1[0], fmaf(p2[0], p2[0], fmaf(p3[0], p3[0], p4[0] * p4[0])));
-              const float d = fmaf(p3[0], p4[0], -p1[0] * p2[0]);
-              const float ds = 0.25f * (fmaf(p1[0], p1[0], p4[0] * p4[0]) - fmaf(p2[0], p2[0], p3[0] * p3[0]));
-              acc_s[t][0] = fmaf(sp_row ? 0.5f : 1.f, sq, acc_s[t][0]);
-              acc_d[t][0] += sp_row ? ds : d;
-            }
+          if (p == 0) {
+            // Z of grid rows iy = 32 ib + 16 pm + 4 g16 + (0..3): base column q
+            // and its partner
+            const int q = 32 * qb + 16 * hf + l16;
+            const bool sp = hf == 0 && sp_col;
+            const float sc = hf == 0 ? s_col : 1.f;
+            const int qp = sp ? L : N - q;
+            V4 br, bi, pr, pi;
 #pragma unroll
-            for (int k = 1; k < 16; ++k) {
-              acc_s[t][k] = fmaf(p1[k], p1[k], fmaf(p2[k], p2[k], fmaf(p3[k], p3[k], fmaf(p4[k], p4[k], acc_s[t][k]))));
-              acc_d[t][k] = fmaf(p3[k], p4[k], fmaf(-p1[k], p2[k], acc_d[t][k]));
+            for (int jj = 0; jj < 4; ++jj) {
+              br[jj] = static_cast<H>(fmaf(-sc, Q[1][jj], Q[0][jj]));
+              bi[jj] = static_cast<H>(fmaf(sc, Q[2][jj], Q[3][jj]));
+              pr[jj] = static_cast<H>(sp ? Q[2][jj] : Q[0][jj] + Q[1][jj]);
+              pi[jj] = static_cast<H>(sp ? Q[1][jj] : Q[3][jj] - Q[2][jj]);
             }
-            p1 = f32x16{};
-            p2 = f32x16{};
-            p3 = f32x16{};
-            p4 = f32x16{};
+            const int iy = 32 * ib + 16 * pm + 4 * g16;
+            *reinterpret_cast<V4*>(zw + q * PITCH + iy) = br;
+            *reinterpret_cast<V4*>(zw + q * PITCH + L + iy) = bi;
+            *reinterpret_cast<V4*>(zw + qp * PITCH + iy) = pr;
+            *reinterpret_cast<V4*>(zw + qp * PITCH + L + iy) = pi;
+          } else {
+            const int h = p - 1;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              const int e = 4 * hf + jj;
+              if (e == 0) {
+                const float sq = fmaf(Q[0][0], Q[0][0], fmaf(Q[1][0], Q[1][0], fmaf(Q[2][0], Q[2][0], Q[3][0] * Q[3][0])));
+                const float d = fmaf(Q[2][0], Q[3][0], -Q[0][0] * Q[1][0]);
+                const float ds = 0.25f * (fmaf(Q[0][0], Q[0][0], Q[3][0] * Q[3][0]) - fmaf(Q[1][0], Q[1][0], Q[2][0] * Q[2][0]));
+                acc_s[h][0] = fmaf(sp_row ? 0.5f : 1.f, sq, acc_s[h][0]);
+                acc_d[h][0] += sp_row ? ds : d;
+              } else {
+                acc_s[h][e] = fmaf(Q[0][jj], Q[0][jj], fmaf(Q[1][jj], Q[1][jj], fmaf(Q[2][jj], Q[2][jj], fmaf(Q[3][jj], Q[3][jj], acc_s[h][e]))));
+                acc_d[h][e] = fmaf(Q[2][jj], Q[3][jj], fmaf(-Q[0][jj], Q[1][jj], acc_d[h][e]));
+              }
+            }
           }
         }
       }
-      if (j >= 2 && j - 2 < nf) {
-        // row stage of frame j - 2: A operands Re Eg, Im Eg from LDS, B = W in registers
-        const H* eg = Eg + ((j - 2) & 1) * S::EG;
-        H* zt = Zt + ((j - 2) & 1) * S::ZT;
-        auto a_src = [&](int ks, int part) {
-          return reinterpret_cast<const V8*>(eg + (32 * ib + row) * PITCH + part * L + 16 * ks + 8 * half);
-        };
-        V8 ra[kRing], rb_[kRing];
-#pragma unroll
-        for (int u = 0; u < kRing; ++u) {
-          ra[u] = *a_src(u, 0);
-          rb_[u] = *a_src(u, 1);
-        }
-        f32x16 p1 = {}, p2 = {}, p3 = {}, p4 = {};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) {
-          const V8 ea = ra[ks % kRing], eb = rb_[ks % kRing];
-          if (ks + kRing < KS) {
-            ra[ks % kRing] = *a_src(ks + kRing, 0);
-            rb_[ks % kRing] = *a_src(ks + kRing, 1);
-          }
-          p1 = mfma32<H>(ea, wc[ks], p1);
-          p2 = mfma32<H>(eb, wd[ks], p2);
-          p3 = mfma32<H>(ea, wd[ks], p3);
-          p4 = mfma32<H>(eb, wc[ks], p4);
-          __builtin_amdgcn_sched_barrier(0);
-        }
-        // lane holds grid rows iy = 32 ib + 8 g + 4 half + (0..3) of base column
-        // q_base and of its partner q_part
-        H* zb = zt + q_base * PITCH + 32 * ib + 4 * half;
-        H* zp = zt + q_part * PITCH + 32 * ib + 4 * half;
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          V4 br, bi, pr, pi;
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int k = 4 * g + i;
-            br[i] = static_cast<H>(fmaf(-s_col, p2[k], p1[k]));
-            bi[i] = static_cast<H>(fmaf(s_col, p3[k], p4[k]));
-            pr[i] = static_cast<H>(sp_col ? p3[k] : p1[k] + p2[k]);
-            pi[i] = static_cast<H>(sp_col ? p2[k] : p4[k] - p3[k]);
-          }
-          *reinterpret_cast<V4*>(zb + 8 * g) = br;
-          *reinterpret_cast<V4*>(zb + 8 * g + L) = bi;
-          *reinterpret_cast<V4*>(zp + 8 * g) = pr;
-          *reinterpret_cast<V4*>(zp + 8 * g + L) = pi;
-        }
-      }
+      // the samples of frame j + 1, requested after this iteration's work
+      if (j + 1 < nf) load_raw(t0 + j + 1);
       __syncthreads();
     }
-    __syncthreads();   // self-power partials of the gather waves are in LDS
+    {
+      // self power per table type: lanes in float64, then one partial per wave
+      double pw[kMaxTypesDev];
+#pragma unroll
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = pwt[q];
+#pragma unroll
+      for (int q = 0; q < kPrefetch; ++q) {
+        const int i = tid + q * NI;
+        if (i < a.n_ant) {
+          const int tp = ty[i];
+#pragma unroll
+          for (int p = 0; p < kMaxTypesDev; ++p) pw[p] += (tp == p) ? static_cast<double>(pws[q]) : 0.0;
+        }
+      }
+#pragma unroll
+      for (int p = 0; p < kMaxTypesDev; ++p) {
+        double x = pw[p];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
+        if (lane == 0) pw_part[w][p] = x;
+      }
+    }
+    __syncthreads();   // self-power partials of the matrix waves are in LDS
     if (tid < kMaxTypesDev) {
       double s = 0.0;
-      for (int g = 0; g < S::NG; ++g) s += pw_part[g][tid];
+      for (int g = 0; g < S::NW; ++g) s += pw_part[g][tid];
       Atot[tid] = s;
     }
     __syncthreads();   // Atot complete (the gather waves take part in every barrier)
@@ -331,14 +397,14 @@ void mfma_kernel(MfmaArgs a) {
       }
     };
 #pragma unroll
-    for (int t = 0; t < CTW; ++t)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int r = 32 * rb + 8 * (k / 4) + 4 * half + (k % 4);
-        const int q = 32 * (qc0 + t) + row;
+      for (int e = 0; e < 8; ++e) {
+        const int r = 32 * rb + 16 * (e / 4) + 4 * g16 + (e % 4);
+        const int q = 32 * qc + 16 * h + l16;
         const int rp = r == 0 ? L : N - r;
-        put(r, q, fmaf(2.f, acc_d[t][k], acc_s[t][k]));
-        put(rp, q, fmaf(-2.f, acc_d[t][k], acc_s[t][k]));
+        put(r, q, fmaf(2.f, acc_d[h][e], acc_s[h][e]));
+        put(rp, q, fmaf(-2.f, acc_d[h][e], acc_s[h][e]));
       }
     if (tid < a.n_types) {
       if (a.mode == kModePartial) {
@@ -350,53 +416,13 @@ void mfma_kernel(MfmaArgs a) {
   } else {
     // ---- gather waves ----
     const int gt = tid - S::NW * 64;   // gather lane, 0 .. NTG - 1 (the matrix waves come first)
-    const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
-    // Raw samples of the next frame are loaded one iteration ahead, so the
-    // HBM latency is hidden behind this iteration's gridding.  The first
-    // kPrefetch * NTG antennas keep their self power in a register (one slot
-    // each); antennas beyond that are loaded when used.  Per-lane self-power
-    // sums are float32 (this path's error budget is set by its 16-bit
-    // operands); lanes are combined in float64.
-    constexpr int kPrefetch = 4;
-    float2 raw[kPrefetch];
-    float pws[kPrefetch];
-#pragma unroll
-    for (int q = 0; q < kPrefetch; ++q) pws[q] = 0.f;
-    float pwt[kMaxTypesDev] = {0.f, 0.f, 0.f, 0.f};
-    auto load_raw = [&](int64_t t) {
-      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-#pragma unroll
-      for (int q = 0; q < kPrefetch; ++q) {
-        const int i = gt + q * NTG;
-        if (i < a.n_ant) raw[q] = load_sample(a.E, base + i, CI4);
-      }
-    };
-    auto ingest = [&](int64_t t, float2* e) {
-#pragma unroll
-      for (int q = 0; q < kPrefetch; ++q) {
-        const int i = gt + q * NTG;
-        if (i < a.n_ant) {
-          const float2 v = c_mul(gl[i], raw[q]);
-          e[i] = v;
-          pws[q] += fmaf(v.x, v.x, v.y * v.y);
-        }
-      }
-      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-      for (int i = gt + kPrefetch * NTG; i < a.n_ant; i += NTG) {
-        const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
-        e[i] = v;
-        const float p = fmaf(v.x, v.x, v.y * v.y);
-        const int tp = ty[i];
-#pragma unroll
-        for (int q = 0; q < kMaxTypesDev; ++q) pwt[q] += (tp == q) ? p : 0.f;
-      }
-    };
+    // Gather-gridding of frame j - 1: each lane walks its balanced slice of the
+    // cell-keyed program (no atomics) and stores finished cells as 16-bit values.
     // entry: x = byte offsets of e[ant] (low half, buffer 0) and K[tap] (high
     // half), y = byte address of the finished cell's real part in grid 0, or 0.
     // The program pointer is either LDS or global memory, never a select of
     // the two: a pointer of unknown address space compiles to flat loads, whose
-    // waits also drain the (in-order) global-load counter and so would stall
-    // every batch on the next frame's samples.
+    // waits also drain the (in-order) global-load counter.
     auto gather = [&](const GatherEntry* prog, int eoff, int goff) {
       float2 g = make_float2(0.f, 0.f);
       auto step = [&](GatherEntry en) {
@@ -423,10 +449,9 @@ void mfma_kernel(MfmaArgs a) {
     };
 
     // The program does not change from frame to frame: when it is short
-    // enough, each lane keeps its entries and their tap values in registers
-    // (the matrix waves set the register allocation, so the gather waves have
-    // room), and a frame costs one batch of sample reads from LDS.
-    constexpr int kProgRegs = 16;
+    // enough, each lane keeps its entries and their tap values in registers,
+    // and a frame costs one batch of sample reads from LDS.
+    constexpr int kProgRegs = N == 128 ? 16 : 24;
     const bool prog_in_regs = a.prog_len <= kProgRegs;
     uint32_t r_e[kProgRegs], r_cell[kProgRegs];
     float2 r_k[kProgRegs];
@@ -441,14 +466,17 @@ void mfma_kernel(MfmaArgs a) {
       }
     }
     // Entries past the program's end are padding (the zero sample, no store),
-    // so the loops have no trip-count branches.
-    auto gather_regs = [&](int eoff, int goff) {
-      float2 ev[kProgRegs];
+    // so the loops have no trip-count branches; a shorter copy covers the
+    // first 3/4 of the slots, for programs that fit there.
+    constexpr int kShort = kProgRegs * 3 / 4;
+    auto gather_regs = [&](auto count, int eoff, int goff) {
+      constexpr int K = decltype(count)::value;
+      float2 ev[K];
 #pragma unroll
-      for (int k = 0; k < kProgRegs; ++k) ev[k] = *reinterpret_cast<const float2*>(lds + eoff + r_e[k]);
+      for (int k = 0; k < K; ++k) ev[k] = *reinterpret_cast<const float2*>(lds + eoff + r_e[k]);
       float2 g = make_float2(0.f, 0.f);
 #pragma unroll
-      for (int k = 0; k < kProgRegs; ++k) {
+      for (int k = 0; k < K; ++k) {
         g.x = fmaf(ev[k].x, r_k[k].x, fmaf(-ev[k].y, r_k[k].y, g.x));
         g.y = fmaf(ev[k].x, r_k[k].y, fmaf(ev[k].y, r_k[k].x, g.y));
         if (r_cell[k] != 0u) {
@@ -460,45 +488,21 @@ void mfma_kernel(MfmaArgs a) {
       }
     };
 
-    // The samples of frame j + 1 are requested after frame j - 1 is gridded,
-    // so no wait of the gridding covers them.
-    if (nf > 0) load_raw(t0);
     for (int64_t j = 0; j < n_iter; ++j) {
-      if (j < nf) ingest(t0 + j, reinterpret_cast<float2*>(lds + lay.e + (j & 1) * lay.e_stride));
       if (j >= 1 && j - 1 < nf) {
         const int eoff = ((j - 1) & 1) * lay.e_stride, goff = ((j - 1) & 1) * lay.eg_stride;
-        if (prog_in_regs)
-          gather_regs(eoff, goff);
+        if (a.prog_len <= kShort)
+          gather_regs(std::integral_constant<int, kShort>(), eoff, goff);
+        else if (prog_in_regs)
+          gather_regs(std::integral_constant<int, kProgRegs>(), eoff, goff);
         else if (a.prog_in_lds)
           gather(lprog + gt, eoff, goff);
         else
           gather(a.prog + gt, eoff, goff);
       }
-      if (j + 1 < nf) load_raw(t0 + j + 1);
       __syncthreads();
     }
-
-    // self power per table type: lanes in float64, then one partial per wave
-    double pw[kMaxTypesDev];
-#pragma unroll
-    for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = pwt[q];
-#pragma unroll
-    for (int q = 0; q < kPrefetch; ++q) {
-      const int i = gt + q * NTG;
-      if (i < a.n_ant) {
-        const int tp = ty[i];
-#pragma unroll
-        for (int p = 0; p < kMaxTypesDev; ++p) pw[p] += (tp == p) ? static_cast<double>(pws[q]) : 0.0;
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < kMaxTypesDev; ++p) {
-      double x = pw[p];
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) x += __shfl_down(x, off, 64);
-      if (lane == 0) pw_part[w - S::NW][p] = x;
-    }
-    __syncthreads();   // partials visible to the matrix waves
+    __syncthreads();   // self-power partials visible to the matrix waves
     __syncthreads();   // matrix waves have read them (Atot)
   }
 }

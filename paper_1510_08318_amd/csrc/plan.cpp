@@ -86,7 +86,7 @@ long long balanced_split(const std::vector<int>& cost, int lanes) {
 // of two, so that its rounded output cannot exceed the largest gridded value;
 // the kernel multiplies |Y|^2 back by (N/2)^2 exactly.
 moff_status build_mfma_tables(HostPlan& P, std::string* why) {
-  const int N = P.N, L = P.L, NRB = L / 32, KS = L / 16;
+  const int N = P.N, L = P.L, NRB = L / 32;
   HostPlan::Mfma& T = P.mfma;
   T.prec = (P.flags & MOFF_MFMA_BF16) ? 2 : 1;
   T.NT = mfma_gather_waves(N) * 64;   // gather lanes
@@ -131,32 +131,36 @@ moff_status build_mfma_tables(HostPlan& P, std::string* why) {
     T.prog[static_cast<size_t>(k - 1) * T.NT + lane].y = static_cast<uint32_t>(lay.eg + 2 * (iy * T.pitch + ix));
   }
 
-  // [stage][base block][k-step][part][lane][slot]: stage 0 = row transform, the
-  // B operand W[ix][q] at contraction index ix = 16 k-step + 8 (lane / 32) + slot
-  // and column q = 32 block + lane % 32; stage 1 = column transform, the A
-  // operand V[r][iy] at row r = 32 block + lane % 32 and iy likewise.  Part 0
-  // holds the real, part 1 the imaginary part; at q = 0 (r = 0) they hold the
-  // real phase vectors of q - N/2 = -N/2 and of q - N/2 = 0.
+  // [stage][base block][half][k-step][part][lane][slot]: stage 0 = row
+  // transform, the B operand W[ix][q] at contraction index
+  // ix = 32 k-step + 8 (lane / 16) + slot and column q = 32 block + 16 half +
+  // lane % 16; stage 1 = column transform, the A operand V[r][iy] at row
+  // r = 32 block + 16 half + lane % 16 and iy likewise.  Part 0 holds the real,
+  // part 1 the imaginary part; at q = 0 (r = 0) they hold the real phase
+  // vectors of q - N/2 = -N/2 and of q - N/2 = 0.
+  const int KS2 = L / 32;
   auto enc = [&](double v) { return T.prec == 2 ? to_bfloat16(v) : to_binary16(v); };
-  T.dft.assign(static_cast<size_t>(2) * NRB * KS * 2 * 64 * 8, 0);
+  T.dft.assign(static_cast<size_t>(2) * NRB * 2 * KS2 * 2 * 64 * 8, 0);
   const double s1 = 1.0 / L;
   for (int st = 0; st < 2; ++st)
     for (int b = 0; b < NRB; ++b)
-      for (int ks = 0; ks < KS; ++ks)
-        for (int part = 0; part < 2; ++part)
-          for (int ln = 0; ln < 64; ++ln)
-            for (int i = 0; i < 8; ++i) {
-              const int j = 16 * ks + 8 * (ln / 32) + i;   // ix (stage 0) or iy (stage 1)
-              const int n = 32 * b + ln % 32;              // base column q (stage 0) or row r (stage 1)
-              std::complex<double> f;
-              if (n == 0)
-                f = std::complex<double>(unit_root(static_cast<long long>(j) * (-L), N).real(), 1.0);
-              else
-                f = unit_root(static_cast<long long>(j) * (n - L), N);
-              if (st == 0) f *= s1;
-              const double v = part == 0 ? f.real() : f.imag();
-              T.dft[((((static_cast<size_t>(st) * NRB + b) * KS + ks) * 2 + part) * 64 + ln) * 8 + i] = enc(v);
-            }
+      for (int hf = 0; hf < 2; ++hf)
+        for (int ks = 0; ks < KS2; ++ks)
+          for (int part = 0; part < 2; ++part)
+            for (int ln = 0; ln < 64; ++ln)
+              for (int i = 0; i < 8; ++i) {
+                const int j = 32 * ks + 8 * (ln / 16) + i;    // ix (stage 0) or iy (stage 1)
+                const int n = 32 * b + 16 * hf + ln % 16;     // base column q (stage 0) or row r (stage 1)
+                std::complex<double> f;
+                if (n == 0)
+                  f = std::complex<double>(unit_root(static_cast<long long>(j) * (-L), N).real(), 1.0);
+                else
+                  f = unit_root(static_cast<long long>(j) * (n - L), N);
+                if (st == 0) f *= s1;
+                const double v = part == 0 ? f.real() : f.imag();
+                T.dft[(((((static_cast<size_t>(st) * NRB + b) * 2 + hf) * KS2 + ks) * 2 + part) * 64 + ln) * 8 + i] =
+                    enc(v);
+              }
   return MOFF_OK;
 }
 

@@ -37,22 +37,24 @@ constexpr FrameShape frame_shape(int N, int V = 0) {
 
 // Waves per workgroup of the reduced-precision (matrix-core) frame transform:
 // matrix waves run the two transform stages, gather waves ingest and grid.
-constexpr int mfma_waves(int N) { return N == 128 ? 4 : 1; }
-constexpr int mfma_gather_waves(int N) { return N == 128 ? 4 : 3; }
+constexpr int mfma_waves(int N) { return N == 128 ? 8 : 2; }
+constexpr int mfma_gather_waves(int N) { return N == 128 ? 4 : 2; }
 
-// LDS of one compute unit, the most one workgroup can take.
-constexpr int kMfmaLdsMax = 160 * 1024;
+// Dynamic LDS one workgroup may take: a compute unit's 160 KB less room for
+// the kernels' static arrays (the launch rejects anything larger).
+constexpr int kMfmaLdsMax = 159 * 1024;
 
 // Dynamic-LDS layout of the reduced-precision kernel, byte offsets.  The two
 // buffers of calibrated samples e[n_ant + 1] (last slot zero) and the kernel
 // taps come first so that gather entries can address them with 16-bit byte
 // offsets; the two 16-bit grids Eg [N/2][pitch] and the two transposed
 // row-stage outputs Zt [N][pitch] follow, then per-antenna gains and types,
+// the row stage's phase-factor operands (read from LDS one step at a time),
 // then (optionally) the program.  Gather entries address buffer 0; buffer 1
 // of each pair lies one *_stride further on.
 struct MfmaLayout {
   int pitch;   // 16-bit elements per Eg / Zt row
-  int e, e_stride, k, eg, eg_stride, zt, zt_stride, gl, ty, prog;
+  int e, e_stride, k, eg, eg_stride, zt, zt_stride, gl, ty, wt, prog;
 };
 
 constexpr int align_up(int x, int a) { return (x + a - 1) / a * a; }
@@ -70,7 +72,9 @@ constexpr MfmaLayout mfma_layout(int N, int n_taps, int n_ant) {
   m.zt_stride = 2 * N * pitch;
   m.gl = m.zt + 2 * m.zt_stride;
   m.ty = m.gl + 8 * n_ant;
-  m.prog = align_up(m.ty + 4 * n_ant, 16);
+  // the row stage's phase-factor operands, [N/64][2][N/64][2][64] x 16 bytes
+  m.wt = align_up(m.ty + 4 * n_ant, 16);
+  m.prog = m.wt + (L / 32) * 2 * (L / 32) * 2 * 64 * 16;
   return m;
 }
 

@@ -61,11 +61,11 @@ def test_max_antennas_fused_staged_tuned(torch, moff):
         close(o.cpu().numpy(), w, [0, 1])
 
 
-@pytest.mark.parametrize("N,n_ant", [(64, 4000), (128, 2000)])
+@pytest.mark.parametrize("N,n_ant", [(64, 4000), (128, 1400)])
 def test_max_antennas_reduced_precision(torch, moff, N, n_ant):
     """The matrix-core kernel double-buffers the samples, the grid and the
     transposed row-stage output in LDS: every count the plan accepts runs on
-    the 64 grid, and on the 128 grid about 2100 antennas fit (these tables)."""
+    the 64 grid, and on the 128 grid about 1490 antennas fit (these tables)."""
     w = max_antennas(N, 0.8 if N == 128 else 1.6, n_ant)
     with moff.Plan.from_geometry(w.geom, device=0, extra_flags=synth.MFMA_BF16) as p:
         got = p.image(dev(torch, w.E), dev(torch, w.gains))

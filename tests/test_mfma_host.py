@@ -32,10 +32,10 @@ def _case(name):
 
 def test_lds_bound_on_antennas(moff):
     """On the 128 grid the double-buffered LDS layout bounds the antenna count:
-    4000 antennas are rejected at plan creation (MOFF_ERR_UNSUPPORTED), 2000 fit."""
+    4000 antennas are rejected at plan creation (MOFF_ERR_UNSUPPORTED), 1400 fit."""
     rng = np.random.default_rng(40)
     tabs = [synth.random_kernel(rng, 3), synth.random_kernel(rng, 1)]
-    for n_ant, ok in ((4000, False), (2000, True)):
+    for n_ant, ok in ((4000, False), (1400, True)):
         w = synth.random_case(41, n_ant, 128, 1, 2, tabs, extent_m=60 * 0.8, cell_m=0.8)
         if ok:
             with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16):
@@ -72,7 +72,7 @@ def test_mfma_gather_program_replays_oracle_grid(moff, name):
     with moff.Plan.from_geometry(w.geom, device=-1, extra_flags=synth.MFMA_F16) as p:
         prog, _, info = p.mfma_tables()
     pitch, base, na = info["row_pitch"], info["grid_base"], w.geom.n_ant
-    assert info["n_threads"] == (256 if N == 128 else 192) and pitch == 2 * L + 8   # gather lanes
+    assert info["n_threads"] == (256 if N == 128 else 128) and pitch == 2 * L + 8   # gather lanes
     assert base % 16 == 0 and base >= 8 * (2 * (na + 1) + len(taps))
     x = prog[..., 0].astype(np.int64)
     y = prog[..., 1].astype(np.int64)
@@ -115,15 +115,15 @@ def _phase(j, n, N):
 
 
 def _expected_operands(N):
-    """float64 [2, N/64, N/32, 2, 64, 8] operand values by their definition: the
-    base half (index n < N/2) of each transform's phase vectors, real part then
-    imaginary part; index 0 carries the two real self-conjugate vectors, of
+    """float64 [2, N/64, 2, N/64, 2, 64, 8] operand values by their definition:
+    the base half (index n < N/2) of each transform's phase vectors, real part
+    then imaginary part; index 0 carries the two real self-conjugate vectors, of
     n - N/2 = -N/2 (real part) and of n - N/2 = 0 (imaginary part)."""
-    L, NRB, KS = N // 2, N // 64, N // 32
-    st, b, ks, part, ln, i = np.meshgrid(np.arange(2), np.arange(NRB), np.arange(KS), np.arange(2), np.arange(64),
-                                         np.arange(8), indexing="ij")
-    j = 16 * ks + 8 * (ln // 32) + i
-    n = 32 * b + ln % 32
+    L, NRB, KS2 = N // 2, N // 64, N // 64
+    st, b, hf, ks, part, ln, i = np.meshgrid(np.arange(2), np.arange(NRB), np.arange(2), np.arange(KS2),
+                                             np.arange(2), np.arange(64), np.arange(8), indexing="ij")
+    j = 32 * ks + 8 * (ln // 16) + i
+    n = 32 * b + 16 * hf + ln % 16
     f = _phase(j, n, N)
     shared = _phase(j, 0, N).real + 1j * _phase(j, L, N).real
     f = np.where(n == 0, shared, f) * np.where(st == 0, 1.0 / L, 1.0)
@@ -145,10 +145,12 @@ def test_conjugate_pairs_give_the_full_transform():
         ops = _expected_operands(N)[1]                                       # column stage, scale 1
         u = np.zeros((L, L), complex)
         for b in range(N // 64):
-            for ks in range(N // 32):
-                for ln in range(64):
-                    for i in range(8):
-                        u[32 * b + ln % 32, 16 * ks + 8 * (ln // 32) + i] = ops[b, ks, 0, ln, i] + 1j * ops[b, ks, 1, ln, i]
+            for hf in range(2):
+                for ks in range(N // 64):
+                    for ln in range(64):
+                        for i in range(8):
+                            u[32 * b + 16 * hf + ln % 16, 32 * ks + 8 * (ln // 16) + i] = (
+                                ops[b, hf, ks, 0, ln, i] + 1j * ops[b, hf, ks, 1, ln, i])
         P1, P2 = u.real @ x.real, u.imag @ x.imag
         P3, P4 = u.imag @ x.real, u.real @ x.imag
         base, part = (P1 - P2) + 1j * (P3 + P4), (P1 + P2) + 1j * (P4 - P3)
