@@ -396,16 +396,16 @@ void mfma_kernel(MfmaArgs a) {
         a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(x * a.scale);
       }
     };
+    // both 64-byte halves of an image row's 128-byte line go out back to back
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int e = 0; e < 8; ++e) {
+      const int r = 32 * rb + 16 * (e / 4) + 4 * g16 + (e % 4);
+      const int rp = r == 0 ? L : N - r;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int r = 32 * rb + 16 * (e / 4) + 4 * g16 + (e % 4);
-        const int q = 32 * qc + 16 * h + l16;
-        const int rp = r == 0 ? L : N - r;
-        put(r, q, fmaf(2.f, acc_d[h][e], acc_s[h][e]));
-        put(rp, q, fmaf(-2.f, acc_d[h][e], acc_s[h][e]));
-      }
+      for (int h = 0; h < 2; ++h) put(r, 32 * qc + 16 * h + l16, fmaf(2.f, acc_d[h][e], acc_s[h][e]));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) put(rp, 32 * qc + 16 * h + l16, fmaf(-2.f, acc_d[h][e], acc_s[h][e]));
+    }
     if (tid < a.n_types) {
       if (a.mode == kModePartial) {
         a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
