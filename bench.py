@@ -35,7 +35,7 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "abaa681d70ce66b7"
+TRAFFIC_SOURCES_SHA = "53fa079c38f41cf2"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
     (2, "f32", 0, 256): (32979, 16384),
@@ -54,14 +54,22 @@ TRAFFIC_KIB = {
     (2, "f32", 1, 2048): (16616, 131136),
     (2, "f32", 1, 4096): (16624, 262272),
     (2, "f32", 1, 8192): (16620, 524544),
-    (4, "f16", 0, 128): (129218, 8192),
-    (4, "f16", 0, 256): (128546, 16392),
-    (4, "f16", 0, 512): (128758, 32785),
-    (4, "f16", 0, 768): (128971, 49177),
-    (4, "f16", 0, 1024): (129183, 65569),
-    (4, "f16", 0, 2048): (129631, 131136),
-    (4, "f16", 0, 4096): (129551, 262272),
-    (4, "f16", 0, 8192): (130627, 524544),
+    (4, "f16", 0, 128): (129020, 8192),
+    (4, "f16", 0, 256): (128460, 16392),
+    (4, "f16", 0, 512): (128672, 32785),
+    (4, "f16", 0, 768): (128884, 49177),
+    (4, "f16", 0, 1024): (129097, 65569),
+    (4, "f16", 0, 2048): (129634, 131136),
+    (4, "f16", 0, 4096): (129589, 262272),
+    (4, "f16", 0, 8192): (130022, 524544),
+    (4, "bf16", 0, 128): (129004, 8192),
+    (4, "bf16", 0, 256): (128440, 16393),
+    (4, "bf16", 0, 512): (128653, 32785),
+    (4, "bf16", 0, 768): (128866, 49177),
+    (4, "bf16", 0, 1024): (129078, 65569),
+    (4, "bf16", 0, 2048): (129609, 131136),
+    (4, "bf16", 0, 4096): (129635, 262272),
+    (4, "bf16", 0, 8192): (130180, 524546),
 }
 
 
