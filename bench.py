@@ -35,17 +35,17 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "53fa079c38f41cf2"
+TRAFFIC_SOURCES_SHA = "1283a2a638ca3637"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
     (2, "f32", 0, 256): (32979, 16384),
-    (2, "f32", 0, 512): (32434, 32776),
-    (2, "f32", 0, 1024): (32434, 65552),
-    (2, "f32", 0, 2048): (32449, 131104),
-    (2, "f32", 0, 3072): (32440, 196656),
-    (2, "f32", 0, 4096): (32440, 262208),
-    (2, "f32", 0, 8192): (32439, 524416),
-    (2, "f32", 0, 16384): (32439, 1048832),
+    (2, "f32", 0, 512): (32435, 16392),
+    (2, "f32", 0, 1024): (32435, 32784),
+    (2, "f32", 0, 2048): (32447, 65568),
+    (2, "f32", 0, 3072): (32441, 98352),
+    (2, "f32", 0, 4096): (32439, 131136),
+    (2, "f32", 0, 8192): (32437, 262272),
+    (2, "f32", 0, 16384): (32437, 524544),
     (2, "f32", 1, 128): (17197, 8192),
     (2, "f32", 1, 256): (16616, 16393),
     (2, "f32", 1, 512): (16616, 32785),

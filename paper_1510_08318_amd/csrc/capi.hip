@@ -308,6 +308,7 @@ moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, in
   r.n_chan = hp.n_chan;
   r.n_types = hp.n_ktypes;
   r.slices = lc.slices;
+  r.sx = is_mfma(hp) ? 1 : moff::frame_shape(hp.N, lc.variant).SX;
   r.final_image = final_image ? 1 : 0;
   r.subtract = subtract;
   r.scale = scale;

@@ -39,6 +39,7 @@ struct ReduceArgs {
   float* out;
   double* outA;
   int N, n_chan, n_types, slices;
+  int sx;                      // column classes of the partials' row layout (1: pixel order)
   int final_image, subtract;
   double scale;
 };

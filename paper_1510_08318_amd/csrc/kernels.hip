@@ -161,7 +161,12 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
       const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
       const size_t pix = static_cast<size_t>(pr) * N + pq;
       if (a.mode == kModePartial) {
-        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = acc[idx];
+        // Partial sums are stored class-major within each image row (this
+        // class's M columns contiguous, pq = SX * pcol + w), so that every
+        // 128-byte line has one writer; the reduction reads them back in
+        // pixel order.
+        const size_t ppix = static_cast<size_t>(pr) * N + static_cast<size_t>(w) * C::M + ((col + C::M / 2) & (C::M - 1));
+        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + ppix] = acc[idx];
       } else if (a.mode == kModeAccum) {
         a.out[static_cast<size_t>(c) * img_stride + pix] += acc[idx];
       } else {
@@ -319,14 +324,18 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const double2* Dp, 
 }
 
 // Sum per-slice partials in slice order; then remove self power and average
-// (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
+// (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).  Partials
+// are laid out class-major within each row when a.sx > 1 (pixel column
+// pq = sx * j + k stored at k * (N / sx) + j).
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const size_t npix = static_cast<size_t>(a.N) * a.N;
   const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= npix * a.n_chan) return;
   const size_t c = i / npix, pix = i % npix;
+  const int pr = static_cast<int>(pix / a.N), pq = static_cast<int>(pix % a.N);
+  const size_t ppix = static_cast<size_t>(pr) * a.N + static_cast<size_t>(pq % a.sx) * (a.N / a.sx) + pq / a.sx;
   double s = 0.0;
-  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + pix];
+  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + ppix];
   double A[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < a.n_types; ++p)
     for (int sl = 0; sl < a.slices; ++sl) A[p] += a.A_part[(static_cast<size_t>(sl) * a.n_chan + c) * a.n_types + p];
@@ -718,6 +727,7 @@ int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
+  if (a.sx < 1 || a.N % a.sx != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
