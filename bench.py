@@ -8,12 +8,15 @@ samples of 4+4-bit complex input, 128 x 128 padded grid: 128,000 frames per step
 timing starts.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--staged]
-                    [--config 1..5] [--precision f32|f16|bf16] [--adjoint]
+                    [--config 1..5] [--precision f32|f16|bf16] [--adjoint] [--fx]
 
 --precision f16 / bf16 runs the reduced-precision path (16-bit gridded fields,
 dense DFT on the matrix cores, float32 accumulation; grid 64 or 128) and also
 times the float32 path on the same input; the CPU-baseline leg's oracle images
-then give the per-image error of both.  Prints one JSON line.
+then give the per-image error of both.  --fx also times the visibility route
+(moff_image_fx: correlate all antenna pairs, grid the visibilities, one
+transform per channel) on the same input, the method MOFF is compared with in
+the paper.  Prints one JSON line.
 """
 import argparse
 import json
@@ -212,6 +215,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
+    ap.add_argument("--fx", action="store_true", help="also time the visibility (FX) route on the same input")
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--grid", type=int, default=0, help="override the workload's grid size")
     ap.add_argument("--precision", choices=("f32", "f16", "bf16"), default=None,
@@ -293,6 +297,23 @@ def main():
         extra["staged_ms_per_step"] = round(st_ms, 3)
         extra["fused_speedup_vs_staged"] = round(st_ms / ms_per_step, 2)
         extra["staged_vs_fused_max_abs_diff"] = float((out2 - out).abs().max().item())
+
+    if args.fx:
+        out3 = torch.empty_like(out)
+        plan.image_fx(E, gains, out=out3)
+        torch.cuda.synchronize()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(3):
+            plan.image_fx(E, gains, out=out3)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        fx_ms = f0.elapsed_time(f1) / 3
+        extra["fx_ms_per_step"] = round(fx_ms, 3)
+        extra["fx_frames_per_s"] = frames / (fx_ms / 1e3)
+        extra["moff_speedup_vs_fx"] = round(fx_ms / ms_per_step, 2)
+        extra["fx_vs_moff_max_abs_diff_rel"] = float((out3 - out).abs().max().item() / out.abs().max().item())
 
     if args.adjoint:
         g_in = gains if gains is not None else torch.ones((C, Na), dtype=torch.complex64, device=dev)

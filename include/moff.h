@@ -339,6 +339,35 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
                               const float* gains_dev, float* image_dev, void* hip_stream);
 
 /* ---------------------------------------------------------------------------
+ * Visibility route (FX), for cross-checks of the MOFF image on the device.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * The same integration imaged by the paper's other method (Sec. 2): the pair
+ * cross-products of the calibrated fields, V_ab = sum_t e_a conj(e_b) with
+ * e = g E (eq. cc-vis), are gridded with each pair's power response -- the
+ * cross-correlation of the two placed illumination tables (eq. e-field-conv) --
+ * on the (2L - 1)^2 grid of footprint lags, L = grid_n / 2, and transformed
+ * once per channel (eq. dirty-image-FX), in the pixel order of moff_image.
+ *   E_dev, gains_dev, image_dev : as for moff_image.
+ * The zero-spacing (a == b) terms are kept under MOFF_AUTOCORR_NONE and left
+ * out otherwise, which is the exact self-power removal: the result then equals
+ * moff_image's default image to rounding.  MOFF_AUTOCORR_UV and the
+ * MOFF_MFMA_* flags do not apply here (float32 products, float64 sums).
+ * MOFF_NORM_PAIRS scales as for moff_image.
+ * Cost: O(n_chan (n_time n_ant^2 + n_ant^2 + N^3)) work and a workspace of
+ * 8 n_chan (n_ant^2 + (n_types^2 + 1) (2L - 1)^2 + (2L - 1) N) bytes, owned by
+ * the plan (shared with the other entry points of the plan).  The pair tables
+ * (4 n_ant^2 bytes) are built and uploaded on the first call.
+ * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
+ * MOFF_ERR_UNSUPPORTED for a plan without a device or more than 65535 channels;
+ * MOFF_ERR_NOMEM when the workspace cannot be allocated; MOFF_ERR_HIP for a
+ * failed launch.
+ */
+moff_status moff_image_fx(moff_plan plan, const void* E_dev, int64_t n_time,
+                          const float* gains_dev, float* image_dev, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
  * Gain gradient (calibration feedback, Sec. 3 "Calibration"; the image is
  * differentiable in the complex gains applied before gridding).
  * ------------------------------------------------------------------------- */

@@ -275,6 +275,18 @@ class Plan:
         _lib.moff_image_staged(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
         return out
 
+    def image_fx(self, E, gains=None, out=None, stream=None):
+        """Visibility-route (FX) image of the same integration: pair
+        cross-products gridded with the tables' pair responses and transformed
+        once; equals image() to rounding (zero spacings as for image())."""
+        torch = self._torch()
+        pE, T = self._E(E)
+        if out is None:
+            out = self._new((self.n_chan, self.N, self.N), torch.float32)
+        po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_image_fx(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
+        return out
+
     def gain_vjp(self, E, gains, dL_dimage, out=None, stream=None, staged=False):
         """dL/dRe(g) + i dL/dIm(g) (complex64 [n_chan, n_ant]) for R = dL/dI
         (staged=True: the HBM-staged form of the same computation)."""

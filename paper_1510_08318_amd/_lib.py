@@ -85,6 +85,8 @@ SIGNATURES = {
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "moff_image_staged": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "moff_image_fx": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -219,6 +221,10 @@ def moff_detect_accumulate(plan, y, n_time, S, stream):
 
 def moff_image_staged(plan, E, n_time, gains, image, stream):
     _call("moff_image_staged", plan, E, n_time, gains, image, stream)
+
+
+def moff_image_fx(plan, E, n_time, gains, image, stream):
+    _call("moff_image_fx", plan, E, n_time, gains, image, stream)
 
 
 def moff_gain_vjp_staged(plan, E, n_time, gains, dL_dimage, dL_dgains, stream):

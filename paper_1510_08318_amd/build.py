@@ -46,11 +46,11 @@ def build(verbose: bool = False, extra_hip_flags=None) -> str:
     jobs.append([gxx, *HOST_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
                  os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
     objs = [plan_o]
-    for src in ("kernels.hip", "mfma.hip", "uv_autocorr.hip", "capi.hip"):
+    for src in ("kernels.hip", "mfma.hip", "uv_autocorr.hip", "fx.hip", "capi.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         jobs.append([HIPCC, *HIP_FLAGS, *(extra_hip_flags or []), *inc, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
-    with ThreadPoolExecutor(max_workers=5) as ex:
+    with ThreadPoolExecutor(max_workers=6) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp], verbose)

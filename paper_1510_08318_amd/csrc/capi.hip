@@ -35,6 +35,11 @@ struct moff_plan_s {
   uint16_t* d_mfma_dft = nullptr;
   double* d_Pn = nullptr;               // uv-plane autocorrelation rule (MOFF_AUTOCORR_UV)
   uint32_t* d_adj_slots = nullptr;      // fused adjoint: antennas per lane (variant 0); null if they do not fit
+  // visibility route (moff_image_fx), built on first use
+  int* d_fx_ptr = nullptr;
+  int* d_fx_ab = nullptr;
+  float2* d_fx_x = nullptr;
+  int fx_NL = 0, fx_xs = 0;
   // workspace, grown on demand
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
@@ -82,7 +87,7 @@ void free_device(moff_plan p) {
   void* ptrs[] = {p->d_tw,        p->d_Pp,        p->d_ant_type, p->d_ktab,        p->d_csr_ptr,
                   p->d_csr_ant,   p->d_csr_tap,   p->d_ant_cells, p->d_ktype_k,    p->d_ktype_off,
                   p->d_mfma_prog, p->d_mfma_dft,  p->d_Pn,        p->d_ws,         p->d_aux,
-                  p->d_adj_slots};
+                  p->d_adj_slots, p->d_fx_ptr,    p->d_fx_ab,     p->d_fx_x};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
@@ -927,6 +932,68 @@ moff_status moff_image_staged(moff_plan p, const void* E, int64_t n_time, const 
   fa.subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
   fa.scale = image_scale(hp, n_time);
   return hip_status(moff::launch_finalize(fa, st));
+}
+
+moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const float* gains, float* image,
+                          void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  const HostPlan& hp = p->hp;
+  if (hp.n_chan > 65535) return MOFF_ERR_UNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  const bool keep_autos = (hp.flags & MOFF_AUTOCORR_NONE) != 0;
+  if (!p->d_fx_ptr) {
+    moff::FxTables t;
+    moff::build_fx_tables(hp, keep_autos, &t);
+    moff_status u = upload(&p->d_fx_ptr, t.ptr.data(), sizeof(int32_t) * t.ptr.size());
+    if (u == MOFF_OK) u = upload(&p->d_fx_ab, t.ab.data(), sizeof(int32_t) * t.ab.size());
+    if (u == MOFF_OK) u = upload(&p->d_fx_x, t.xcorr.data(), sizeof(float) * t.xcorr.size());
+    if (u != MOFF_OK) {
+      for (void** q : {reinterpret_cast<void**>(&p->d_fx_ptr), reinterpret_cast<void**>(&p->d_fx_ab),
+                       reinterpret_cast<void**>(&p->d_fx_x)})
+        if (*q) {
+          (void)hipFree(*q);
+          *q = nullptr;
+        }
+      return u;
+    }
+    p->fx_NL = t.NL;
+    p->fx_xs = t.xs;
+  }
+  const int NL = p->fx_NL, NTP = hp.n_ktypes * hp.n_ktypes;
+  const size_t C = hp.n_chan;
+  const size_t v_bytes = sizeof(float2) * C * hp.n_ant * hp.n_ant;
+  const size_t h_bytes = sizeof(float2) * C * NTP * NL * NL;
+  const size_t r_bytes = sizeof(float2) * C * NL * NL;
+  const size_t z_bytes = sizeof(float2) * C * NL * hp.N;
+  s = ensure_workspace(p, v_bytes + h_bytes + r_bytes + z_bytes);
+  if (s != MOFF_OK) return s;
+  char* ws = static_cast<char*>(p->d_ws);
+  moff::FxArgs a{};
+  a.E = E;
+  a.gains = reinterpret_cast<const float2*>(gains);
+  a.n_ant = hp.n_ant;
+  a.n_chan = hp.n_chan;
+  a.n_types = hp.n_ktypes;
+  a.n_time = n_time;
+  a.N = hp.N;
+  a.L = hp.L;
+  a.NL = NL;
+  a.xs = p->fx_xs;
+  a.pair_ptr = p->d_fx_ptr;
+  a.pair_ab = p->d_fx_ab;
+  a.ktype_k = p->d_ktype_k;
+  a.xcorr = p->d_fx_x;
+  a.tw = p->d_tw;
+  a.V = reinterpret_cast<float2*>(ws);
+  a.H = reinterpret_cast<float2*>(ws + v_bytes);
+  a.R = reinterpret_cast<float2*>(ws + v_bytes + h_bytes);
+  a.Z = reinterpret_cast<float2*>(ws + v_bytes + h_bytes + r_bytes);
+  a.out = image;
+  a.scale = image_scale(hp, n_time);
+  return hip_status(moff::launch_fx(a, hp.flags & MOFF_IN_CI4, static_cast<hipStream_t>(stream)));
 }
 
 moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* gains, const float* dL_dimage,
