@@ -8,6 +8,8 @@
 //
 //   fx_correlate_kernel  V[c][a][b] = sum_t e_a conj(e_b), e = g E: float32
 //                        products over 32-sample chunks, chunks summed in float64
+//                        (complex64 samples); fx_correlate_i8_kernel: exact
+//                        integer products on the matrix cores (4+4-bit samples)
 //   fx_bin_kernel        H[c][pq][dy][dx] = sum of V[c][a][b] over the pairs of
 //                        table types (p, q) whose footprints are offset by
 //                        (dy, dx) - (L - 1) cells (plan-time CSR, fixed order)
@@ -102,6 +104,80 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
     }
 }
 
+// 4+4-bit samples: the cross-products are exact integer sums, formed on the
+// matrix cores (v_mfma_i32_16x16x64_i8, int32 accumulation) from the raw
+// samples; the gains are constant over the integration and are applied once,
+// V_ab = g_a conj(g_b) sum_t E_a conj(E_b), in float64.  One workgroup per
+// (32 x 32 antenna tile, channel), four waves of one 16 x 16 sub-tile each; per
+// 64-sample step the real and imaginary parts of both antenna blocks are staged
+// in LDS as int8 rows [antenna][sample] and each wave runs four products
+// (re.re, im.im, im.re, re.im).  A and B take their samples in the same lane
+// order, so the sum covers each sample once whatever order the instruction
+// gives its contraction index; the accumulators hold D[4 (l / 16) + j][l % 16].
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+constexpr int kI8Step = 64;                 // samples per step
+constexpr int kI8Pitch = kI8Step + 16;      // LDS row bytes: 16-byte operand reads of 16 rows hit distinct banks
+
+__global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
+  __shared__ __attribute__((aligned(16))) int8_t pl[4][kFxTile][kI8Pitch];   // re A, im A, re B, im B
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, c = blockIdx.z;
+  const int na = a.n_ant;
+  const int8_t* E = reinterpret_cast<const int8_t*>(a.E);
+  const size_t tstride = static_cast<size_t>(a.n_chan) * na;
+  // staging: thread = (antenna an, group of 8 samples tg) for both blocks
+  const int an = tid % kFxTile, tg = tid / kFxTile;   // tg < 8
+  // this wave's sub-tile and its operand rows
+  const int ah = w >> 1, bh = w & 1, l16 = lane & 15, g = lane >> 4;
+  i32x4 pxx = {0, 0, 0, 0}, pyy = pxx, pyx = pxx, pxy = pxx;
+  for (int64_t t0 = 0; t0 < a.n_time; t0 += kI8Step) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      const int ant = (blk ? b0 : a0) + an;
+      uint64_t xr = 0, xi = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int64_t t = t0 + 8 * tg + i;
+        int8_t byte = 0;
+        if (ant < na && t < a.n_time) byte = E[static_cast<size_t>(t) * tstride + static_cast<size_t>(c) * na + ant];
+        const int8_t re = static_cast<int8_t>(byte >> 4);
+        const int8_t im = static_cast<int8_t>(static_cast<int8_t>(byte << 4) >> 4);
+        xr |= static_cast<uint64_t>(static_cast<uint8_t>(re)) << (8 * i);
+        xi |= static_cast<uint64_t>(static_cast<uint8_t>(im)) << (8 * i);
+      }
+      *reinterpret_cast<uint64_t*>(&pl[2 * blk][an][8 * tg]) = xr;
+      *reinterpret_cast<uint64_t*>(&pl[2 * blk + 1][an][8 * tg]) = xi;
+    }
+    __syncthreads();
+    const i32x4 ar = *reinterpret_cast<const i32x4*>(&pl[0][16 * ah + l16][16 * g]);
+    const i32x4 ai = *reinterpret_cast<const i32x4*>(&pl[1][16 * ah + l16][16 * g]);
+    const i32x4 br = *reinterpret_cast<const i32x4*>(&pl[2][16 * bh + l16][16 * g]);
+    const i32x4 bi = *reinterpret_cast<const i32x4*>(&pl[3][16 * bh + l16][16 * g]);
+    pxx = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, br, pxx, 0, 0, 0);
+    pyy = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, pyy, 0, 0, 0);
+    pyx = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, br, pyx, 0, 0, 0);
+    pxy = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, bi, pxy, 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int ia = a0 + 16 * ah + 4 * g + j, ib = b0 + 16 * bh + l16;
+    if (ia >= na || ib >= na) continue;
+    // E_a conj(E_b) = (xa xb + ya yb) + i (ya xb - xa yb)
+    const double vr = static_cast<double>(pxx[j]) + pyy[j], vi = static_cast<double>(pyx[j]) - pxy[j];
+    double zr = vr, zi = vi;
+    if (a.gains) {
+      const float2 ga = a.gains[static_cast<size_t>(c) * na + ia], gb = a.gains[static_cast<size_t>(c) * na + ib];
+      // g_a conj(g_b)
+      const double gr = static_cast<double>(ga.x) * gb.x + static_cast<double>(ga.y) * gb.y;
+      const double gi = static_cast<double>(ga.y) * gb.x - static_cast<double>(ga.x) * gb.y;
+      zr = gr * vr - gi * vi;
+      zi = gr * vi + gi * vr;
+    }
+    a.V[(static_cast<size_t>(c) * na + ia) * na + ib] = make_float2(static_cast<float>(zr), static_cast<float>(zi));
+  }
+}
+
 // One thread per (channel, type pair, offset cell).
 __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
@@ -167,17 +243,25 @@ __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
   a.Z[(static_cast<size_t>(c) * NL + ly) * N + q] = make_float2(static_cast<float>(x), static_cast<float>(y));
 }
 
-// One workgroup of N threads per (image row r, channel); thread q.
+// One workgroup of N threads per (block of kFxRows image rows, channel);
+// thread q reads each Z[ly][q] once for all the block's rows.
+constexpr int kFxRows = 8;
+
 __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
-  const int N = a.N, NL = a.NL, r = blockIdx.x, c = blockIdx.y, q = threadIdx.x;
-  const int s = r - N / 2;
+  const int N = a.N, NL = a.NL, r0 = blockIdx.x * kFxRows, c = blockIdx.y, q = threadIdx.x;
   const float2* Z = a.Z + static_cast<size_t>(c) * NL * N;
-  double x = 0.0;
+  double x[kFxRows] = {};
   for (int ly = 0; ly < NL; ++ly) {
-    const float2 w = a.tw[((ly - (a.L - 1)) * s) & (N - 1)], z = Z[static_cast<size_t>(ly) * N + q];
-    x += static_cast<double>(w.x) * z.x - static_cast<double>(w.y) * z.y;
+    const float2 z = Z[static_cast<size_t>(ly) * N + q];
+    const int d = ly - (a.L - 1);
+#pragma unroll
+    for (int k = 0; k < kFxRows; ++k) {
+      const float2 w = a.tw[(d * (r0 + k - N / 2)) & (N - 1)];
+      x[k] += static_cast<double>(w.x) * z.x - static_cast<double>(w.y) * z.y;
+    }
   }
-  a.out[(static_cast<size_t>(c) * N + r) * N + q] = static_cast<float>(x * a.scale);
+#pragma unroll
+  for (int k = 0; k < kFxRows; ++k) a.out[(static_cast<size_t>(c) * N + r0 + k) * N + q] = static_cast<float>(x[k] * a.scale);
 }
 
 hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
@@ -187,7 +271,7 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   const unsigned tiles = static_cast<unsigned>((a.n_ant + kFxTile - 1) / kFxTile);
   const dim3 g1(tiles, tiles, static_cast<unsigned>(a.n_chan));
   if (ci4)
-    hipLaunchKernelGGL(fx_correlate_kernel<true>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(fx_correlate_i8_kernel, g1, dim3(256), 0, st, a);
   else
     hipLaunchKernelGGL(fx_correlate_kernel<false>, g1, dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
@@ -201,7 +285,7 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   const size_t lds = sizeof(float2) * (a.NL + a.N);
   hipLaunchKernelGGL(fx_row_kernel, dim3(a.NL, a.n_chan), dim3(a.N), lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N, a.n_chan), dim3(a.N), 0, st, a);
+  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / kFxRows, a.n_chan), dim3(a.N), 0, st, a);
   return hipGetLastError();
 }
 
