@@ -13,7 +13,9 @@ timing starts.
 --precision f16 / bf16 runs the reduced-precision path (16-bit gridded fields,
 dense DFT on the matrix cores, float32 accumulation; grid 64 or 128) and also
 times the float32 path on the same input; the CPU-baseline leg's oracle images
-then give the per-image error of both.  --fx also times the visibility route
+then give the per-image error of both.  The CPU leg also times the oracle on
+one core and the paper's own CPU form of the pipeline (sparse gridding matrix
++ scipy.fft, float64 and float32, all cores and one), in `extra`.  --fx also times the visibility route
 (moff_image_fx: correlate all antenna pairs, grid the visibilities, one
 transform per channel) on the same input, the method MOFF is compared with in
 the paper.  Prints one JSON line.
@@ -157,6 +159,106 @@ def cpu_baseline(w, budget_s=10.0):
             "sample": f"{n} channel(s) x all {T} time samples of the same workload "
                       f"({n * T} frames, {dt:.1f} s, float64 NumPy oracle)"}
     return line, images
+
+
+def oracle_single_core(w, budget_s=3.0):
+    """The FP64 oracle on one host core (BLAS limited to one thread): whole
+    channels until about budget_s; frames/s."""
+    import oracle
+    from threadpoolctl import threadpool_limits
+    P = oracle.plan(w.geom)
+    T = w.E.shape[0]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        n = 0
+        while n < w.E.shape[1]:
+            oracle.moff_channel(w.geom, w.E, w.gains, n, P)
+            n += 1
+            if time.perf_counter() - t0 >= budget_s:
+                break
+        dt = time.perf_counter() - t0
+    return {"value": n * T / dt, "unit": "frames/s", "cores": 1, "sample": f"{n} channel(s) x {T} samples, {dt:.1f} s"}
+
+
+def cpu_pipeline(w, plan, ref_images, budget_s=2.5):
+    """The paper's own CPU form of the pipeline (Sec. 3: gridding as one sparse
+    matrix product per readout, then the 2-D FFT of the zero-padded grid,
+    squaring, accumulation and self-power removal), written with SciPy: a CSR
+    gridding matrix from the plan's cells and tables, scipy.fft with the
+    positive exponent and no normalisation, pixel N/2 at the phase centre.
+    Timed in float64 and float32, on all host cores and on one, over whole
+    channels (all time samples) until about budget_s per variant; the first
+    sampled channel is checked against the oracle image of the CPU-baseline
+    leg.  Context for the CPU baseline, not the target."""
+    import numpy as np
+    import scipy.fft as sfft
+    import scipy.sparse as sp
+    import synth
+    from threadpoolctl import threadpool_limits
+    g = w.geom
+    Na, N, T, C = g.n_ant, g.grid_n, w.E.shape[0], g.n_chan
+    L = N // 2
+    nt = len(g.ktype_k)
+    cells = plan.cells()
+    rows, cols, vals = [], [], []
+    for a in range(Na):
+        K = np.asarray(g.ktype_vals[int(g.ant_ktype[a])], np.complex128)
+        k = K.shape[0]
+        ix0, iy0 = int(cells[a, 0]), int(cells[a, 1])
+        for u in range(k):
+            for v in range(k):
+                rows.append((iy0 + u) * L + ix0 + v)
+                cols.append(a)
+                vals.append(K[u, v])
+    W = sp.csr_matrix((np.asarray(vals), (rows, cols)), shape=(L * L, Na))
+    Pp = np.stack([plan.power_pattern(p) for p in range(nt)])
+    types = np.asarray(g.ant_ktype)
+    ci4 = bool(g.flags & synth.IN_CI4)
+    pairs = bool(g.flags & synth.NORM_PAIRS)
+
+    def field(c, dt):
+        x = w.E[:, c, :]
+        if ci4:
+            b = x.view(np.int8)
+            e = (b >> 4).astype(np.float64) + 1j * ((b << 4).astype(np.int8) >> 4).astype(np.float64)
+        else:
+            e = x.astype(np.complex128)
+        if w.gains is not None:
+            e = e * w.gains[c][None, :]
+        return e.astype(dt)
+
+    def channel(c, dt, workers):
+        e = field(c, dt)
+        grid = np.zeros((T, N, N), dt)
+        grid[:, :L, :L] = (W.astype(dt) @ e.T).T.reshape(T, L, L)
+        Y = sfft.fftshift(sfft.ifft2(grid, axes=(1, 2), norm="forward", workers=workers), axes=(1, 2))
+        S = (Y.real.astype(np.float64) ** 2 + Y.imag.astype(np.float64) ** 2).sum(0)
+        A = np.array([(np.abs(e[:, types == p].astype(np.complex128)) ** 2).sum() for p in range(nt)])
+        img = (S - np.tensordot(A, Pp, 1)) / T
+        return img / (Na * (Na - 1)) if pairs else img
+
+    ncores = os.cpu_count() or 1
+    out = {}
+    for name, dt in (("f64", np.complex128), ("f32", np.complex64)):
+        for cores in (ncores, 1):
+            with threadpool_limits(limits=cores):
+                channel(0, dt, cores)   # warm-up
+                t0 = time.perf_counter()
+                n = 0
+                while n < C:
+                    channel(n, dt, cores)
+                    n += 1
+                    if time.perf_counter() - t0 >= budget_s:
+                        break
+                dt_s = time.perf_counter() - t0
+            out[f"scipy_{name}_{cores}core"] = {"value": n * T / dt_s, "unit": "frames/s", "cores": cores,
+                                                "sample": f"{n} channel(s) x {T} samples, {dt_s:.1f} s"}
+    if ref_images:
+        c, ref, pbar = ref_images[0]
+        for name, dt in (("f64", np.complex128), ("f32", np.complex64)):
+            d = channel(c, dt, ncores) - ref
+            out[f"scipy_{name}_err_inf_vs_oracle"] = float(f"{np.abs(d).max() / np.abs(pbar).max():.3g}")
+    return out
 
 
 def image_errors(img, ref_images):
@@ -350,6 +452,8 @@ def main():
         extra["error_vs_oracle"] = {prec: image_errors(img, ref_images)}
         if prec != "f32":
             extra["error_vs_oracle"]["f32"] = image_errors(out32.cpu().numpy(), ref_images)
+        extra["cpu_oracle_1core"] = oracle_single_core(w)
+        extra["cpu_pipeline"] = cpu_pipeline(w, plan, ref_images)
         del ref_images
 
     line = {
