@@ -40,7 +40,7 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "1283a2a638ca3637"
+TRAFFIC_SOURCES_SHA = "562bcc618c8e24ac"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
     (2, "f32", 0, 256): (32979, 16384),

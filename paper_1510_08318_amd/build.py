@@ -41,16 +41,17 @@ def build(verbose: bool = False, extra_hip_flags=None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     inc = ["-I", os.path.join(HERE, "..", "include")]
     jobs = []
-    plan_o = os.path.join(BUILD, "plan.o")
     gxx = shutil.which("g++") or "g++"
-    jobs.append([gxx, *HOST_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c",
-                 os.path.join(CSRC, "plan.cpp"), "-o", plan_o])
-    objs = [plan_o]
+    objs = []
+    for src in ("plan.cpp", "fx_tables.cpp"):
+        o = os.path.join(BUILD, src.replace(".cpp", ".o"))
+        jobs.append([gxx, *HOST_FLAGS, *inc, "-I", os.path.join(ROCM, "include"), "-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
     for src in ("kernels.hip", "mfma.hip", "uv_autocorr.hip", "fx.hip", "capi.hip"):
         o = os.path.join(BUILD, src.replace(".hip", ".o"))
         jobs.append([HIPCC, *HIP_FLAGS, *(extra_hip_flags or []), *inc, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
-    with ThreadPoolExecutor(max_workers=6) as ex:
+    with ThreadPoolExecutor(max_workers=7) as ex:
         list(ex.map(lambda c: _run(c, verbose), jobs))
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp], verbose)

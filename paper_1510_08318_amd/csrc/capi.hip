@@ -9,6 +9,8 @@
 #include <vector>
 
 #include "../../include/moff.h"
+#include "fx.h"
+#include "fx_tables.h"
 #include "kernels.h"
 #include "plan.h"
 

@@ -25,8 +25,8 @@
 
 #include <cstdint>
 
+#include "fx.h"
 #include "ingest.h"
-#include "kernels.h"
 
 namespace moff {
 
@@ -41,14 +41,14 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 
 }  // namespace
 
-// One workgroup per (32 x 32 antenna tile, channel); thread (ty, tx) owns the
-// pairs (ty + 16 i, tx + 16 j), i, j < 2.
-template <bool CI4>
+// Complex64 samples.  One workgroup per (32 x 32 antenna tile, channel); thread
+// (ty, tx) owns the pairs (ty + 16 i, tx + 16 j), i, j < 2.
 __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   __shared__ float2 ea[kFxChunk][kFxTile + 1], eb[kFxChunk][kFxTile + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
   const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, c = blockIdx.z;
   const int na = a.n_ant;
+  const float2* E = reinterpret_cast<const float2*>(a.E);
   double acc[2][2][2] = {};
   for (int64_t t0 = 0; t0 < a.n_time; t0 += kFxChunk) {
     for (int k = tid; k < kFxChunk * kFxTile; k += 256) {
@@ -59,11 +59,11 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
         const size_t base = (static_cast<size_t>(t) * a.n_chan + c) * na;
         const int ia = a0 + an, ib = b0 + an;
         if (ia < na) {
-          va = load_sample(a.E, base + ia, CI4);
+          va = E[base + ia];
           if (a.gains) va = cmul(a.gains[static_cast<size_t>(c) * na + ia], va);
         }
         if (ib < na) {
-          vb = load_sample(a.E, base + ib, CI4);
+          vb = E[base + ib];
           if (a.gains) vb = cmul(a.gains[static_cast<size_t>(c) * na + ib], vb);
         }
       }
@@ -273,7 +273,7 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   if (ci4)
     hipLaunchKernelGGL(fx_correlate_i8_kernel, g1, dim3(256), 0, st, a);
   else
-    hipLaunchKernelGGL(fx_correlate_kernel<false>, g1, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(fx_correlate_kernel, g1, dim3(256), 0, st, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;

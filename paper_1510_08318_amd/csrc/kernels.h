@@ -157,29 +157,6 @@ struct UvArgs {
 hipError_t launch_uv_finalize(const UvArgs& a, hipStream_t st);
 hipError_t launch_uv_adjoint_shift(const UvArgs& a, hipStream_t st);
 
-// Visibility-route (FX) image of one integration, for cross-checks of the MOFF
-// image on the device (fx.hip).  NL = 2L - 1 lags per axis, NTP = n_types^2
-// ordered pairs of table types.
-struct FxArgs {
-  const void* E;
-  const float2* gains;         // [n_chan][n_ant] or null (unit gains)
-  int n_ant, n_chan, n_types;
-  int64_t n_time;
-  int N, L, NL, xs;            // xs: side of each pair-response table
-  const int* pair_ptr;         // [NTP * NL * NL + 1] CSR over (type pair, footprint offset)
-  const int* pair_ab;          // [entries] a * n_ant + b, ascending within a row
-  const int* ktype_k;          // [n_types]
-  const float2* xcorr;         // [NTP][xs][xs] pair responses of the tables
-  const float2* tw;            // [N] exp(+2 pi i k / N)
-  float2* V;                   // [n_chan][n_ant][n_ant] workspace
-  float2* H;                   // [n_chan][NTP][NL][NL] workspace
-  float2* R;                   // [n_chan][NL][NL] workspace
-  float2* Z;                   // [n_chan][NL][N] workspace
-  float* out;                  // [n_chan][N][N]
-  double scale;
-};
-hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st);
-
 // Fused gain adjoint: one workgroup per (column class, channel, time slice) runs
 // ingest, gridding, the frame transform, the pixel-wise product with R, the
 // adjoint transform and the degridding for every frame, and writes per-antenna

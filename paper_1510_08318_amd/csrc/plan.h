@@ -87,21 +87,6 @@ struct HostPlan {
   } mfma;
 };
 
-// Tables of the visibility-route (FX) image (Sec. 2, eq. dirty-image-FX with
-// eq. e-field-conv), built on first use:
-//   ptr / ab : CSR over (type pair p * n_types + q, footprint offset cell
-//              (iy0_a - iy0_b + L - 1) * NL + ix0_a - ix0_b + L - 1) of the
-//              ordered antenna pairs (a of type p, b of type q) as a * n_ant + b,
-//              ascending; a == b only when the zero-spacing terms are kept.
-//   xcorr    : per type pair, X[u][v] = sum K_p[s][t] conj(K_q[s - u + k_q - 1][t - v + k_q - 1])
-//              on a (k_p + k_q - 1)^2 support, stored [pair][xs][xs] as float32 (re, im).
-struct FxTables {
-  int NL = 0, xs = 0;
-  std::vector<int32_t> ptr, ab;
-  std::vector<float> xcorr;
-};
-void build_fx_tables(const HostPlan& hp, bool keep_autos, FxTables* t);
-
 // 16-bit encodings of a float64 value, rounded to nearest (ties to even).
 uint16_t to_binary16(double x);
 uint16_t to_bfloat16(double x);
