@@ -360,7 +360,9 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  * the plan (shared with the other entry points of the plan).  The pair tables
  * (4 n_ant^2 bytes) are built and uploaded on the first call.
  * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
- * MOFF_ERR_UNSUPPORTED for a plan without a device or more than 65535 channels;
+ * MOFF_ERR_UNSUPPORTED for a plan without a device, more than 65535 channels,
+ * or 4+4-bit samples with n_time > 2^24 (their cross-products are exact int32
+ * sums on the matrix cores);
  * MOFF_ERR_NOMEM when the workspace cannot be allocated; MOFF_ERR_HIP for a
  * failed launch.
  */

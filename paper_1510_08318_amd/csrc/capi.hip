@@ -943,6 +943,8 @@ moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const floa
   if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
   const HostPlan& hp = p->hp;
   if (hp.n_chan > 65535) return MOFF_ERR_UNSUPPORTED;
+  // 4+4-bit samples are correlated in int32: |sum_t x_a x_b| <= 64 n_time
+  if ((hp.flags & MOFF_IN_CI4) && n_time > (int64_t(1) << 24)) return MOFF_ERR_UNSUPPORTED;
   DeviceGuard guard(p->device);
   if (!guard.ok()) return MOFF_ERR_HIP;
   const bool keep_autos = (hp.flags & MOFF_AUTOCORR_NONE) != 0;
