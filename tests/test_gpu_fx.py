@@ -15,7 +15,8 @@ import pytest
 
 import oracle
 import synth
-from test_gpu_parity import CASES, TOL, assert_image_close, moff, oracle_channels, to_dev, torch  # noqa: F401
+from test_gpu_parity import (CASES, TOL, _replay_matches, assert_image_close, moff, oracle_channels,  # noqa: F401
+                             to_dev, torch)
 
 pytestmark = pytest.mark.gpu
 
@@ -89,3 +90,20 @@ def test_fx_rejects_bad_arguments(torch, moff):
         E = to_dev(torch, w.E)
         with pytest.raises(moff.MoffError):
             p.image_fx(E[:0])
+
+
+@pytest.mark.parametrize("case", ["config2_sub", "config5_sub"])
+def test_fx_deterministic_and_graph_replay(torch, moff, case):
+    """Fixed-order sums: two eager calls agree bitwise, and the route captured in
+    a HIP graph (after the first call has built its tables and workspace)
+    reproduces the eager image on every replay (4+4-bit: int8 matrix-core
+    correlator; complex64: float32 correlator)."""
+    w = CASES[case]()
+    C, N = w.geom.n_chan, w.geom.grid_n
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        g = to_dev(torch, w.gains) if w.gains is not None else None
+        first = p.image_fx(E, g).clone()
+        out = torch.empty((C, N, N), dtype=torch.float32, device="cuda:0")
+        eager = _replay_matches(torch, lambda st: p.image_fx(E, g, out=out, stream=st), out)
+        assert torch.equal(first, eager)
