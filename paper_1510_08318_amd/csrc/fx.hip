@@ -14,13 +14,16 @@
 //                        table types (p, q) whose footprints are offset by
 //                        (dy, dx) - (L - 1) cells (plan-time CSR, fixed order)
 //   fx_lag_kernel        R[c][ly][lx] = sum_pq sum_(u,v) X_pq[u][v]
-//                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]
+//                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]  (LDS-tiled)
 //   fx_row_kernel        Z[c][ly][q] = sum_lx R[c][ly][lx] w^((lx - L + 1)(q - N/2))
 //   fx_col_kernel        I[c][r][q] = scale Re sum_ly w^((ly - L + 1)(r - N/2)) Z[c][ly][q]
+//                        (both as N-point radix-2 transforms in LDS, float32)
 //
 // w = exp(+2 pi i / N); lags span -(L - 1) .. L - 1, so the image comes out in
 // the same pixel order as the MOFF image.  Every sum runs in a fixed order
-// (no atomics) and accumulates in float64; intermediate arrays are float32.
+// (no atomics); the correlator and the binning accumulate in float64, each
+// pair response's lag sum in float32 (the pairs in float64), and the two
+// transform passes run in float32; intermediate arrays are float32.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -194,74 +197,132 @@ __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   a.H[static_cast<size_t>(c) * cells + i] = make_float2(static_cast<float>(x), static_cast<float>(y));
 }
 
-// One thread per (channel, lag cell).
+// One workgroup per (16 x 16 block of lag cells, channel), one thread per cell.
+// Per type pair the block's window of H (with a halo of the pair response's
+// side) and the response itself are staged in LDS; cells of H outside the lag
+// grid read as zero.
+constexpr int kLagTile = 16;
+
 __global__ __launch_bounds__(256) void fx_lag_kernel(FxArgs a) {
-  const int NL = a.NL;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= NL * NL) return;
-  const int c = blockIdx.y, ly = i / NL, lx = i % NL;
+  extern __shared__ float2 fx_lds[];
+  const int NL = a.NL, nt = a.n_types, c = blockIdx.z;
+  const int ht = kLagTile + a.xs - 1;             // widest window
+  float2* Ht = fx_lds;                            // [ht][ht]
+  float2* Xt = fx_lds + ht * ht;                  // [side][side]
+  const int tyl = threadIdx.x / kLagTile, txl = threadIdx.x % kLagTile;
+  const int ty0 = blockIdx.y * kLagTile, tx0 = blockIdx.x * kLagTile;
   const size_t plane = static_cast<size_t>(NL) * NL;
   double x = 0.0, y = 0.0;
-  for (int p = 0; p < a.n_types; ++p)
-    for (int q = 0; q < a.n_types; ++q) {
-      const int tp = p * a.n_types + q;
-      const int kb = a.ktype_k[q], side = a.ktype_k[p] + kb - 1;
-      const float2* H = a.H + (static_cast<size_t>(c) * a.n_types * a.n_types + tp) * plane;
-      const float2* X = a.xcorr + static_cast<size_t>(tp) * a.xs * a.xs;
-      for (int u = 0; u < side; ++u) {
-        const int hy = ly - u + kb - 1;
-        if (hy < 0 || hy >= NL) continue;
-        for (int v = 0; v < side; ++v) {
-          const int hx = lx - v + kb - 1;
-          if (hx < 0 || hx >= NL) continue;
-          const float2 h = H[static_cast<size_t>(hy) * NL + hx], w = X[u * a.xs + v];
-          x += static_cast<double>(w.x) * h.x - static_cast<double>(w.y) * h.y;
-          y += static_cast<double>(w.x) * h.y + static_cast<double>(w.y) * h.x;
-        }
-      }
+  for (int tp = 0; tp < nt * nt; ++tp) {
+    const int kb = a.ktype_k[tp % nt], side = a.ktype_k[tp / nt] + kb - 1, ext = kLagTile + side - 1;
+    const int hy0 = ty0 + kb - side, hx0 = tx0 + kb - side;
+    const float2* H = a.H + (static_cast<size_t>(c) * nt * nt + tp) * plane;
+    const float2* X = a.xcorr + static_cast<size_t>(tp) * a.xs * a.xs;
+    __syncthreads();   // the previous pair's windows are no longer read
+    for (int i = threadIdx.x; i < ext * ext; i += blockDim.x) {
+      const int hy = hy0 + i / ext, hx = hx0 + i % ext;
+      Ht[(i / ext) * ht + i % ext] =
+          (hy >= 0 && hy < NL && hx >= 0 && hx < NL) ? H[static_cast<size_t>(hy) * NL + hx] : make_float2(0.f, 0.f);
     }
-  a.R[static_cast<size_t>(c) * plane + i] = make_float2(static_cast<float>(x), static_cast<float>(y));
+    for (int i = threadIdx.x; i < side * side; i += blockDim.x) Xt[i] = X[(i / side) * a.xs + i % side];
+    __syncthreads();
+    // H row of response row u: ly - u + kb - 1, i.e. window row tyl - u + side - 1;
+    // one pair's response sum in float32, the pairs combined in float64
+    float px = 0.f, py = 0.f;
+    for (int u = 0; u < side; ++u)
+      for (int v = 0; v < side; ++v) {
+        const float2 h = Ht[(tyl - u + side - 1) * ht + (txl - v + side - 1)], w = Xt[u * side + v];
+        px = fmaf(w.x, h.x, fmaf(-w.y, h.y, px));
+        py = fmaf(w.x, h.y, fmaf(w.y, h.x, py));
+      }
+    x += px;
+    y += py;
+  }
+  const int ly = ty0 + tyl, lx = tx0 + txl;
+  if (ly < NL && lx < NL) a.R[static_cast<size_t>(c) * plane + static_cast<size_t>(ly) * NL + lx] =
+      make_float2(static_cast<float>(x), static_cast<float>(y));
 }
 
-// One workgroup of N threads per (lag row ly, channel); thread q.
+// Radix-2 decimation-in-time transform, in place, of `lines` interleaved lines
+// of N points in LDS (point n of line k at X[n * lines + k]) loaded in
+// bit-reversed order: X[m] = sum_n x[n] w^(n m), w = tw[1] = exp(+2 pi i / N).
+__device__ __forceinline__ void fft_lines(float2* X, const float2* tw, int N, int lines) {
+  for (int len = 2; len <= N; len <<= 1) {
+    const int half = len >> 1, step = N / len;
+    for (int b = threadIdx.x; b < lines * (N >> 1); b += blockDim.x) {
+      const int k = b % lines, j = b / lines;
+      const int i0 = (j / half) * len + (j % half), i1 = i0 + half;
+      const float2 u = X[i0 * lines + k], v = cmul(X[i1 * lines + k], tw[(j % half) * step]);
+      X[i0 * lines + k] = make_float2(u.x + v.x, u.y + v.y);
+      X[i1 * lines + k] = make_float2(u.x - v.x, u.y - v.y);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ int bit_reverse(int n, int bits) { return static_cast<int>(__brev(static_cast<unsigned>(n)) >> (32 - bits)); }
+
+// Lag d = j - (L - 1) of a lag-grid line goes to point n = d mod N with the
+// factor (-1)^d, so that the transform's output index is the pixel index:
+// w^(d (q - N/2)) = (-1)^d w^(d q).  Point N/2 (d = -L) stays zero.
+__device__ __forceinline__ float2 lag_point(const float2* line, int n, int N, int L) {
+  const int d = n < N / 2 ? n : n - N;
+  if (d < -(L - 1) || d > L - 1) return make_float2(0.f, 0.f);
+  const float2 v = line[d + L - 1];
+  return (d & 1) ? make_float2(-v.x, -v.y) : v;
+}
+
+constexpr int kFxRowLines = 8;   // lag rows per workgroup of the row pass
+
+// Row pass: one workgroup per (block of kFxRowLines lag rows, channel).
 __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
-  float2* row = fx_lds;            // [NL]
-  float2* tw = fx_lds + a.NL;      // [N]
-  const int N = a.N, NL = a.NL, ly = blockIdx.x, c = blockIdx.y, q = threadIdx.x;
-  const float2* Rrow = a.R + (static_cast<size_t>(c) * NL + ly) * NL;
-  for (int k = q; k < NL; k += N) row[k] = Rrow[k];
-  tw[q] = a.tw[q];
-  __syncthreads();
-  const int s = q - N / 2;
-  double x = 0.0, y = 0.0;
-  for (int lx = 0; lx < NL; ++lx) {
-    const float2 w = tw[((lx - (a.L - 1)) * s) & (N - 1)], r = row[lx];
-    x += static_cast<double>(r.x) * w.x - static_cast<double>(r.y) * w.y;
-    y += static_cast<double>(r.x) * w.y + static_cast<double>(r.y) * w.x;
+  const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y, ly0 = blockIdx.x * kFxRowLines;
+  const int bits = 31 - __clz(N);
+  float2* X = fx_lds;                       // [N][kFxRowLines]
+  float2* tw = fx_lds + N * kFxRowLines;    // [N]
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = a.tw[i];
+  const float2* R = a.R + static_cast<size_t>(c) * NL * NL;
+  for (int i = threadIdx.x; i < kFxRowLines * N; i += blockDim.x) {
+    const int k = i / N, n = i % N, ly = ly0 + k;
+    X[bit_reverse(n, bits) * kFxRowLines + k] =
+        ly < NL ? lag_point(R + static_cast<size_t>(ly) * NL, n, N, L) : make_float2(0.f, 0.f);
   }
-  a.Z[(static_cast<size_t>(c) * NL + ly) * N + q] = make_float2(static_cast<float>(x), static_cast<float>(y));
+  __syncthreads();
+  fft_lines(X, tw, N, kFxRowLines);
+  for (int i = threadIdx.x; i < kFxRowLines * N; i += blockDim.x) {
+    const int k = i / N, q = i % N, ly = ly0 + k;
+    if (ly < NL) a.Z[(static_cast<size_t>(c) * NL + ly) * N + q] = X[q * kFxRowLines + k];
+  }
 }
 
-// One workgroup of N threads per (block of kFxRows image rows, channel);
-// thread q reads each Z[ly][q] once for all the block's rows.
-constexpr int kFxRows = 8;
-
+// Column pass: one workgroup per (block of min(32, N) image columns, channel);
+// the lag column of Z is gathered through lag_point's mapping, transformed, and
+// its real part (scaled) written as 128-byte row segments of the image.
 __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
-  const int N = a.N, NL = a.NL, r0 = blockIdx.x * kFxRows, c = blockIdx.y, q = threadIdx.x;
+  extern __shared__ float2 fx_lds[];
+  const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y;
+  const int cw = N < 32 ? N : 32, q0 = blockIdx.x * cw, bits = 31 - __clz(N);
+  float2* X = fx_lds;                       // [N][cw]
+  float2* tw = fx_lds + N * cw;             // [N]
+  for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = a.tw[i];
   const float2* Z = a.Z + static_cast<size_t>(c) * NL * N;
-  double x[kFxRows] = {};
-  for (int ly = 0; ly < NL; ++ly) {
-    const float2 z = Z[static_cast<size_t>(ly) * N + q];
-    const int d = ly - (a.L - 1);
-#pragma unroll
-    for (int k = 0; k < kFxRows; ++k) {
-      const float2 w = a.tw[(d * (r0 + k - N / 2)) & (N - 1)];
-      x[k] += static_cast<double>(w.x) * z.x - static_cast<double>(w.y) * z.y;
+  for (int i = threadIdx.x; i < cw * N; i += blockDim.x) {
+    const int n = i / cw, k = i % cw;
+    const int d = n < N / 2 ? n : n - N;
+    float2 v = make_float2(0.f, 0.f);
+    if (d >= -(L - 1) && d <= L - 1) {
+      v = Z[static_cast<size_t>(d + L - 1) * N + q0 + k];
+      if (d & 1) v = make_float2(-v.x, -v.y);
     }
+    X[bit_reverse(n, bits) * cw + k] = v;
   }
-#pragma unroll
-  for (int k = 0; k < kFxRows; ++k) a.out[(static_cast<size_t>(c) * N + r0 + k) * N + q] = static_cast<float>(x[k] * a.scale);
+  __syncthreads();
+  fft_lines(X, tw, N, cw);
+  for (int i = threadIdx.x; i < cw * N; i += blockDim.x) {
+    const int r = i / cw, k = i % cw;
+    a.out[(static_cast<size_t>(c) * N + r) * N + q0 + k] = static_cast<float>(X[r * cw + k].x * a.scale);
+  }
 }
 
 hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
@@ -279,13 +340,21 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
   hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>((cells + 255) / 256), a.n_chan), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const unsigned lag_blocks = static_cast<unsigned>((a.NL * a.NL + 255) / 256);
-  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_blocks, a.n_chan), dim3(256), 0, st, a);
+  const unsigned lag_tiles = static_cast<unsigned>((a.NL + kLagTile - 1) / kLagTile);
+  const int ht = kLagTile + a.xs - 1;
+  const size_t lag_lds = sizeof(float2) * static_cast<size_t>(ht * ht + a.xs * a.xs);
+  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_tiles, lag_tiles, a.n_chan), dim3(kLagTile * kLagTile), lag_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds = sizeof(float2) * (a.NL + a.N);
-  hipLaunchKernelGGL(fx_row_kernel, dim3(a.NL, a.n_chan), dim3(a.N), lds, st, a);
+  const size_t row_lds = sizeof(float2) * static_cast<size_t>(a.N) * (kFxRowLines + 1);
+  const unsigned row_blocks = static_cast<unsigned>((a.NL + kFxRowLines - 1) / kFxRowLines);
+  hipLaunchKernelGGL(fx_row_kernel, dim3(row_blocks, a.n_chan), dim3(256), row_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / kFxRows, a.n_chan), dim3(a.N), 0, st, a);
+  const int cw = a.N < 32 ? a.N : 32;
+  const size_t col_lds = sizeof(float2) * static_cast<size_t>(a.N) * (cw + 1);
+  if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fx_col_kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(col_lds))) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / cw, a.n_chan), dim3(256), col_lds, st, a);
   return hipGetLastError();
 }
 
