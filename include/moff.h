@@ -355,14 +355,15 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  * moff_image's default image to rounding.  MOFF_AUTOCORR_UV and the
  * MOFF_MFMA_* flags do not apply here (float32 products, float64 sums).
  * MOFF_NORM_PAIRS scales as for moff_image.
- * Cost: O(n_chan (n_time n_ant^2 + n_ant^2 + N^3)) work and a workspace of
- * 8 n_chan (n_ant^2 + (n_types^2 + 1) (2L - 1)^2 + (2L - 1) N) bytes, owned by
- * the plan (shared with the other entry points of the plan).  The pair tables
- * (4 n_ant^2 bytes) are built and uploaded on the first call.
+ * Cost: O(n_chan (n_time n_ant^2 + n_ant^2 + N^2 log N)) work.  Channels run in
+ * chunks whose workspace, 8 (n_ant^2 + (n_types^2 + 1) (2L - 1)^2 + (2L - 1) N)
+ * bytes per channel, stays within about 2 GiB (at least one channel); it is
+ * owned by the plan and shared with the plan's other entry points.  The pair
+ * tables (4 n_ant^2 bytes) are built and uploaded on the first call.
  * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
- * MOFF_ERR_UNSUPPORTED for a plan without a device, more than 65535 channels,
- * or 4+4-bit samples with n_time > 2^24 (their cross-products are exact int32
- * sums on the matrix cores);
+ * MOFF_ERR_UNSUPPORTED for a plan without a device, or 4+4-bit samples with
+ * n_time > 2^24 (their cross-products are exact int32 sums on the matrix
+ * cores);
  * MOFF_ERR_NOMEM when the workspace cannot be allocated; MOFF_ERR_HIP for a
  * failed launch.
  */

@@ -942,7 +942,6 @@ moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const floa
   if (s != MOFF_OK) return s;
   if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
   const HostPlan& hp = p->hp;
-  if (hp.n_chan > 65535) return MOFF_ERR_UNSUPPORTED;
   // 4+4-bit samples are correlated in int32: |sum_t x_a x_b| <= 64 n_time
   if ((hp.flags & MOFF_IN_CI4) && n_time > (int64_t(1) << 24)) return MOFF_ERR_UNSUPPORTED;
   DeviceGuard guard(p->device);
@@ -967,12 +966,15 @@ moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const floa
     p->fx_xs = t.xs;
   }
   const int NL = p->fx_NL, NTP = hp.n_ktypes * hp.n_ktypes;
-  const size_t C = hp.n_chan;
-  const size_t v_bytes = sizeof(float2) * C * hp.n_ant * hp.n_ant;
-  const size_t h_bytes = sizeof(float2) * C * NTP * NL * NL;
-  const size_t r_bytes = sizeof(float2) * C * NL * NL;
-  const size_t z_bytes = sizeof(float2) * C * NL * hp.N;
-  s = ensure_workspace(p, v_bytes + h_bytes + r_bytes + z_bytes);
+  // workspace per channel; channels run in chunks that keep it within ~2 GiB
+  const size_t v_per = sizeof(float2) * hp.n_ant * hp.n_ant;
+  const size_t h_per = sizeof(float2) * NTP * NL * NL;
+  const size_t r_per = sizeof(float2) * NL * NL;
+  const size_t z_per = sizeof(float2) * NL * hp.N;
+  const size_t per_chan = v_per + h_per + r_per + z_per;
+  const int chunk = static_cast<int>(std::max<size_t>(
+      1, std::min<size_t>({static_cast<size_t>(hp.n_chan), (size_t(2) << 30) / per_chan, size_t(65535)})));
+  s = ensure_workspace(p, per_chan * chunk);
   if (s != MOFF_OK) return s;
   char* ws = static_cast<char*>(p->d_ws);
   moff::FxArgs a{};
@@ -992,12 +994,18 @@ moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const floa
   a.xcorr = p->d_fx_x;
   a.tw = p->d_tw;
   a.V = reinterpret_cast<float2*>(ws);
-  a.H = reinterpret_cast<float2*>(ws + v_bytes);
-  a.R = reinterpret_cast<float2*>(ws + v_bytes + h_bytes);
-  a.Z = reinterpret_cast<float2*>(ws + v_bytes + h_bytes + r_bytes);
+  a.H = reinterpret_cast<float2*>(ws + v_per * chunk);
+  a.R = reinterpret_cast<float2*>(ws + (v_per + h_per) * chunk);
+  a.Z = reinterpret_cast<float2*>(ws + (v_per + h_per + r_per) * chunk);
   a.out = image;
   a.scale = image_scale(hp, n_time);
-  return hip_status(moff::launch_fx(a, hp.flags & MOFF_IN_CI4, static_cast<hipStream_t>(stream)));
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  for (int c0 = 0; c0 < hp.n_chan; c0 += chunk) {
+    a.c0 = c0;
+    a.n_launch = std::min(chunk, hp.n_chan - c0);
+    if (moff::launch_fx(a, ci4, static_cast<hipStream_t>(stream)) != hipSuccess) return MOFF_ERR_HIP;
+  }
+  return MOFF_OK;
 }
 
 moff_status moff_gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* gains, const float* dL_dimage,

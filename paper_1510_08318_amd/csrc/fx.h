@@ -14,7 +14,8 @@ namespace moff {
 struct FxArgs {
   const void* E;
   const float2* gains;         // [n_chan][n_ant] or null (unit gains)
-  int n_ant, n_chan, n_types;
+  int n_ant, n_chan, n_types;  // n_chan: channels of E, gains and out
+  int c0, n_launch;            // this launch's channels c0 .. c0 + n_launch - 1 (workspace holds n_launch)
   int64_t n_time;
   int N, L, NL, xs;            // xs: side of each pair-response table
   const int* pair_ptr;         // [NTP * NL * NL + 1] CSR over (type pair, footprint offset)
@@ -22,10 +23,10 @@ struct FxArgs {
   const int* ktype_k;          // [n_types]
   const float2* xcorr;         // [NTP][xs][xs] pair responses of the tables
   const float2* tw;            // [N] exp(+2 pi i k / N)
-  float2* V;                   // [n_chan][n_ant][n_ant] workspace
-  float2* H;                   // [n_chan][NTP][NL][NL] workspace
-  float2* R;                   // [n_chan][NL][NL] workspace
-  float2* Z;                   // [n_chan][NL][N] workspace
+  float2* V;                   // [n_launch][n_ant][n_ant] workspace
+  float2* H;                   // [n_launch][NTP][NL][NL] workspace
+  float2* R;                   // [n_launch][NL][NL] workspace
+  float2* Z;                   // [n_launch][NL][N] workspace
   float* out;                  // [n_chan][N][N]
   double scale;
 };

@@ -49,7 +49,7 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   __shared__ float2 ea[kFxChunk][kFxTile + 1], eb[kFxChunk][kFxTile + 1];
   const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, c = blockIdx.z;
+  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, cl = blockIdx.z, c = a.c0 + cl;
   const int na = a.n_ant;
   const float2* E = reinterpret_cast<const float2*>(a.E);
   double acc[2][2][2] = {};
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
     for (int j = 0; j < 2; ++j) {
       const int ia = a0 + ty + 16 * i, ib = b0 + tx + 16 * j;
       if (ia < na && ib < na)
-        a.V[(static_cast<size_t>(c) * na + ia) * na + ib] =
+        a.V[(static_cast<size_t>(cl) * na + ia) * na + ib] =
             make_float2(static_cast<float>(acc[i][j][0]), static_cast<float>(acc[i][j][1]));
     }
 }
@@ -124,7 +124,7 @@ constexpr int kI8Pitch = kI8Step + 16;      // LDS row bytes: 16-byte operand re
 __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t pl[4][kFxTile][kI8Pitch];   // re A, im A, re B, im B
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, c = blockIdx.z;
+  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, cl = blockIdx.z, c = a.c0 + cl;
   const int na = a.n_ant;
   const int8_t* E = reinterpret_cast<const int8_t*>(a.E);
   const size_t tstride = static_cast<size_t>(a.n_chan) * na;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
       zr = gr * vr - gi * vi;
       zi = gr * vi + gi * vr;
     }
-    a.V[(static_cast<size_t>(c) * na + ia) * na + ib] = make_float2(static_cast<float>(zr), static_cast<float>(zi));
+    a.V[(static_cast<size_t>(cl) * na + ia) * na + ib] = make_float2(static_cast<float>(zr), static_cast<float>(zi));
   }
 }
 
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
 // its real part (scaled) written as 128-byte row segments of the image.
 __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
-  const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y;
+  const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y;   // c: channel within the launch
   const int cw = N < 32 ? N : 32, q0 = blockIdx.x * cw, bits = 31 - __clz(N);
   float2* X = fx_lds;                       // [N][cw]
   float2* tw = fx_lds + N * cw;             // [N]
@@ -321,16 +321,16 @@ __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
   fft_lines(X, tw, N, cw);
   for (int i = threadIdx.x; i < cw * N; i += blockDim.x) {
     const int r = i / cw, k = i % cw;
-    a.out[(static_cast<size_t>(c) * N + r) * N + q0 + k] = static_cast<float>(X[r * cw + k].x * a.scale);
+    a.out[(static_cast<size_t>(a.c0 + c) * N + r) * N + q0 + k] = static_cast<float>(X[r * cw + k].x * a.scale);
   }
 }
 
 hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
-  if (a.n_ant < 1 || a.n_chan < 1 || a.n_chan > 65535 || a.N < 8 || a.N > 256 || a.NL != 2 * a.L - 1 ||
-      a.n_types < 1 || a.n_types > kMaxTypesDev)
+  if (a.n_ant < 1 || a.n_launch < 1 || a.n_launch > 65535 || a.c0 < 0 || a.c0 + a.n_launch > a.n_chan || a.N < 8 ||
+      a.N > 256 || a.NL != 2 * a.L - 1 || a.n_types < 1 || a.n_types > kMaxTypesDev)
     return hipErrorInvalidValue;
   const unsigned tiles = static_cast<unsigned>((a.n_ant + kFxTile - 1) / kFxTile);
-  const dim3 g1(tiles, tiles, static_cast<unsigned>(a.n_chan));
+  const dim3 g1(tiles, tiles, static_cast<unsigned>(a.n_launch));
   if (ci4)
     hipLaunchKernelGGL(fx_correlate_i8_kernel, g1, dim3(256), 0, st, a);
   else
@@ -338,23 +338,23 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
-  hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>((cells + 255) / 256), a.n_chan), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>((cells + 255) / 256), a.n_launch), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned lag_tiles = static_cast<unsigned>((a.NL + kLagTile - 1) / kLagTile);
   const int ht = kLagTile + a.xs - 1;
   const size_t lag_lds = sizeof(float2) * static_cast<size_t>(ht * ht + a.xs * a.xs);
-  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_tiles, lag_tiles, a.n_chan), dim3(kLagTile * kLagTile), lag_lds, st, a);
+  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_tiles, lag_tiles, a.n_launch), dim3(kLagTile * kLagTile), lag_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t row_lds = sizeof(float2) * static_cast<size_t>(a.N) * (kFxRowLines + 1);
   const unsigned row_blocks = static_cast<unsigned>((a.NL + kFxRowLines - 1) / kFxRowLines);
-  hipLaunchKernelGGL(fx_row_kernel, dim3(row_blocks, a.n_chan), dim3(256), row_lds, st, a);
+  hipLaunchKernelGGL(fx_row_kernel, dim3(row_blocks, a.n_launch), dim3(256), row_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const int cw = a.N < 32 ? a.N : 32;
   const size_t col_lds = sizeof(float2) * static_cast<size_t>(a.N) * (cw + 1);
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fx_col_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(col_lds))) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / cw, a.n_chan), dim3(256), col_lds, st, a);
+  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / cw, a.n_launch), dim3(256), col_lds, st, a);
   return hipGetLastError();
 }
 

@@ -59,13 +59,14 @@ def test_fx_flags(torch, moff, flag):
     assert_image_close(got, ref, pbar, label=f"FX {flag}")
 
 
-@pytest.mark.parametrize("shape", [("config2", 200, 16), ("config3", 8, 4), ("config5", 1, 2)])
+@pytest.mark.parametrize("shape", [("config2", 200, 16), ("config3", 8, 4), ("config5", 1, 2), ("config5", 1, 256)])
 def test_fx_route_equals_device_moff_image(torch, moff, shape):
     """Cross-method check on the device at sizes the oracle would take long for:
     the FX image equals moff_image (LWA-shaped 256 antennas; HERA-shaped 350
     antennas with 7x7 tables on the 256 grid; the 1024-antenna two-type
-    calibration layout with one time sample).  Pbar comes from the device MOFF
-    image without self-power removal."""
+    calibration layout with one time sample; over all 256 channels its
+    workspace of about 10.6 MB per channel runs in two chunks).  Pbar comes from
+    the device MOFF image without self-power removal."""
     cfg, T, C = shape
     w = synth.make_config(int(cfg[-1]), n_time=T, n_chan=C)
     with moff.Plan.from_geometry(w.geom, device=0) as p:
