@@ -35,7 +35,8 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 
 # HBM traffic per launch of the timed kernel, measured with rocprofv3 --pmc
 # FETCH_SIZE and, in a second run, WRITE_SIZE on this script (KiB per dispatch;
-# profiles/fused_kernel_lwa_n128.md, profiles/mfma_kernel_lwa_f16_n128.md).
+# profiles/fused_kernel_lwa_n128.md, profiles/mfma_kernel_lwa_f16_n128.md; the
+# HERA-shaped and calibration workloads in the same two runs of --config 3 / 5).
 # Scaled by what the same counters read for one 256 MiB device copy in the same
 # runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
@@ -59,6 +60,20 @@ TRAFFIC_KIB = {
     (2, "f32", 1, 2048): (16616, 131136),
     (2, "f32", 1, 4096): (16624, 262272),
     (2, "f32", 1, 8192): (16620, 524544),
+    (3, "f32", 0, 4096): (261643, 1048576),
+    (3, "f32", 0, 8192): (244768, 524320),
+    (3, "f32", 0, 16384): (244744, 1048640),
+    (3, "f32", 1, 2048): (144348, 544754),
+    (3, "f32", 1, 4096): (131917, 559657),
+    (3, "f32", 1, 8192): (138645, 1124560),
+    (3, "f32", 1, 16384): (149844, 2254325),
+    (5, "f32", 0, 1024): (548996, 262144),
+    (5, "f32", 0, 2048): (534180, 131088),
+    (5, "f32", 0, 4096): (542951, 262176),
+    (5, "f32", 1, 512): (278683, 138240),
+    (5, "f32", 1, 1024): (275402, 145385),
+    (5, "f32", 1, 2048): (289482, 290823),
+    (5, "f32", 1, 4096): (320930, 581664),
     (4, "f16", 0, 128): (129020, 8192),
     (4, "f16", 0, 256): (128460, 16392),
     (4, "f16", 0, 512): (128672, 32785),
