@@ -456,6 +456,7 @@ def main():
         plan.set_timing(True)
         plan.gain_vjp(E, g_in, R, out=grads[False])
         extra["adjoint_kernel_ms"] = round(plan.last_kernel_ms(), 4)
+        extra["adjoint_waves_per_simd"] = plan.adjoint_waves()[0]
         plan.set_timing(False)
         extra["adjoint_fused_vs_staged_max_rel_diff"] = float(
             ((grads[False] - grads[True]).abs().max() / grads[True].abs().max()).item())

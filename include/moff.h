@@ -27,9 +27,9 @@
  *   - Calls enqueue work on `hip_stream` (a hipStream_t, NULL = default stream)
  *     and return without synchronising; argument validation is synchronous.
  *   - A plan's tables are fixed at creation; its only mutable state is the
- *     launch configuration (moff_plan_autotune / moff_plan_set_config), the
- *     timing switch and a device workspace, so concurrent calls must use
- *     different plans.
+ *     launch configuration (moff_plan_autotune / moff_plan_set_config /
+ *     moff_plan_set_adjoint_waves), the timing switch and a device workspace,
+ *     so concurrent calls must use different plans.
  *   - The workspace grows on demand: a call that needs more than the plan holds
  *     synchronises the device and allocates.  Under stream (graph) capture, make
  *     one eager call of the same shape first; captured calls then allocate
@@ -240,12 +240,29 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * slice counts that fill whole rounds of resident workgroups) with HIP events
  * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
  * the stream; later results do not depend on the choice beyond float32
- * rounding order.  moff_plan_set_config forces a choice (slices = 0:
+ * rounding order.  Where the fused gain adjoint is built with more than one
+ * register budget (grid_n 256, see moff_plan_set_adjoint_waves), it also times
+ * moff_gain_vjp with each, on the same samples and gains with the tuned image
+ * as the pixel sensitivities, and keeps the fastest.  moff_plan_set_config forces a choice (slices = 0:
  * heuristic); moff_plan_get_config reports the configuration a call with
  * n_time samples would use.  Any output of get_config may be NULL.
  */
 moff_status moff_plan_autotune(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
                                void* hip_stream);
+
+/*
+ * Register budget of the fused gain adjoint (moff_gain_vjp): the number of
+ * waves per SIMD its registers are sized for.  At grid_n 256 the adjoint needs
+ * more registers than two waves per SIMD can hold; waves_per_simd = 1 (the
+ * default) keeps the excess in the accumulation registers, 2 spills it to
+ * scratch memory and runs two waves, which is faster for some workloads (the
+ * 4+4-bit HERA-shaped one) and slower for others.  Results are the same either
+ * way.  max_waves_per_simd = 2 at grid_n 256, 1 otherwise; set_adjoint_waves
+ * returns MOFF_ERR_UNSUPPORTED above it and MOFF_ERR_INVALID_ARG below 1.
+ * Outputs of get_adjoint_waves may be NULL.
+ */
+moff_status moff_plan_set_adjoint_waves(moff_plan plan, int32_t waves_per_simd);
+moff_status moff_plan_get_adjoint_waves(moff_plan plan, int32_t* waves_per_simd, int32_t* max_waves_per_simd);
 moff_status moff_plan_set_config(moff_plan plan, int32_t variant, int32_t slices);
 moff_status moff_plan_get_config(moff_plan plan, int64_t n_time, int32_t* variant, int32_t* slices, int32_t* grid,
                                  int32_t* threads, int32_t* n_variants, int32_t* tuned);

@@ -275,6 +275,16 @@ class Plan:
         _lib.moff_image_staged(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
         return out
 
+    def set_adjoint_waves(self, waves_per_simd):
+        """Register budget of the fused gain adjoint: waves per SIMD (1, or 2 at grid 256)."""
+        _lib.moff_plan_set_adjoint_waves(self.handle, int(waves_per_simd))
+
+    def adjoint_waves(self):
+        """(waves per SIMD in use, largest available) for the fused gain adjoint."""
+        w, m = ctypes.c_int32(), ctypes.c_int32()
+        _lib.moff_plan_get_adjoint_waves(self.handle, ctypes.byref(w), ctypes.byref(m))
+        return w.value, m.value
+
     def image_fx(self, E, gains=None, out=None, stream=None):
         """Visibility-route (FX) image of the same integration: pair
         cross-products gridded with the tables' pair responses and transformed

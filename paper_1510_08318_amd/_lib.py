@@ -87,6 +87,8 @@ SIGNATURES = {
                                          ctypes.c_void_p, ctypes.c_void_p]),
     "moff_image_fx": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "moff_plan_set_adjoint_waves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "moff_plan_get_adjoint_waves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
 }
 
 _lib = None
@@ -233,3 +235,11 @@ def moff_gain_vjp_staged(plan, E, n_time, gains, dL_dimage, dL_dgains, stream):
 
 def moff_gain_vjp(plan, E, n_time, gains, dL_dimage, dL_dgains, stream):
     _call("moff_gain_vjp", plan, E, n_time, gains, dL_dimage, dL_dgains, stream)
+
+
+def moff_plan_set_adjoint_waves(plan, waves):
+    _call("moff_plan_set_adjoint_waves", plan, waves)
+
+
+def moff_plan_get_adjoint_waves(plan, waves, max_waves):
+    _call("moff_plan_get_adjoint_waves", plan, waves, max_waves)

@@ -55,6 +55,7 @@ struct moff_plan_s {
   int variant = 0;          // index into hp.variants
   int slices = 0;           // time slices; 0 = heuristic
   bool tuned = false;
+  int adj_waves = 1;        // fused adjoint: waves per SIMD its registers are sized for
 };
 
 namespace {
@@ -396,7 +397,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     // fused: every frame's grid, field and adjoint stay in LDS
     const int per_slice = V.shape.SX * hp.n_chan;
     const int resident =
-        std::max(1, moff::adjoint_fused_blocks_per_cu(hp.N, 0, ci4, lds)) * std::max(1, p->cu_count);
+        std::max(1, moff::adjoint_fused_blocks_per_cu(hp.N, 0, ci4, p->adj_waves, lds)) * std::max(1, p->cu_count);
     const int slices = static_cast<int>(
         std::max<int64_t>(1, std::min<int64_t>({(2 * resident + per_slice - 1) / per_slice, n_time, 64})));
     const int parts = slices * V.shape.SX;
@@ -423,7 +424,8 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.slices = slices;
     a.Dp = Dp;
     if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-    if (moff::launch_adjoint_fused(a, hp.N, 0, ci4, per_slice * slices, st) != hipSuccess) return MOFF_ERR_HIP;
+    if (moff::launch_adjoint_fused(a, hp.N, 0, ci4, p->adj_waves, per_slice * slices, st) != hipSuccess)
+      return MOFF_ERR_HIP;
     if (p->timing) {
       if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
       p->timed = true;
@@ -765,6 +767,39 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
       }
     }
   }
+  // The fused gain adjoint's register budget (moff_plan_set_adjoint_waves):
+  // where more than one is built, time each on the same input with the tuned
+  // forward image as the pixel sensitivities, and keep the fastest.
+  int bw = p->adj_waves;
+  const int wmax = moff::adjoint_waves_max(hp.N);
+  if (result == MOFF_OK && wmax > 1 && p->d_adj_slots) {
+    p->variant = bv;
+    p->slices = bs;
+    float* grad = nullptr;
+    if (hipMalloc(reinterpret_cast<void**>(&grad), sizeof(float) * 2 * hp.n_chan * hp.n_ant) != hipSuccess)
+      result = MOFF_ERR_NOMEM;
+    float best_adj = 1e30f;
+    for (int wv = 1; wv <= wmax && result == MOFF_OK; ++wv) {
+      p->adj_waves = wv;
+      result = gain_vjp(p, E, n_time, gains, img, grad, st, false);   // warm-up (and workspace)
+      float ms = 1e30f;
+      for (int rep = 0; rep < 2 && result == MOFF_OK; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
+        if (result == MOFF_OK) result = gain_vjp(p, E, n_time, gains, img, grad, st, false);
+        if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
+        if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
+        float one = 0.f;
+        if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+        if (result == MOFF_OK) ms = std::min(ms, one);
+      }
+      if (result == MOFF_OK && ms < best_adj) {
+        best_adj = ms;
+        bw = wv;
+      }
+    }
+    (void)hipStreamSynchronize(st);
+    if (grad) (void)hipFree(grad);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipStreamSynchronize(st);
@@ -773,11 +808,28 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   if (result != MOFF_OK) {
     p->variant = saved_v;
     p->slices = saved_s;
+    p->adj_waves = 1;
     return result;
   }
   p->variant = bv;
   p->slices = bs;
+  p->adj_waves = bw;
   p->tuned = true;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_set_adjoint_waves(moff_plan p, int32_t waves_per_simd) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (waves_per_simd < 1) return MOFF_ERR_INVALID_ARG;
+  if (waves_per_simd > moff::adjoint_waves_max(p->hp.N)) return MOFF_ERR_UNSUPPORTED;
+  p->adj_waves = waves_per_simd;
+  return MOFF_OK;
+}
+
+moff_status moff_plan_get_adjoint_waves(moff_plan p, int32_t* waves_per_simd, int32_t* max_waves_per_simd) {
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (waves_per_simd) *waves_per_simd = p->adj_waves;
+  if (max_waves_per_simd) *max_waves_per_simd = moff::adjoint_waves_max(p->hp.N);
   return MOFF_OK;
 }
 

@@ -176,8 +176,10 @@ struct AdjFusedArgs {
   int slices;
   double2* Dp;                 // [slices * SX][C][n_ant]
 };
-hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st);
-int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, size_t lds);
+// wps: waves per SIMD the adjoint's registers are sized for, 1 .. adjoint_waves_max(N)
+int adjoint_waves_max(int N);
+hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int wps, int grid, hipStream_t st);
+int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, int wps, size_t lds);
 // Q[c][a] = sum_t |E[t][c][a]|^2 (float64); D[c][a] = sum_k Dp[k][c][a] over `parts` partials.
 hipError_t launch_antenna_power(const void* E, bool ci4, int64_t n_time, int n_chan, int n_ant, double* Q,
                                 hipStream_t st);

@@ -190,8 +190,14 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
 // fused gain adjoint
 // ---------------------------------------------------------------------------
 
-template <int N, int V, bool CI4>
-__global__ __launch_bounds__((FT<N, V>::NT)) void adjoint_fused_kernel(AdjFusedArgs a) {
+// WPS: waves per SIMD the registers are sized for.  At N = 256 the kernel
+// needs more than a SIMD's registers for two waves; WPS = 1 keeps the excess in
+// the accumulation registers (one wave per SIMD), WPS = 2 spills it to scratch
+// memory and runs two.  Which is faster depends on the workload, so both are
+// built there and the plan's autotuner picks one.
+template <int N, int V, bool CI4, int WPS>
+__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(WPS)))
+void adjoint_fused_kernel(AdjFusedArgs a) {
   using C = FT<N, V>;
   constexpr int NT = C::NT;
   extern __shared__ float2 lds[];
@@ -651,25 +657,27 @@ hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hi
 
 namespace {
 
-template <int N, int V, bool CI4>
+template <int N, int V, bool CI4, int WPS>
 const void* adjoint_fused_symbol() {
-  return reinterpret_cast<const void*>(adjoint_fused_kernel<N, V, CI4>);
+  return reinterpret_cast<const void*>(adjoint_fused_kernel<N, V, CI4, WPS>);
 }
 
 template <int N, int V>
-const void* adjoint_fused_symbol_v(bool ci4) {
-  if constexpr (frame_shape(N, V).N == N)
-    return ci4 ? adjoint_fused_symbol<N, V, true>() : adjoint_fused_symbol<N, V, false>();
-  else
-    return nullptr;
+const void* adjoint_fused_symbol_v(bool ci4, int wps) {
+  if constexpr (frame_shape(N, V).N == N) {
+    if (wps == 1) return ci4 ? adjoint_fused_symbol<N, V, true, 1>() : adjoint_fused_symbol<N, V, false, 1>();
+    if constexpr (N == 256)
+      if (wps == 2) return ci4 ? adjoint_fused_symbol<N, V, true, 2>() : adjoint_fused_symbol<N, V, false, 2>();
+  }
+  return nullptr;
 }
 
-const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4) {
+const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4, int wps) {
   auto pick = [&](auto nc) -> const void* {
     constexpr int NN = decltype(nc)::value;
     // variant 0 only: at N = 256 variant 1's 512-thread workgroups would spill the
     // column round trip's state (forward inputs, adjoint sums, pixel sensitivities)
-    return V == 0 ? adjoint_fused_symbol_v<NN, 0>(ci4) : nullptr;
+    return V == 0 ? adjoint_fused_symbol_v<NN, 0>(ci4, wps) : nullptr;
   };
   switch (N) {
     case 8: return pick(std::integral_constant<int, 8>{});
@@ -684,8 +692,10 @@ const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4) {
 
 }  // namespace
 
-hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st) {
-  const void* k = adjoint_fused_kernel_symbol(N, V, ci4);
+int adjoint_waves_max(int N) { return N == 256 ? 2 : 1; }
+
+hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int wps, int grid, hipStream_t st) {
+  const void* k = adjoint_fused_kernel_symbol(N, V, ci4, wps);
   if (!k) return hipErrorInvalidValue;
   const FrameShape S = frame_shape(N, V);
   const size_t lds = fused_lds_bytes(N, V, a.n_weights, a.n_ant);
@@ -695,8 +705,8 @@ hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, i
   return hipLaunchKernel(k, dim3(grid), dim3(S.NT), args, lds, st);
 }
 
-int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
-  const void* k = adjoint_fused_kernel_symbol(N, V, ci4);
+int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, int wps, size_t lds) {
+  const void* k = adjoint_fused_kernel_symbol(N, V, ci4, wps);
   if (!k) return 0;
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k, frame_shape(N, V).NT, lds) != hipSuccess) return 1;
