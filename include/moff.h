@@ -241,7 +241,7 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
  * the stream; later results do not depend on the choice beyond float32
  * rounding order.  Where the fused gain adjoint is built with more than one
- * register budget (grid_n 256, see moff_plan_set_adjoint_waves), it also times
+ * register budget (grid_n 128 and 256, see moff_plan_set_adjoint_waves), it also times
  * moff_gain_vjp with each, on the same samples and gains with the tuned image
  * as the pixel sensitivities, and keeps the fastest.  moff_plan_set_config forces a choice (slices = 0:
  * heuristic); moff_plan_get_config reports the configuration a call with
@@ -251,15 +251,16 @@ moff_status moff_plan_autotune(moff_plan plan, const void* E_dev, int64_t n_time
                                void* hip_stream);
 
 /*
- * Register budget of the fused gain adjoint (moff_gain_vjp): the number of
- * waves per SIMD its registers are sized for.  At grid_n 256 the adjoint needs
- * more registers than two waves per SIMD can hold; waves_per_simd = 1 (the
- * default) keeps the excess in the accumulation registers, 2 spills it to
- * scratch memory and runs two waves, which is faster for some workloads (the
- * 4+4-bit HERA-shaped one) and slower for others.  Results are the same either
- * way.  max_waves_per_simd = 2 at grid_n 256, 1 otherwise; set_adjoint_waves
- * returns MOFF_ERR_UNSUPPORTED above it and MOFF_ERR_INVALID_ARG below 1.
- * Outputs of get_adjoint_waves may be NULL.
+ * Register budget of the fused gain adjoint (moff_gain_vjp): the least number
+ * of waves per SIMD its registers are sized for (1, the default: as many as the
+ * kernel wants).  At grid_n 256 the adjoint wants more registers than two waves
+ * per SIMD can hold: 1 keeps the excess in the accumulation registers, 2 spills
+ * it to scratch memory and runs two waves.  At grid_n 128 it fits two waves,
+ * and 3 spills a little to run three.  Which is fastest depends on the
+ * workload; results are the same either way.  max_waves_per_simd = 3 at
+ * grid_n 128, 2 at 256, 1 otherwise; set_adjoint_waves returns
+ * MOFF_ERR_UNSUPPORTED above it and MOFF_ERR_INVALID_ARG below 1.  Outputs of
+ * get_adjoint_waves may be NULL.
  */
 moff_status moff_plan_set_adjoint_waves(moff_plan plan, int32_t waves_per_simd);
 moff_status moff_plan_get_adjoint_waves(moff_plan plan, int32_t* waves_per_simd, int32_t* max_waves_per_simd);

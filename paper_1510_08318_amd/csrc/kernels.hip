@@ -190,11 +190,13 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
 // fused gain adjoint
 // ---------------------------------------------------------------------------
 
-// WPS: waves per SIMD the registers are sized for.  At N = 256 the kernel
-// needs more than a SIMD's registers for two waves; WPS = 1 keeps the excess in
-// the accumulation registers (one wave per SIMD), WPS = 2 spills it to scratch
-// memory and runs two.  Which is faster depends on the workload, so both are
-// built there and the plan's autotuner picks one.
+// WPS: the least number of waves per SIMD the registers are sized for (1: as
+// many registers as the kernel wants).  At N = 256 the kernel wants more than
+// two waves' worth: WPS = 1 keeps the excess in the accumulation registers (one
+// wave per SIMD), WPS = 2 spills it to scratch memory and runs two.  At
+// N = 128 it wants two waves' worth, and WPS = 3 spills a little to run three.
+// Which is faster depends on the workload, so these are built and the plan's
+// autotuner picks one.
 template <int N, int V, bool CI4, int WPS>
 __global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(WPS)))
 void adjoint_fused_kernel(AdjFusedArgs a) {
@@ -662,12 +664,19 @@ const void* adjoint_fused_symbol() {
   return reinterpret_cast<const void*>(adjoint_fused_kernel<N, V, CI4, WPS>);
 }
 
+template <int N, int V, int WPS>
+const void* adjoint_fused_symbol_w(bool ci4) {
+  return ci4 ? adjoint_fused_symbol<N, V, true, WPS>() : adjoint_fused_symbol<N, V, false, WPS>();
+}
+
 template <int N, int V>
 const void* adjoint_fused_symbol_v(bool ci4, int wps) {
   if constexpr (frame_shape(N, V).N == N) {
-    if (wps == 1) return ci4 ? adjoint_fused_symbol<N, V, true, 1>() : adjoint_fused_symbol<N, V, false, 1>();
-    if constexpr (N == 256)
-      if (wps == 2) return ci4 ? adjoint_fused_symbol<N, V, true, 2>() : adjoint_fused_symbol<N, V, false, 2>();
+    if (wps == 1) return adjoint_fused_symbol_w<N, V, 1>(ci4);
+    if constexpr (N == 128 || N == 256)
+      if (wps == 2) return adjoint_fused_symbol_w<N, V, 2>(ci4);
+    if constexpr (N == 128)
+      if (wps == 3) return adjoint_fused_symbol_w<N, V, 3>(ci4);
   }
   return nullptr;
 }
@@ -692,7 +701,7 @@ const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4, int wps) {
 
 }  // namespace
 
-int adjoint_waves_max(int N) { return N == 256 ? 2 : 1; }
+int adjoint_waves_max(int N) { return N == 128 ? 3 : N == 256 ? 2 : 1; }
 
 hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int wps, int grid, hipStream_t st) {
   const void* k = adjoint_fused_kernel_symbol(N, V, ci4, wps);
