@@ -38,58 +38,73 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # profiles/fused_kernel_lwa_n128.md, profiles/mfma_kernel_lwa_f16_n128.md; the
 # HERA-shaped and calibration workloads in the same two runs of --config 3 / 5).
 # Scaled by what the same counters read for one 256 MiB device copy in the same
-# runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  Keyed by (workload,
+# runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  All entries are from
+# one set of runs on the current sources.  Keyed by (workload,
 # precision, shape variant, workgroups); valid only for the kernel sources they
 # were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "562bcc618c8e24ac"
+TRAFFIC_SOURCES_SHA = "2e00f0131f0f9e31"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (32979, 16384),
-    (2, "f32", 0, 512): (32435, 16392),
-    (2, "f32", 0, 1024): (32435, 32784),
-    (2, "f32", 0, 2048): (32447, 65568),
-    (2, "f32", 0, 3072): (32441, 98352),
-    (2, "f32", 0, 4096): (32439, 131136),
-    (2, "f32", 0, 8192): (32437, 262272),
-    (2, "f32", 0, 16384): (32437, 524544),
-    (2, "f32", 1, 128): (17197, 8192),
-    (2, "f32", 1, 256): (16616, 16393),
-    (2, "f32", 1, 512): (16616, 32785),
-    (2, "f32", 1, 1024): (16624, 65569),
-    (2, "f32", 1, 1536): (16624, 98352),
-    (2, "f32", 1, 2048): (16616, 131136),
-    (2, "f32", 1, 4096): (16624, 262272),
-    (2, "f32", 1, 8192): (16620, 524544),
-    (3, "f32", 0, 4096): (261643, 1048576),
-    (3, "f32", 0, 8192): (244768, 524320),
-    (3, "f32", 0, 16384): (244744, 1048640),
-    (3, "f32", 1, 2048): (144348, 544754),
-    (3, "f32", 1, 4096): (131917, 559657),
-    (3, "f32", 1, 8192): (138645, 1124560),
-    (3, "f32", 1, 16384): (149844, 2254325),
-    (5, "f32", 0, 1024): (548996, 262144),
-    (5, "f32", 0, 2048): (534180, 131088),
-    (5, "f32", 0, 4096): (542951, 262176),
-    (5, "f32", 1, 512): (278683, 138240),
-    (5, "f32", 1, 1024): (275402, 145385),
-    (5, "f32", 1, 2048): (289482, 290823),
-    (5, "f32", 1, 4096): (320930, 581664),
-    (4, "f16", 0, 128): (129020, 8192),
+    (2, "f32", 0, 256): (32977, 16384),
+    (2, "f32", 0, 512): (32433, 16392),
+    (2, "f32", 0, 1024): (32433, 32784),
+    (2, "f32", 0, 2048): (32444, 65568),
+    (2, "f32", 0, 3072): (32435, 98352),
+    (2, "f32", 0, 4096): (32435, 131136),
+    (2, "f32", 0, 8192): (32434, 262272),
+    (2, "f32", 0, 16384): (32434, 524544),
+    (2, "f32", 1, 128): (17196, 8192),
+    (2, "f32", 1, 256): (16617, 16392),
+    (2, "f32", 1, 512): (16617, 32784),
+    (2, "f32", 1, 1024): (16630, 65569),
+    (2, "f32", 1, 1536): (16628, 98352),
+    (2, "f32", 1, 2048): (16618, 131136),
+    (2, "f32", 1, 4096): (16632, 262272),
+    (2, "f32", 1, 8192): (16631, 524544),
+    (3, "f32", 0, 4096): (261596, 1048576),
+    (3, "f32", 0, 8192): (244770, 524320),
+    (3, "f32", 0, 16384): (244752, 1048640),
+    (3, "f32", 0, 32768): (244769, 2097280),
+    (3, "f32", 0, 65536): (244752, 4194560),
+    (3, "f32", 0, 131072): (245074, 8389120),
+    (3, "f32", 0, 262144): (246018, 16778240),
+    (3, "f32", 1, 2048): (143948, 544739),
+    (3, "f32", 1, 4096): (131871, 559945),
+    (3, "f32", 1, 8192): (138357, 1123973),
+    (3, "f32", 1, 16384): (149761, 2252654),
+    (3, "f32", 1, 32768): (189602, 4507538),
+    (3, "f32", 1, 65536): (516351, 9044517),
+    (3, "f32", 1, 131072): (1012191, 18090008),
+    (4, "f16", 0, 128): (129019, 8192),
     (4, "f16", 0, 256): (128460, 16392),
     (4, "f16", 0, 512): (128672, 32785),
     (4, "f16", 0, 768): (128884, 49177),
     (4, "f16", 0, 1024): (129097, 65569),
-    (4, "f16", 0, 2048): (129634, 131136),
-    (4, "f16", 0, 4096): (129589, 262272),
-    (4, "f16", 0, 8192): (130022, 524544),
+    (4, "f16", 0, 2048): (129624, 131136),
+    (4, "f16", 0, 4096): (129654, 262272),
+    (4, "f16", 0, 8192): (129875, 524544),
     (4, "bf16", 0, 128): (129004, 8192),
     (4, "bf16", 0, 256): (128440, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
     (4, "bf16", 0, 1024): (129078, 65569),
-    (4, "bf16", 0, 2048): (129609, 131136),
-    (4, "bf16", 0, 4096): (129635, 262272),
-    (4, "bf16", 0, 8192): (130180, 524546),
+    (4, "bf16", 0, 2048): (129610, 131136),
+    (4, "bf16", 0, 4096): (129651, 262272),
+    (4, "bf16", 0, 8192): (129881, 524544),
+    (5, "f32", 0, 1024): (548510, 262144),
+    (5, "f32", 0, 2048): (534243, 131088),
+    (5, "f32", 0, 4096): (543091, 262176),
+    (5, "f32", 0, 8192): (559808, 524352),
+    (5, "f32", 0, 16384): (591129, 1048704),
+    (5, "f32", 0, 32768): (656561, 2097408),
+    (5, "f32", 0, 65536): (787622, 4194816),
+    (5, "f32", 1, 512): (278633, 138240),
+    (5, "f32", 1, 1024): (275491, 145371),
+    (5, "f32", 1, 2048): (289296, 290795),
+    (5, "f32", 1, 4096): (320813, 581673),
+    (5, "f32", 1, 8192): (382058, 1163396),
+    (5, "f32", 1, 16384): (503031, 2326787),
+    (5, "f32", 1, 32768): (743760, 4653569),
 }
 
 
