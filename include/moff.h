@@ -241,7 +241,8 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
  * the stream; later results do not depend on the choice beyond float32
  * rounding order.  Where the fused gain adjoint is built with more than one
- * register budget (grid_n 128 and 256, see moff_plan_set_adjoint_waves), it also times
+ * register budget (grid_n 128 and 256, see moff_plan_set_adjoint_waves) and
+ * the plan has no MOFF_MFMA_* flag, it also times
  * moff_gain_vjp with each, on the same samples and gains with the tuned image
  * as the pixel sensitivities, and keeps the fastest.  moff_plan_set_config forces a choice (slices = 0:
  * heuristic); moff_plan_get_config reports the configuration a call with

@@ -769,10 +769,11 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   }
   // The fused gain adjoint's register budget (moff_plan_set_adjoint_waves):
   // where more than one is built, time each on the same input with the tuned
-  // forward image as the pixel sensitivities, and keep the fastest.
+  // forward image as the pixel sensitivities, and keep the fastest.  Not for
+  // the reduced-precision plans, whose tuning is about their image path.
   int bw = p->adj_waves;
   const int wmax = moff::adjoint_waves_max(hp.N);
-  if (result == MOFF_OK && wmax > 1 && p->d_adj_slots) {
+  if (result == MOFF_OK && wmax > 1 && p->d_adj_slots && !is_mfma(hp)) {
     p->variant = bv;
     p->slices = bs;
     float* grad = nullptr;
