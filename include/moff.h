@@ -239,7 +239,9 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * moff_plan_autotune times every candidate (variant x slices, including the
  * slice counts that fill whole rounds of resident workgroups) with HIP events
  * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
- * the stream; later results do not depend on the choice beyond float32
+ * the stream.  It first runs the default shape for about 200 ms so that no
+ * candidate is timed on a cold device, then takes each candidate's time as the
+ * best of three batches of three back-to-back calls; later results do not depend on the choice beyond float32
  * rounding order.  Where the fused gain adjoint is built with more than one
  * register budget (grid_n 128 and 256, see moff_plan_set_adjoint_waves) and
  * the plan has no MOFF_MFMA_* flag, it also times

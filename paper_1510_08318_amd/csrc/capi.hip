@@ -157,7 +157,8 @@ struct LaunchConfig {
   int variant, slices, grid;
 };
 
-constexpr int kTuneReps = 4;   // timed calls per autotuner candidate
+constexpr int kTuneReps = 3;    // timed batches per autotuner candidate
+constexpr int kTuneBatch = 3;   // back-to-back calls per timed batch (steady state, as in use)
 
 bool is_mfma(const HostPlan& hp) { return hp.mfma.prec != 0; }
 
@@ -730,6 +731,22 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   float best = 1e30f;
   int bv = saved_v, bs = saved_s;
   moff_status result = MOFF_OK;
+  {
+    // Bring the device to its steady clocks first (about 200 ms of the default
+    // launch): candidates are swept in order, and the first ones would
+    // otherwise be timed on a device that is still ramping up.
+    const LaunchConfig lc0 = launch_config(p, n_time);
+    float spent = 0.f;
+    for (int i = 0; i < 256 && spent < 200.f && result == MOFF_OK; ++i) {
+      if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
+      if (result == MOFF_OK) result = fused_run_cfg(p, lc0, E, n_time, gains, img, nullptr, true, st);
+      if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
+      if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
+      float one = 0.f;
+      if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+      spent += one;
+    }
+  }
   for (int v = 0; v < n_variants(hp) && result == MOFF_OK; ++v) {
     const KernelFootprint f = footprint(p, v);
     if (f.lds > size_t(159) * 1024) continue;
@@ -747,12 +764,14 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
         const LaunchConfig lc = launch_config(p, n_time);
         result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);   // warm-up
         if (result != MOFF_OK) break;
-        // the fastest of several separately timed calls: near-equal candidates
-        // are then ranked by their undisturbed time, not by one noisy sample
+        // the fastest of several timed batches of back-to-back calls: candidates
+        // are ranked by their steady-state time (as in use, call after call),
+        // and near-equal ones by their undisturbed batch, not one noisy sample
         float ms = 1e30f;
         for (int rep = 0; rep < kTuneReps && result == MOFF_OK; ++rep) {
           if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
-          if (result == MOFF_OK) result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);
+          for (int b = 0; b < kTuneBatch && result == MOFF_OK; ++b)
+            result = fused_run_cfg(p, lc, E, n_time, gains, img, nullptr, true, st);
           if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
           if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
           float one = 0.f;
