@@ -35,6 +35,8 @@
  *     one eager call of the same shape first; captured calls then allocate
  *     nothing and record no memset nodes (buffers are cleared by a kernel).
  *   - On any error status the contents of output buffers are unspecified.
+ *   - No C++ exception crosses this interface: a failed host allocation while
+ *     a plan or its tables are built returns MOFF_ERR_NOMEM.
  *   - NaN / Inf inputs propagate; they are not checked.
  */
 #ifndef MOFF_H

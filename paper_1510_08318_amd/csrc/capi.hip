@@ -497,47 +497,17 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
   return hip_status(moff::launch_grad_final(gf, st));
 }
 
-}  // namespace
-
-extern "C" {
-
-int moff_abi_version(void) { return MOFF_ABI_VERSION; }
-
-const char* moff_status_str(moff_status s) {
-  switch (s) {
-    case MOFF_OK: return "ok";
-    case MOFF_ERR_INVALID_ARG: return "invalid argument";
-    case MOFF_ERR_GRID_NOT_POW2: return "grid_n must be a power of two in [8, 256]";
-    case MOFF_ERR_FOOTPRINT_OVERFLOW: return "antenna footprints do not fit in the grid_n/2 aperture region";
-    case MOFF_ERR_UNSUPPORTED: return "unsupported request";
-    case MOFF_ERR_NOMEM: return "out of memory";
-    case MOFF_ERR_HIP: return "HIP runtime error";
-  }
-  return "unknown status";
-}
-
-moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_plan* out) {
-  if (!out) return MOFF_ERR_INVALID_ARG;
-  *out = nullptr;
-  moff_plan p = new (std::nothrow) moff_plan_s;
-  if (!p) return MOFF_ERR_NOMEM;
+// Host plan, then the device tables.  On an error the caller frees whatever
+// was uploaded (p->device is set once the device is current).
+moff_status plan_create_body(const moff_geometry* geom, int hip_device, moff_plan p) {
   std::string why;
   moff_status st = moff::build_host_plan(geom, &p->hp, &why);
-  if (st != MOFF_OK) {
-    delete p;
-    return st;
-  }
+  if (st != MOFF_OK) return st;
   if (hip_device >= 0) {
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) {
-      delete p;
-      return MOFF_ERR_INVALID_ARG;
-    }
+    if (hipGetDeviceCount(&count) != hipSuccess || hip_device >= count) return MOFF_ERR_INVALID_ARG;
     DeviceGuard guard(hip_device);
-    if (!guard.ok()) {
-      delete p;
-      return MOFF_ERR_HIP;
-    }
+    if (!guard.ok()) return MOFF_ERR_HIP;
     p->device = hip_device;
     const HostPlan& hp = p->hp;
     std::vector<double> Pp(hp.Pp);
@@ -575,16 +545,52 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
       up(upload(&p->d_ktype_k, hp.ktype_k.data(), sizeof(int) * hp.ktype_k.size()));
       up(upload(&p->d_ktype_off, hp.ktype_off.data(), sizeof(int) * hp.ktype_off.size()));
     }
-    if (s != MOFF_OK) {
+    if (s != MOFF_OK) return s;
+  }
+  return MOFF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int moff_abi_version(void) { return MOFF_ABI_VERSION; }
+
+const char* moff_status_str(moff_status s) {
+  switch (s) {
+    case MOFF_OK: return "ok";
+    case MOFF_ERR_INVALID_ARG: return "invalid argument";
+    case MOFF_ERR_GRID_NOT_POW2: return "grid_n must be a power of two in [8, 256]";
+    case MOFF_ERR_FOOTPRINT_OVERFLOW: return "antenna footprints do not fit in the grid_n/2 aperture region";
+    case MOFF_ERR_UNSUPPORTED: return "unsupported request";
+    case MOFF_ERR_NOMEM: return "out of memory";
+    case MOFF_ERR_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_plan* out) {
+  if (!out) return MOFF_ERR_INVALID_ARG;
+  *out = nullptr;
+  moff_plan p = new (std::nothrow) moff_plan_s;
+  if (!p) return MOFF_ERR_NOMEM;
+  moff_status st;
+  try {
+    st = plan_create_body(geom, hip_device, p);
+  } catch (...) {   // host containers of the plan build: a failed allocation
+    st = MOFF_ERR_NOMEM;
+  }
+  if (st != MOFF_OK) {
+    if (p->device >= 0) {
+      DeviceGuard guard(p->device);
       free_device(p);
-      delete p;
-      return s;
     }
+    delete p;
+    return st;
   }
   *out = p;
   return MOFF_OK;
 }
-
 moff_status moff_plan_destroy(moff_plan p) {
   if (!p) return MOFF_OK;
   if (p->device >= 0) {
@@ -751,12 +757,13 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
     const KernelFootprint f = footprint(p, v);
     if (f.lds > size_t(159) * 1024) continue;
     const int per_slice = f.per_slice, resident = f.resident;
-    std::vector<int> cand;
-    for (int k = 1; k <= 4; ++k) cand.push_back((k * resident + per_slice - 1) / per_slice);  // whole rounds
-    for (int sl : {1, 2, 4, 8, 16, 32, 64}) cand.push_back(sl);
-    std::sort(cand.begin(), cand.end());
-    cand.erase(std::unique(cand.begin(), cand.end()), cand.end());
-    for (int sl : cand) {
+    int cand[11], n_cand = 0;   // fixed size: the tuner allocates nothing on the host
+    for (int k = 1; k <= 4; ++k) cand[n_cand++] = (k * resident + per_slice - 1) / per_slice;  // whole rounds
+    for (int sl : {1, 2, 4, 8, 16, 32, 64}) cand[n_cand++] = sl;
+    std::sort(cand, cand + n_cand);
+    n_cand = static_cast<int>(std::unique(cand, cand + n_cand) - cand);
+    for (int ci = 0; ci < n_cand; ++ci) {
+      const int sl = cand[ci];
       if (sl < 1 || sl > 256 || sl > n_time || result != MOFF_OK) continue;
       {
         p->variant = v;
@@ -1021,7 +1028,11 @@ moff_status moff_image_fx(moff_plan p, const void* E, int64_t n_time, const floa
   const bool keep_autos = (hp.flags & MOFF_AUTOCORR_NONE) != 0;
   if (!p->d_fx_ptr) {
     moff::FxTables t;
-    moff::build_fx_tables(hp, keep_autos, &t);
+    try {
+      moff::build_fx_tables(hp, keep_autos, &t);
+    } catch (...) {   // the tables' host vectors: a failed allocation
+      return MOFF_ERR_NOMEM;
+    }
     moff_status u = upload(&p->d_fx_ptr, t.ptr.data(), sizeof(int32_t) * t.ptr.size());
     if (u == MOFF_OK) u = upload(&p->d_fx_ab, t.ab.data(), sizeof(int32_t) * t.ab.size());
     if (u == MOFF_OK) u = upload(&p->d_fx_x, t.xcorr.data(), sizeof(float) * t.xcorr.size());
