@@ -7,7 +7,8 @@
 // out it equals the image with the antennas' self power removed).
 //
 //   fx_correlate_kernel  V[c][a][b] = sum_t e_a conj(e_b), e = g E: float32
-//                        products over 32-sample chunks, chunks summed in float64
+//                        matrix-core products over 32-sample chunks, chunks
+//                        summed in float64, upper-triangle tiles mirrored
 //                        (complex64 samples); fx_correlate_i8_kernel: exact
 //                        integer products on the matrix cores (4+4-bit samples)
 //   fx_bin_kernel        H[c][pq][dy][dx] = sum of V[c][a][b] over the pairs of
@@ -35,7 +36,7 @@ namespace moff {
 
 namespace {
 
-constexpr int kFxTile = 32;    // antennas per side of a correlator tile
+constexpr int kFxTile = 32;    // antennas per side of a 4+4-bit correlator tile
 constexpr int kFxChunk = 32;   // time samples staged per step
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -44,22 +45,45 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 
 }  // namespace
 
-// Complex64 samples.  One workgroup per (32 x 32 antenna tile, channel); thread
-// (ty, tx) owns the pairs (ty + 16 i, tx + 16 j), i, j < 2.
+// Complex64 samples, on the matrix cores in float32 (v_mfma_f32_16x16x4_f32).
+// The visibility matrix is Hermitian, V_ba = conj(V_ab): only the tiles on and
+// above the diagonal are formed, and each off-diagonal tile also writes its
+// mirror image.  One workgroup per (64 x 64 antenna tile, channel), four waves
+// of a 32 x 32 sub-tile each (2 x 2 blocks of 16 x 16).  The complex product
+// is two real contractions over k = (sample, part):
+//   Re V_ab = sum_k A_ak B_bk,   A = (re e, im e) of antenna a, B the same of b,
+//   Im V_ab = sum_k A'_ak B_bk,  A' = (im e, -re e) of antenna a.
+// Lane l holds A[l % 16][l / 16] and B[l / 16][l % 16] with the same k = l / 16
+// (sample 2 step + k / 2, part k % 2), so each (sample, part) is summed once
+// whatever order the instruction takes its contraction index in; the
+// accumulators hold D[4 (l / 16) + v][l % 16].  Each 32-sample chunk is summed
+// in float32 and the chunks in float64.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kC64Tile = 64;               // antennas per side of a tile
+constexpr int kC64Pitch = kC64Tile + 16;   // float2 per LDS row: two samples' 16 rows hit distinct banks
+
 __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
-  __shared__ float2 ea[kFxChunk][kFxTile + 1], eb[kFxChunk][kFxTile + 1];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, cl = blockIdx.z, c = a.c0 + cl;
-  const int na = a.n_ant;
+  __shared__ float2 ea[kFxChunk][kC64Pitch], eb[kFxChunk][kC64Pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wa = wave >> 1, wb = wave & 1, r16 = lane & 15, kk = lane >> 4;
+  const int na = a.n_ant, n_tiles = (na + kC64Tile - 1) / kC64Tile;
+  int t = blockIdx.x, ta = 0;                 // upper-triangle tile (ta, tb), tb >= ta
+  while (ta < n_tiles && t >= n_tiles - ta) {
+    t -= n_tiles - ta;
+    ++ta;
+  }
+  if (ta >= n_tiles) return;                  // beyond the triangle (the launch has none)
+  const int tb = ta + t;
+  const int a0 = ta * kC64Tile, b0 = tb * kC64Tile, cl = blockIdx.z, c = a.c0 + cl;
   const float2* E = reinterpret_cast<const float2*>(a.E);
-  double acc[2][2][2] = {};
+  double acc[2][2][4][2] = {};
   for (int64_t t0 = 0; t0 < a.n_time; t0 += kFxChunk) {
-    for (int k = tid; k < kFxChunk * kFxTile; k += 256) {
-      const int tt = k / kFxTile, an = k % kFxTile;
-      const int64_t t = t0 + tt;
+    for (int k = tid; k < kFxChunk * kC64Tile; k += 256) {
+      const int tt = k / kC64Tile, an = k % kC64Tile;
+      const int64_t ts = t0 + tt;
       float2 va = make_float2(0.f, 0.f), vb = va;
-      if (t < a.n_time) {
-        const size_t base = (static_cast<size_t>(t) * a.n_chan + c) * na;
+      if (ts < a.n_time) {
+        const size_t base = (static_cast<size_t>(ts) * a.n_chan + c) * na;
         const int ia = a0 + an, ib = b0 + an;
         if (ia < na) {
           va = E[base + ia];
@@ -74,37 +98,62 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
       eb[tt][an] = vb;
     }
     __syncthreads();
-    float s[2][2][2] = {};
-    for (int tt = 0; tt < kFxChunk; ++tt) {
-      const float2 x0 = ea[tt][ty], x1 = ea[tt][ty + 16], y0 = eb[tt][tx], y1 = eb[tt][tx + 16];
-      const float2 x[2] = {x0, x1}, y[2] = {y0, y1};
+    f32x4 re[2][2], im[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        re[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        im[i][j] = re[i][j];
+      }
+    const bool imag_part = kk & 1;
+#pragma unroll 4
+    for (int step = 0; step < kFxChunk / 2; ++step) {
+      const int sm = 2 * step + (kk >> 1);
+      float A[2], Ap[2], B[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const float2 x = ea[sm][32 * wa + 16 * i + r16];
+        A[i] = imag_part ? x.y : x.x;
+        Ap[i] = imag_part ? -x.x : x.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const float2 y = eb[sm][32 * wb + 16 * j + r16];
+        B[j] = imag_part ? y.y : y.x;
+      }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          // x conj(y)
-          s[i][j][0] = fmaf(x[i].x, y[j].x, fmaf(x[i].y, y[j].y, s[i][j][0]));
-          s[i][j][1] = fmaf(x[i].y, y[j].x, fmaf(-x[i].x, y[j].y, s[i][j][1]));
+          re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(A[i], B[j], re[i][j], 0, 0, 0);
+          im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(Ap[i], B[j], im[i][j], 0, 0, 0);
         }
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j][0] += s[i][j][0];
-        acc[i][j][1] += s[i][j][1];
-      }
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          acc[i][j][v][0] += re[i][j][v];
+          acc[i][j][v][1] += im[i][j][v];
+        }
     __syncthreads();
   }
+  float2* V = a.V + static_cast<size_t>(cl) * na * na;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int ia = a0 + ty + 16 * i, ib = b0 + tx + 16 * j;
-      if (ia < na && ib < na)
-        a.V[(static_cast<size_t>(cl) * na + ia) * na + ib] =
-            make_float2(static_cast<float>(acc[i][j][0]), static_cast<float>(acc[i][j][1]));
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ia = a0 + 32 * wa + 16 * i + 4 * kk + v, ib = b0 + 32 * wb + 16 * j + r16;
+        if (ia >= na || ib >= na) continue;
+        const float x = static_cast<float>(acc[i][j][v][0]), y = static_cast<float>(acc[i][j][v][1]);
+        V[static_cast<size_t>(ia) * na + ib] = make_float2(x, y);
+        if (ta != tb) V[static_cast<size_t>(ib) * na + ia] = make_float2(x, -y);
+      }
 }
 
 // 4+4-bit samples: the cross-products are exact integer sums, formed on the
@@ -329,12 +378,15 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   if (a.n_ant < 1 || a.n_launch < 1 || a.n_launch > 65535 || a.c0 < 0 || a.c0 + a.n_launch > a.n_chan || a.N < 8 ||
       a.N > 256 || a.NL != 2 * a.L - 1 || a.n_types < 1 || a.n_types > kMaxTypesDev)
     return hipErrorInvalidValue;
-  const unsigned tiles = static_cast<unsigned>((a.n_ant + kFxTile - 1) / kFxTile);
-  const dim3 g1(tiles, tiles, static_cast<unsigned>(a.n_launch));
-  if (ci4)
-    hipLaunchKernelGGL(fx_correlate_i8_kernel, g1, dim3(256), 0, st, a);
-  else
-    hipLaunchKernelGGL(fx_correlate_kernel, g1, dim3(256), 0, st, a);
+  if (ci4) {
+    const unsigned tiles = static_cast<unsigned>((a.n_ant + kFxTile - 1) / kFxTile);
+    hipLaunchKernelGGL(fx_correlate_i8_kernel, dim3(tiles, tiles, static_cast<unsigned>(a.n_launch)), dim3(256), 0,
+                       st, a);
+  } else {
+    const unsigned nt = static_cast<unsigned>((a.n_ant + kC64Tile - 1) / kC64Tile);
+    hipLaunchKernelGGL(fx_correlate_kernel, dim3(nt * (nt + 1) / 2, 1, static_cast<unsigned>(a.n_launch)), dim3(256),
+                       0, st, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
