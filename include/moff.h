@@ -382,7 +382,8 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  * chunks whose workspace, 8 (n_ant^2 + (n_types^2 + 1) (2L - 1)^2 + (2L - 1) N)
  * bytes per channel, stays within about 2 GiB (at least one channel); it is
  * owned by the plan and shared with the plan's other entry points.  The pair
- * tables (4 n_ant^2 bytes) are built and uploaded on the first call.
+ * tables (about 2 n_ant^2 bytes: each unordered pair once) are built and
+ * uploaded on the first call.
  * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
  * MOFF_ERR_UNSUPPORTED for a plan without a device, or 4+4-bit samples with
  * n_time > 2^24 (their cross-products are exact int32 sums on the matrix

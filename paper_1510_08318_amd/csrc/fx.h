@@ -19,11 +19,11 @@ struct FxArgs {
   int64_t n_time;
   int N, L, NL, xs;            // xs: side of each pair-response table
   const int* pair_ptr;         // [NTP * NL * NL + 1] CSR over (type pair, footprint offset)
-  const int* pair_ab;          // [entries] a * n_ant + b, ascending within a row
+  const int* pair_ab;          // [entries] upper-triangle index of V, kFxConjBit: read conjugated
   const int* ktype_k;          // [n_types]
   const float2* xcorr;         // [NTP][xs][xs] pair responses of the tables
   const float2* tw;            // [N] exp(+2 pi i k / N)
-  float2* V;                   // [n_launch][n_ant][n_ant] workspace
+  float2* V;                   // [n_launch][n_ant][n_ant] workspace (upper triangle used)
   float2* H;                   // [n_launch][NTP][NL][NL] workspace
   float2* R;                   // [n_launch][NL][NL] workspace
   float2* Z;                   // [n_launch][NL][N] workspace

@@ -6,14 +6,17 @@
 // dirty-image-FX, give the MOFF image; with the zero-spacing a == b terms left
 // out it equals the image with the antennas' self power removed).
 //
-//   fx_correlate_kernel  V[c][a][b] = sum_t e_a conj(e_b), e = g E: float32
+//   fx_correlate_kernel  V[c][a][b] = sum_t e_a conj(e_b), e = g E, for a <= b
+//                        (the upper triangle; V is Hermitian): float32
 //                        matrix-core products over 32-sample chunks, chunks
-//                        summed in float64, upper-triangle tiles mirrored
-//                        (complex64 samples); fx_correlate_i8_kernel: exact
-//                        integer products on the matrix cores (4+4-bit samples)
+//                        summed in float64 (complex64 samples);
+//                        fx_correlate_i8_kernel: exact integer products on the
+//                        matrix cores (4+4-bit samples)
 //   fx_bin_kernel        H[c][pq][dy][dx] = sum of V[c][a][b] over the pairs of
 //                        table types (p, q) whose footprints are offset by
-//                        (dy, dx) - (L - 1) cells (plan-time CSR, fixed order)
+//                        (dy, dx) - (L - 1) cells (plan-time CSR, fixed order);
+//                        half the cells are summed, their mirrors
+//                        H[qp][-dy][-dx] written as the conjugates
 //   fx_lag_kernel        R[c][ly][lx] = sum_pq sum_(u,v) X_pq[u][v]
 //                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]  (LDS-tiled)
 //   fx_row_kernel        Z[c][ly][q] = sum_lx R[c][ly][lx] w^((lx - L + 1)(q - N/2))
@@ -30,6 +33,7 @@
 #include <cstdint>
 
 #include "fx.h"
+#include "fx_tables.h"
 #include "ingest.h"
 
 namespace moff {
@@ -46,9 +50,9 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }  // namespace
 
 // Complex64 samples, on the matrix cores in float32 (v_mfma_f32_16x16x4_f32).
-// The visibility matrix is Hermitian, V_ba = conj(V_ab): only the tiles on and
-// above the diagonal are formed, and each off-diagonal tile also writes its
-// mirror image.  One workgroup per (64 x 64 antenna tile, channel), four waves
+// The visibility matrix is Hermitian, V_ba = conj(V_ab), and the binning reads
+// its upper triangle only, so only the tiles on and above the diagonal are
+// formed.  One workgroup per (64 x 64 antenna tile, channel), four waves
 // of a 32 x 32 sub-tile each (2 x 2 blocks of 16 x 16).  The complex product
 // is two real contractions over k = (sample, part):
 //   Re V_ab = sum_k A_ak B_bk,   A = (re e, im e) of antenna a, B the same of b,
@@ -152,7 +156,6 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
         if (ia >= na || ib >= na) continue;
         const float x = static_cast<float>(acc[i][j][v][0]), y = static_cast<float>(acc[i][j][v][1]);
         V[static_cast<size_t>(ia) * na + ib] = make_float2(x, y);
-        if (ta != tb) V[static_cast<size_t>(ib) * na + ia] = make_float2(x, -y);
       }
 }
 
@@ -173,6 +176,7 @@ constexpr int kI8Pitch = kI8Step + 16;      // LDS row bytes: 16-byte operand re
 __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t pl[4][kFxTile][kI8Pitch];   // re A, im A, re B, im B
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (blockIdx.x < blockIdx.y) return;   // below the diagonal: the binning reads the upper triangle only
   const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, cl = blockIdx.z, c = a.c0 + cl;
   const int na = a.n_ant;
   const int8_t* E = reinterpret_cast<const int8_t*>(a.E);
@@ -230,20 +234,30 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
   }
 }
 
-// One thread per (channel, type pair, offset cell).
+// One thread per (channel, type pair, offset cell).  The thread of a cell at
+// or before its mirror (types swapped, offset negated) sums the cell's pairs
+// and writes the mirror cell as the conjugate; the thread of a later cell has
+// nothing to do.
 __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
-  const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
+  const int nl2 = a.NL * a.NL;
+  const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * nl2;
   const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= cells) return;
+  const int tp = static_cast<int>(i / nl2), off = static_cast<int>(i % nl2);
+  const size_t m = static_cast<size_t>((tp % a.n_types) * a.n_types + tp / a.n_types) * nl2 + (nl2 - 1 - off);
+  if (m < i) return;
   const int c = blockIdx.y;
   const float2* V = a.V + static_cast<size_t>(c) * a.n_ant * a.n_ant;
   double x = 0.0, y = 0.0;
   for (int k = a.pair_ptr[i]; k < a.pair_ptr[i + 1]; ++k) {
-    const float2 v = V[a.pair_ab[k]];
+    const uint32_t e = static_cast<uint32_t>(a.pair_ab[k]);
+    const float2 v = V[e & ~kFxConjBit];
     x += v.x;
-    y += v.y;
+    y += (e & kFxConjBit) ? -v.y : v.y;
   }
-  a.H[static_cast<size_t>(c) * cells + i] = make_float2(static_cast<float>(x), static_cast<float>(y));
+  float2* H = a.H + static_cast<size_t>(c) * cells;
+  H[i] = make_float2(static_cast<float>(x), static_cast<float>(y));
+  if (m != i) H[m] = make_float2(static_cast<float>(x), static_cast<float>(-y));
 }
 
 // One workgroup per (16 x 16 block of lag cells, channel), one thread per cell.

@@ -38,23 +38,33 @@ void build_fx_tables(const HostPlan& hp, bool keep_autos, FxTables* t) {
           dst[2 * (u * xs + v) + 1] = static_cast<float>(X[static_cast<size_t>(u) * side + v].imag());
         }
     }
-  // CSR of the ordered pairs by (type pair, offset cell), by counting sort
+  // CSR of the ordered pairs by (type pair, offset cell), by counting sort.
+  // The pair (b, a) lands in the mirror row -- types swapped, offset negated --
+  // with the conjugate visibility, so only rows that do not follow their mirror
+  // hold entries; the device sums those and writes each mirror as the
+  // conjugate.  An entry names the upper-triangle element min(a, b) n_ant +
+  // max(a, b), with the top bit set when a > b (conjugate on reading).
   const size_t rows = static_cast<size_t>(nt) * nt * NL * NL;
   auto row_of = [&](int a, int b) {
     const int tp = hp.ant_ktype[a] * nt + hp.ant_ktype[b];
     const int dy = hp.iy0[a] - hp.iy0[b] + L - 1, dx = hp.ix0[a] - hp.ix0[b] + L - 1;
     return (static_cast<size_t>(tp) * NL + dy) * NL + dx;
   };
+  auto canonical = [&](int a, int b) { return row_of(a, b) <= row_of(b, a); };
+  auto keep = [&](int a, int b) { return (a != b || keep_autos) && canonical(a, b); };
   t->ptr.assign(rows + 1, 0);
   for (int a = 0; a < na; ++a)
     for (int b = 0; b < na; ++b)
-      if (a != b || keep_autos) ++t->ptr[row_of(a, b) + 1];
+      if (keep(a, b)) ++t->ptr[row_of(a, b) + 1];
   for (size_t r = 0; r < rows; ++r) t->ptr[r + 1] += t->ptr[r];
   t->ab.assign(static_cast<size_t>(t->ptr[rows]), 0);
   std::vector<int32_t> fill(t->ptr.begin(), t->ptr.end() - 1);
   for (int a = 0; a < na; ++a)
     for (int b = 0; b < na; ++b)
-      if (a != b || keep_autos) t->ab[static_cast<size_t>(fill[row_of(a, b)]++)] = a * na + b;
+      if (keep(a, b)) {
+        const uint32_t upper = static_cast<uint32_t>(std::min(a, b)) * na + std::max(a, b);
+        t->ab[static_cast<size_t>(fill[row_of(a, b)]++)] = static_cast<int32_t>(upper | (a > b ? kFxConjBit : 0u));
+      }
 }
 
 }  // namespace moff
