@@ -40,7 +40,6 @@ namespace moff {
 
 namespace {
 
-constexpr int kFxTile = 32;    // antennas per side of a 4+4-bit correlator tile
 constexpr int kFxChunk = 32;   // time samples staged per step
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -163,75 +162,128 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
 // matrix cores (v_mfma_i32_16x16x64_i8, int32 accumulation) from the raw
 // samples; the gains are constant over the integration and are applied once,
 // V_ab = g_a conj(g_b) sum_t E_a conj(E_b), in float64.  One workgroup per
-// (32 x 32 antenna tile, channel), four waves of one 16 x 16 sub-tile each; per
-// 64-sample step the real and imaginary parts of both antenna blocks are staged
-// in LDS as int8 rows [antenna][sample] and each wave runs four products
-// (re.re, im.im, im.re, re.im).  A and B take their samples in the same lane
-// order, so the sum covers each sample once whatever order the instruction
-// gives its contraction index; the accumulators hold D[4 (l / 16) + j][l % 16].
+// (64 x 64 antenna tile on or above the diagonal, channel), four waves of a
+// 32 x 32 sub-tile each (2 x 2 blocks of 16 x 16).  Per 64-sample step the
+// real and imaginary parts of both antenna blocks are staged in LDS as int8
+// rows [antenna][sample], and each wave runs four products (re.re, im.im,
+// im.re, re.im) per block; the next step's samples are loaded into registers
+// while the current step's products run.  A and B take their samples in the
+// same lane order, so the sum covers each sample once whatever order the
+// instruction gives its contraction index; the accumulators hold
+// D[4 (l / 16) + j][l % 16].
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 constexpr int kI8Step = 64;                 // samples per step
 constexpr int kI8Pitch = kI8Step + 16;      // LDS row bytes: 16-byte operand reads of 16 rows hit distinct banks
 
+constexpr int kI8Blocks = 2;                          // 16 x 16 blocks per wave and side
+constexpr int kI8Tile = 32 * kI8Blocks;               // antennas per side of a tile
+constexpr int kI8PerThread = kI8Step * kI8Tile / 256;   // samples per thread and step, per block
+
 __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
-  __shared__ __attribute__((aligned(16))) int8_t pl[4][kFxTile][kI8Pitch];   // re A, im A, re B, im B
+  __shared__ __attribute__((aligned(16))) int8_t pl[4][kI8Tile][kI8Pitch];   // re A, im A, re B, im B
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (blockIdx.x < blockIdx.y) return;   // below the diagonal: the binning reads the upper triangle only
-  const int a0 = blockIdx.y * kFxTile, b0 = blockIdx.x * kFxTile, cl = blockIdx.z, c = a.c0 + cl;
-  const int na = a.n_ant;
+  const int na = a.n_ant, n_tiles = (na + kI8Tile - 1) / kI8Tile;
+  int t = blockIdx.x, ta = 0;                 // upper-triangle tile (ta, tb), tb >= ta
+  while (ta < n_tiles && t >= n_tiles - ta) {
+    t -= n_tiles - ta;
+    ++ta;
+  }
+  if (ta >= n_tiles) return;                  // beyond the triangle (the launch has none)
+  const int a0 = ta * kI8Tile, b0 = (ta + t) * kI8Tile, cl = blockIdx.z, c = a.c0 + cl;
   const int8_t* E = reinterpret_cast<const int8_t*>(a.E);
   const size_t tstride = static_cast<size_t>(a.n_chan) * na;
-  // staging: thread = (antenna an, group of 8 samples tg) for both blocks
-  const int an = tid % kFxTile, tg = tid / kFxTile;   // tg < 8
+  // staging: thread = (antenna an, group tg of kI8PerThread samples) for both blocks
+  const int an = tid % kI8Tile, tg = tid / kI8Tile;   // tg < 256 / kI8Tile
   // this wave's sub-tile and its operand rows
   const int ah = w >> 1, bh = w & 1, l16 = lane & 15, g = lane >> 4;
-  i32x4 pxx = {0, 0, 0, 0}, pyy = pxx, pyx = pxx, pxy = pxx;
-  for (int64_t t0 = 0; t0 < a.n_time; t0 += kI8Step) {
+  i32x4 acc[kI8Blocks][kI8Blocks][4];
+#pragma unroll
+  for (int i = 0; i < kI8Blocks; ++i)
+#pragma unroll
+    for (int j = 0; j < kI8Blocks; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[i][j][q] = i32x4{0, 0, 0, 0};
+  int8_t nxt[2][kI8PerThread];
+  auto load_step = [&](int64_t t0) {
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
       const int ant = (blk ? b0 : a0) + an;
-      uint64_t xr = 0, xi = 0;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int64_t t = t0 + 8 * tg + i;
-        int8_t byte = 0;
-        if (ant < na && t < a.n_time) byte = E[static_cast<size_t>(t) * tstride + static_cast<size_t>(c) * na + ant];
+      for (int i = 0; i < kI8PerThread; ++i) {
+        // out-of-range samples load element 0 (always valid) and read as zero:
+        // no branch around each load
+        const int64_t ts = t0 + kI8PerThread * tg + i;
+        const bool ok = ant < na && ts < a.n_time;
+        const int8_t v = E[ok ? static_cast<size_t>(ts) * tstride + static_cast<size_t>(c) * na + ant : size_t(0)];
+        nxt[blk][i] = ok ? v : int8_t(0);
+      }
+    }
+  };
+  load_step(0);
+  for (int64_t t0 = 0; t0 < a.n_time; t0 += kI8Step) {
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      uint64_t xr[kI8Blocks] = {}, xi[kI8Blocks] = {};
+#pragma unroll
+      for (int i = 0; i < kI8PerThread; ++i) {
+        const int8_t byte = nxt[blk][i];
         const int8_t re = static_cast<int8_t>(byte >> 4);
         const int8_t im = static_cast<int8_t>(static_cast<int8_t>(byte << 4) >> 4);
-        xr |= static_cast<uint64_t>(static_cast<uint8_t>(re)) << (8 * i);
-        xi |= static_cast<uint64_t>(static_cast<uint8_t>(im)) << (8 * i);
+        xr[i / 8] |= static_cast<uint64_t>(static_cast<uint8_t>(re)) << (8 * (i % 8));
+        xi[i / 8] |= static_cast<uint64_t>(static_cast<uint8_t>(im)) << (8 * (i % 8));
       }
-      *reinterpret_cast<uint64_t*>(&pl[2 * blk][an][8 * tg]) = xr;
-      *reinterpret_cast<uint64_t*>(&pl[2 * blk + 1][an][8 * tg]) = xi;
-    }
-    __syncthreads();
-    const i32x4 ar = *reinterpret_cast<const i32x4*>(&pl[0][16 * ah + l16][16 * g]);
-    const i32x4 ai = *reinterpret_cast<const i32x4*>(&pl[1][16 * ah + l16][16 * g]);
-    const i32x4 br = *reinterpret_cast<const i32x4*>(&pl[2][16 * bh + l16][16 * g]);
-    const i32x4 bi = *reinterpret_cast<const i32x4*>(&pl[3][16 * bh + l16][16 * g]);
-    pxx = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, br, pxx, 0, 0, 0);
-    pyy = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, bi, pyy, 0, 0, 0);
-    pyx = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai, br, pyx, 0, 0, 0);
-    pxy = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar, bi, pxy, 0, 0, 0);
-    __syncthreads();
-  }
+      uint64_t* dr = reinterpret_cast<uint64_t*>(&pl[2 * blk][an][kI8PerThread * tg]);
+      uint64_t* di = reinterpret_cast<uint64_t*>(&pl[2 * blk + 1][an][kI8PerThread * tg]);
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int ia = a0 + 16 * ah + 4 * g + j, ib = b0 + 16 * bh + l16;
-    if (ia >= na || ib >= na) continue;
-    // E_a conj(E_b) = (xa xb + ya yb) + i (ya xb - xa yb)
-    const double vr = static_cast<double>(pxx[j]) + pyy[j], vi = static_cast<double>(pyx[j]) - pxy[j];
-    double zr = vr, zi = vi;
-    if (a.gains) {
-      const float2 ga = a.gains[static_cast<size_t>(c) * na + ia], gb = a.gains[static_cast<size_t>(c) * na + ib];
-      // g_a conj(g_b)
-      const double gr = static_cast<double>(ga.x) * gb.x + static_cast<double>(ga.y) * gb.y;
-      const double gi = static_cast<double>(ga.y) * gb.x - static_cast<double>(ga.x) * gb.y;
-      zr = gr * vr - gi * vi;
-      zi = gr * vi + gi * vr;
+      for (int h = 0; h < kI8Blocks; ++h) {
+        dr[h] = xr[h];
+        di[h] = xi[h];
+      }
     }
-    a.V[(static_cast<size_t>(cl) * na + ia) * na + ib] = make_float2(static_cast<float>(zr), static_cast<float>(zi));
+    __syncthreads();
+    if (t0 + kI8Step < a.n_time) load_step(t0 + kI8Step);   // in flight during the products
+    i32x4 ar[kI8Blocks], ai[kI8Blocks], br[kI8Blocks], bi[kI8Blocks];
+#pragma unroll
+    for (int i = 0; i < kI8Blocks; ++i) {
+      ar[i] = *reinterpret_cast<const i32x4*>(&pl[0][16 * kI8Blocks * ah + 16 * i + l16][16 * g]);
+      ai[i] = *reinterpret_cast<const i32x4*>(&pl[1][16 * kI8Blocks * ah + 16 * i + l16][16 * g]);
+      br[i] = *reinterpret_cast<const i32x4*>(&pl[2][16 * kI8Blocks * bh + 16 * i + l16][16 * g]);
+      bi[i] = *reinterpret_cast<const i32x4*>(&pl[3][16 * kI8Blocks * bh + 16 * i + l16][16 * g]);
+    }
+#pragma unroll
+    for (int i = 0; i < kI8Blocks; ++i)
+#pragma unroll
+      for (int j = 0; j < kI8Blocks; ++j) {
+        acc[i][j][0] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar[i], br[j], acc[i][j][0], 0, 0, 0);
+        acc[i][j][1] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai[i], bi[j], acc[i][j][1], 0, 0, 0);
+        acc[i][j][2] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ai[i], br[j], acc[i][j][2], 0, 0, 0);
+        acc[i][j][3] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ar[i], bi[j], acc[i][j][3], 0, 0, 0);
+      }
+    __syncthreads();
   }
+  float2* V = a.V + static_cast<size_t>(cl) * na * na;
+#pragma unroll
+  for (int i = 0; i < kI8Blocks; ++i)
+#pragma unroll
+    for (int j = 0; j < kI8Blocks; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int ia = a0 + 16 * kI8Blocks * ah + 16 * i + 4 * g + e, ib = b0 + 16 * kI8Blocks * bh + 16 * j + l16;
+        if (ia >= na || ib >= na) continue;
+        // E_a conj(E_b) = (xa xb + ya yb) + i (ya xb - xa yb)
+        const double vr = static_cast<double>(acc[i][j][0][e]) + acc[i][j][1][e];
+        const double vi = static_cast<double>(acc[i][j][2][e]) - acc[i][j][3][e];
+        double zr = vr, zi = vi;
+        if (a.gains) {
+          const float2 ga = a.gains[static_cast<size_t>(c) * na + ia], gb = a.gains[static_cast<size_t>(c) * na + ib];
+          // g_a conj(g_b)
+          const double gr = static_cast<double>(ga.x) * gb.x + static_cast<double>(ga.y) * gb.y;
+          const double gi = static_cast<double>(ga.y) * gb.x - static_cast<double>(ga.x) * gb.y;
+          zr = gr * vr - gi * vi;
+          zi = gr * vi + gi * vr;
+        }
+        V[static_cast<size_t>(ia) * na + ib] = make_float2(static_cast<float>(zr), static_cast<float>(zi));
+      }
 }
 
 // One thread per (channel, type pair, offset cell).  The thread of a cell at
@@ -393,9 +445,9 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
       a.N > 256 || a.NL != 2 * a.L - 1 || a.n_types < 1 || a.n_types > kMaxTypesDev)
     return hipErrorInvalidValue;
   if (ci4) {
-    const unsigned tiles = static_cast<unsigned>((a.n_ant + kFxTile - 1) / kFxTile);
-    hipLaunchKernelGGL(fx_correlate_i8_kernel, dim3(tiles, tiles, static_cast<unsigned>(a.n_launch)), dim3(256), 0,
-                       st, a);
+    const unsigned nt = static_cast<unsigned>((a.n_ant + kI8Tile - 1) / kI8Tile);
+    hipLaunchKernelGGL(fx_correlate_i8_kernel, dim3(nt * (nt + 1) / 2, 1, static_cast<unsigned>(a.n_launch)), dim3(256),
+                       0, st, a);
   } else {
     const unsigned nt = static_cast<unsigned>((a.n_ant + kC64Tile - 1) / kC64Tile);
     hipLaunchKernelGGL(fx_correlate_kernel, dim3(nt * (nt + 1) / 2, 1, static_cast<unsigned>(a.n_launch)), dim3(256),
