@@ -18,7 +18,8 @@
 //                        half the cells are summed, their mirrors
 //                        H[qp][-dy][-dx] written as the conjugates
 //   fx_lag_kernel        R[c][ly][lx] = sum_pq sum_(u,v) X_pq[u][v]
-//                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]  (LDS-tiled)
+//                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]  (LDS-tiled;
+//                        half the cells, their mirrors written as conjugates)
 //   fx_row_kernel        Z[c][ly][q] = sum_lx R[c][ly][lx] w^((lx - L + 1)(q - N/2))
 //   fx_col_kernel        I[c][r][q] = scale Re sum_ly w^((ly - L + 1)(r - N/2)) Z[c][ly][q]
 //                        (both as N-point radix-2 transforms in LDS, float32)
@@ -315,7 +316,10 @@ __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
 // One workgroup per (16 x 16 block of lag cells, channel), one thread per cell.
 // Per type pair the block's window of H (with a halo of the pair response's
 // side) and the response itself are staged in LDS; cells of H outside the lag
-// grid read as zero.
+// grid read as zero.  The pair responses obey X_qp(-u) = conj X_pq(u) and the
+// binned sums H_qp(-d) = conj H_pq(d) (centred offsets), so the lag grid obeys
+// R(-l) = conj R(l): blocks past the zero lag return at once, and each cell
+// before it also writes its mirror.
 constexpr int kLagTile = 16;
 
 __global__ __launch_bounds__(256) void fx_lag_kernel(FxArgs a) {
@@ -326,6 +330,10 @@ __global__ __launch_bounds__(256) void fx_lag_kernel(FxArgs a) {
   float2* Xt = fx_lds + ht * ht;                  // [side][side]
   const int tyl = threadIdx.x / kLagTile, txl = threadIdx.x % kLagTile;
   const int ty0 = blockIdx.y * kLagTile, tx0 = blockIdx.x * kLagTile;
+  const int mid = NL / 2;                         // the zero lag, L - 1
+  // R(-l) = conj R(l): only cells (ly, lx) at or before their mirror
+  // (NL - 1 - ly, NL - 1 - lx) are summed; blocks with none of them stop here
+  if (ty0 > mid || (ty0 == mid && tx0 > mid)) return;
   const size_t plane = static_cast<size_t>(NL) * NL;
   double x = 0.0, y = 0.0;
   for (int tp = 0; tp < nt * nt; ++tp) {
@@ -354,8 +362,13 @@ __global__ __launch_bounds__(256) void fx_lag_kernel(FxArgs a) {
     y += py;
   }
   const int ly = ty0 + tyl, lx = tx0 + txl;
-  if (ly < NL && lx < NL) a.R[static_cast<size_t>(c) * plane + static_cast<size_t>(ly) * NL + lx] =
-      make_float2(static_cast<float>(x), static_cast<float>(y));
+  const bool canonical = ly < mid || (ly == mid && lx <= mid);
+  if (ly < NL && lx < NL && canonical) {
+    float2* R = a.R + static_cast<size_t>(c) * plane;
+    R[static_cast<size_t>(ly) * NL + lx] = make_float2(static_cast<float>(x), static_cast<float>(y));
+    if (ly != mid || lx != mid)
+      R[static_cast<size_t>(NL - 1 - ly) * NL + (NL - 1 - lx)] = make_float2(static_cast<float>(x), static_cast<float>(-y));
+  }
 }
 
 // Radix-2 decimation-in-time transform, in place, of `lines` interleaved lines
