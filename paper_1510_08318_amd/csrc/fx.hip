@@ -21,7 +21,9 @@
 //                        H[c][pq][ly - u + k_q - 1][lx - v + k_q - 1]  (LDS-tiled;
 //                        half the cells, their mirrors written as conjugates)
 //   fx_row_kernel        Z[c][ly][q] = sum_lx R[c][ly][lx] w^((lx - L + 1)(q - N/2))
+//                        (rows up to the zero lag; the others are conjugates)
 //   fx_col_kernel        I[c][r][q] = scale Re sum_ly w^((ly - L + 1)(r - N/2)) Z[c][ly][q]
+//                        (real, two columns per complex transform)
 //                        (both as N-point radix-2 transforms in LDS, float32)
 //
 // w = exp(+2 pi i / N); lags span -(L - 1) .. L - 1, so the image comes out in
@@ -31,6 +33,7 @@
 // transform passes run in float32; intermediate arrays are float32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "fx.h"
@@ -402,7 +405,10 @@ __device__ __forceinline__ float2 lag_point(const float2* line, int n, int N, in
 
 constexpr int kFxRowLines = 8;   // lag rows per workgroup of the row pass
 
-// Row pass: one workgroup per (block of kFxRowLines lag rows, channel).
+// Row pass: one workgroup per (block of kFxRowLines lag rows, channel).  With
+// R(-l) = conj R(l), the transform of lag row NL - 1 - ly is the conjugate of
+// that of row ly (same pixel column), so only rows up to the zero lag L - 1
+// are transformed and each row before it also writes its mirror.
 __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
   const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y, ly0 = blockIdx.x * kFxRowLines;
@@ -418,19 +424,28 @@ __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
   }
   __syncthreads();
   fft_lines(X, tw, N, kFxRowLines);
+  float2* Z = a.Z + static_cast<size_t>(c) * NL * N;
   for (int i = threadIdx.x; i < kFxRowLines * N; i += blockDim.x) {
     const int k = i / N, q = i % N, ly = ly0 + k;
-    if (ly < NL) a.Z[(static_cast<size_t>(c) * NL + ly) * N + q] = X[q * kFxRowLines + k];
+    if (ly > L - 1) continue;   // written by its mirror row
+    const float2 v = X[q * kFxRowLines + k];
+    Z[static_cast<size_t>(ly) * N + q] = v;
+    if (ly < L - 1) Z[static_cast<size_t>(NL - 1 - ly) * N + q] = make_float2(v.x, -v.y);
   }
 }
 
-// Column pass: one workgroup per (block of min(32, N) image columns, channel);
-// the lag column of Z is gathered through lag_point's mapping, transformed, and
-// its real part (scaled) written as 128-byte row segments of the image.
+// Column pass: one workgroup per (block of 2 cw image columns, channel).  Each
+// column of Z is Hermitian in the lag (Z(-l, q) = conj Z(l, q)), so its
+// transform is real: columns q and q + cw go through one complex transform as
+// Z(., q) + i Z(., q + cw), and the real and imaginary parts of the result are
+// the two image columns.  The lag columns are gathered through lag_point's
+// mapping, and the scaled results written as row segments of the image.
+__device__ __forceinline__ int fx_col_width(int N) { return N < 16 ? 1 : (N / 8 < 32 ? N / 8 : 32); }
+
 __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
   const int N = a.N, NL = a.NL, L = a.L, c = blockIdx.y;   // c: channel within the launch
-  const int cw = N < 32 ? N : 32, q0 = blockIdx.x * cw, bits = 31 - __clz(N);
+  const int cw = fx_col_width(N), q0 = blockIdx.x * 2 * cw, bits = 31 - __clz(N);
   float2* X = fx_lds;                       // [N][cw]
   float2* tw = fx_lds + N * cw;             // [N]
   for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = a.tw[i];
@@ -440,16 +455,20 @@ __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
     const int d = n < N / 2 ? n : n - N;
     float2 v = make_float2(0.f, 0.f);
     if (d >= -(L - 1) && d <= L - 1) {
-      v = Z[static_cast<size_t>(d + L - 1) * N + q0 + k];
+      const float2 z1 = Z[static_cast<size_t>(d + L - 1) * N + q0 + k];
+      const float2 z2 = Z[static_cast<size_t>(d + L - 1) * N + q0 + cw + k];
+      v = make_float2(z1.x - z2.y, z1.y + z2.x);   // z1 + i z2
       if (d & 1) v = make_float2(-v.x, -v.y);
     }
     X[bit_reverse(n, bits) * cw + k] = v;
   }
   __syncthreads();
   fft_lines(X, tw, N, cw);
-  for (int i = threadIdx.x; i < cw * N; i += blockDim.x) {
-    const int r = i / cw, k = i % cw;
-    a.out[(static_cast<size_t>(a.c0 + c) * N + r) * N + q0 + k] = static_cast<float>(X[r * cw + k].x * a.scale);
+  float* out = a.out + static_cast<size_t>(a.c0 + c) * N * N;
+  for (int i = threadIdx.x; i < 2 * cw * N; i += blockDim.x) {
+    const int r = i / (2 * cw), k = i % (2 * cw);
+    const float2 y = X[r * cw + k % cw];
+    out[static_cast<size_t>(r) * N + q0 + k] = static_cast<float>((k < cw ? y.x : y.y) * a.scale);
   }
 }
 
@@ -477,15 +496,15 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_tiles, lag_tiles, a.n_launch), dim3(kLagTile * kLagTile), lag_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t row_lds = sizeof(float2) * static_cast<size_t>(a.N) * (kFxRowLines + 1);
-  const unsigned row_blocks = static_cast<unsigned>((a.NL + kFxRowLines - 1) / kFxRowLines);
+  const unsigned row_blocks = static_cast<unsigned>((a.L + kFxRowLines - 1) / kFxRowLines);   // rows 0 .. L - 1
   hipLaunchKernelGGL(fx_row_kernel, dim3(row_blocks, a.n_launch), dim3(256), row_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int cw = a.N < 32 ? a.N : 32;
+  const int cw = a.N < 16 ? 1 : std::min(a.N / 8, 32);   // fx_col_width
   const size_t col_lds = sizeof(float2) * static_cast<size_t>(a.N) * (cw + 1);
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fx_col_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(col_lds))) != hipSuccess)
     return e;
-  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / cw, a.n_launch), dim3(256), col_lds, st, a);
+  hipLaunchKernelGGL(fx_col_kernel, dim3(a.N / (2 * cw), a.n_launch), dim3(256), col_lds, st, a);
   return hipGetLastError();
 }
 
