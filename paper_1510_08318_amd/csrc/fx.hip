@@ -290,6 +290,8 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
       }
 }
 
+constexpr int kFxBinBatch = 8;   // pair loads in flight per thread of the binning
+
 // One thread per (channel, type pair, offset cell).  The thread of a cell at
 // or before its mirror (types swapped, offset negated) sums the cell's pairs
 // and writes the mirror cell as the conjugate; the thread of a later cell has
@@ -305,7 +307,25 @@ __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   const int c = blockIdx.y;
   const float2* V = a.V + static_cast<size_t>(c) * a.n_ant * a.n_ant;
   double x = 0.0, y = 0.0;
-  for (int k = a.pair_ptr[i]; k < a.pair_ptr[i + 1]; ++k) {
+  // Rows of short, redundant baselines hold hundreds of pairs: loads go out
+  // kFxBinBatch at a time (indices, then visibilities) and are summed in the
+  // same order as one at a time.
+  int k = a.pair_ptr[i];
+  const int k1 = a.pair_ptr[i + 1];
+  for (; k + kFxBinBatch <= k1; k += kFxBinBatch) {
+    uint32_t e[kFxBinBatch];
+    float2 v[kFxBinBatch];
+#pragma unroll
+    for (int j = 0; j < kFxBinBatch; ++j) e[j] = static_cast<uint32_t>(a.pair_ab[k + j]);
+#pragma unroll
+    for (int j = 0; j < kFxBinBatch; ++j) v[j] = V[e[j] & ~kFxConjBit];
+#pragma unroll
+    for (int j = 0; j < kFxBinBatch; ++j) {
+      x += v[j].x;
+      y += (e[j] & kFxConjBit) ? -v[j].y : v[j].y;
+    }
+  }
+  for (; k < k1; ++k) {
     const uint32_t e = static_cast<uint32_t>(a.pair_ab[k]);
     const float2 v = V[e & ~kFxConjBit];
     x += v.x;
