@@ -84,27 +84,37 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   const int a0 = ta * kC64Tile, b0 = tb * kC64Tile, cl = blockIdx.z, c = a.c0 + cl;
   const float2* E = reinterpret_cast<const float2*>(a.E);
   double acc[2][2][4][2] = {};
+  // staging: thread = (antenna an, samples sg + kC64Rows i); each thread keeps
+  // its two antennas' gains, and the next chunk's samples load into registers
+  // while the current chunk's products run
+  constexpr int kC64Rows = 256 / kC64Tile, kC64Per = kFxChunk / kC64Rows;
+  const int an = tid % kC64Tile, sg = tid / kC64Tile;
+  const int ia = a0 + an, ib = b0 + an;
+  const float2 one = make_float2(1.f, 0.f);
+  const float2 ga = (a.gains && ia < na) ? a.gains[static_cast<size_t>(c) * na + ia] : one;
+  const float2 gb = (a.gains && ib < na) ? a.gains[static_cast<size_t>(c) * na + ib] : one;
+  float2 pa[kC64Per], pb[kC64Per];
+  auto load_chunk = [&](int64_t t0) {
+#pragma unroll
+    for (int i = 0; i < kC64Per; ++i) {
+      const int64_t ts = t0 + sg + kC64Rows * i;
+      const size_t base = (static_cast<size_t>(ts) * a.n_chan + c) * na;
+      // out-of-range samples load element 0 (always valid) and read as zero
+      const bool oka = ts < a.n_time && ia < na, okb = ts < a.n_time && ib < na;
+      const float2 va = E[oka ? base + ia : size_t(0)], vb = E[okb ? base + ib : size_t(0)];
+      pa[i] = oka ? va : make_float2(0.f, 0.f);
+      pb[i] = okb ? vb : make_float2(0.f, 0.f);
+    }
+  };
+  load_chunk(0);
   for (int64_t t0 = 0; t0 < a.n_time; t0 += kFxChunk) {
-    for (int k = tid; k < kFxChunk * kC64Tile; k += 256) {
-      const int tt = k / kC64Tile, an = k % kC64Tile;
-      const int64_t ts = t0 + tt;
-      float2 va = make_float2(0.f, 0.f), vb = va;
-      if (ts < a.n_time) {
-        const size_t base = (static_cast<size_t>(ts) * a.n_chan + c) * na;
-        const int ia = a0 + an, ib = b0 + an;
-        if (ia < na) {
-          va = E[base + ia];
-          if (a.gains) va = cmul(a.gains[static_cast<size_t>(c) * na + ia], va);
-        }
-        if (ib < na) {
-          vb = E[base + ib];
-          if (a.gains) vb = cmul(a.gains[static_cast<size_t>(c) * na + ib], vb);
-        }
-      }
-      ea[tt][an] = va;
-      eb[tt][an] = vb;
+#pragma unroll
+    for (int i = 0; i < kC64Per; ++i) {
+      ea[sg + kC64Rows * i][an] = cmul(ga, pa[i]);
+      eb[sg + kC64Rows * i][an] = cmul(gb, pb[i]);
     }
     __syncthreads();
+    if (t0 + kFxChunk < a.n_time) load_chunk(t0 + kFxChunk);
     f32x4 re[2][2], im[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
