@@ -301,6 +301,7 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
 }
 
 constexpr int kFxBinBatch = 8;   // pair loads in flight per thread of the binning
+constexpr unsigned kFxXcds = 8;  // accelerator dies (XCDs), each with its own L2
 
 // One thread per (channel, type pair, offset cell).  The thread of a cell at
 // or before its mirror (types swapped, offset negated) sums the cell's pairs
@@ -309,12 +310,18 @@ constexpr int kFxBinBatch = 8;   // pair loads in flight per thread of the binni
 __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   const int nl2 = a.NL * a.NL;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * nl2;
-  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  // Workgroups go to the XCDs round-robin by linear index; all blocks of one
+  // channel take the same residue mod kFxXcds, so one XCD's L2 serves that
+  // channel's visibilities
+  const unsigned nblk = static_cast<unsigned>((cells + 255) / 256);
+  const unsigned xcd = blockIdx.x % kFxXcds, s = blockIdx.x / kFxXcds;
+  const int c = static_cast<int>(xcd + kFxXcds * (s / nblk));
+  if (c >= a.n_launch) return;
+  const size_t i = static_cast<size_t>(s % nblk) * 256 + threadIdx.x;
   if (i >= cells) return;
   const int tp = static_cast<int>(i / nl2), off = static_cast<int>(i % nl2);
   const size_t m = static_cast<size_t>((tp % a.n_types) * a.n_types + tp / a.n_types) * nl2 + (nl2 - 1 - off);
   if (m < i) return;
-  const int c = blockIdx.y;
   const float2* V = a.V + static_cast<size_t>(c) * a.n_ant * a.n_ant;
   double x = 0.0, y = 0.0;
   // Rows of short, redundant baselines hold hundreds of pairs: loads go out
@@ -518,7 +525,9 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
-  hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>((cells + 255) / 256), a.n_launch), dim3(256), 0, st, a);
+  const size_t bin_blocks = ((cells + 255) / 256) * kFxXcds * ((a.n_launch + kFxXcds - 1) / kFxXcds);
+  if (bin_blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>(bin_blocks)), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const unsigned lag_tiles = static_cast<unsigned>((a.NL + kLagTile - 1) / kLagTile);
   const int ht = kLagTile + a.xs - 1;
