@@ -45,6 +45,20 @@ namespace moff {
 namespace {
 
 constexpr int kFxChunk = 32;   // time samples staged per step
+constexpr unsigned kFxXcds = 8;  // accelerator dies (XCDs), each with its own L2
+
+// Workgroups go to the XCDs round-robin by linear index.  For a 1-D grid of
+// kFxXcds * ceil(n / kFxXcds) * per blocks over n channels of `per` blocks
+// each, the channel of block b and its index within the channel: all blocks of
+// a channel share one residue mod kFxXcds, so one XCD's L2 serves the data of
+// that channel.  Returns false for the padding blocks.
+__device__ __forceinline__ bool xcd_channel(unsigned b, unsigned per, int n, int* ch, unsigned* j) {
+  const unsigned xcd = b % kFxXcds, s = b / kFxXcds;
+  *ch = static_cast<int>(xcd + kFxXcds * (s / per));
+  *j = s % per;
+  return *ch < n;
+}
+inline size_t xcd_grid(size_t per, int n) { return per * kFxXcds * ((static_cast<size_t>(n) + kFxXcds - 1) / kFxXcds); }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -74,14 +88,17 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave >> 1, wb = wave & 1, r16 = lane & 15, kk = lane >> 4;
   const int na = a.n_ant, n_tiles = (na + kC64Tile - 1) / kC64Tile;
-  int t = blockIdx.x, ta = 0;                 // upper-triangle tile (ta, tb), tb >= ta
+  int cl;
+  unsigned tri;
+  if (!xcd_channel(blockIdx.x, static_cast<unsigned>(n_tiles * (n_tiles + 1) / 2), a.n_launch, &cl, &tri)) return;
+  int t = static_cast<int>(tri), ta = 0;      // upper-triangle tile (ta, tb), tb >= ta
   while (ta < n_tiles && t >= n_tiles - ta) {
     t -= n_tiles - ta;
     ++ta;
   }
   if (ta >= n_tiles) return;                  // beyond the triangle (the launch has none)
   const int tb = ta + t;
-  const int a0 = ta * kC64Tile, b0 = tb * kC64Tile, cl = blockIdx.z, c = a.c0 + cl;
+  const int a0 = ta * kC64Tile, b0 = tb * kC64Tile, c = a.c0 + cl;
   const float2* E = reinterpret_cast<const float2*>(a.E);
   double acc[2][2][4][2] = {};
   // staging: thread = (antenna an, samples sg + kC64Rows i); each thread keeps
@@ -197,13 +214,16 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
   __shared__ __attribute__((aligned(16))) int8_t pl[4][kI8Tile][kI8Pitch];   // re A, im A, re B, im B
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int na = a.n_ant, n_tiles = (na + kI8Tile - 1) / kI8Tile;
-  int t = blockIdx.x, ta = 0;                 // upper-triangle tile (ta, tb), tb >= ta
+  int cl;
+  unsigned tri;
+  if (!xcd_channel(blockIdx.x, static_cast<unsigned>(n_tiles * (n_tiles + 1) / 2), a.n_launch, &cl, &tri)) return;
+  int t = static_cast<int>(tri), ta = 0;      // upper-triangle tile (ta, tb), tb >= ta
   while (ta < n_tiles && t >= n_tiles - ta) {
     t -= n_tiles - ta;
     ++ta;
   }
   if (ta >= n_tiles) return;                  // beyond the triangle (the launch has none)
-  const int a0 = ta * kI8Tile, b0 = (ta + t) * kI8Tile, cl = blockIdx.z, c = a.c0 + cl;
+  const int a0 = ta * kI8Tile, b0 = (ta + t) * kI8Tile, c = a.c0 + cl;
   const int8_t* E = reinterpret_cast<const int8_t*>(a.E);
   const size_t tstride = static_cast<size_t>(a.n_chan) * na;
   // staging: thread = (antenna an, group tg of kI8PerThread samples) for both blocks
@@ -301,7 +321,6 @@ __global__ __launch_bounds__(256) void fx_correlate_i8_kernel(FxArgs a) {
 }
 
 constexpr int kFxBinBatch = 8;   // pair loads in flight per thread of the binning
-constexpr unsigned kFxXcds = 8;  // accelerator dies (XCDs), each with its own L2
 
 // One thread per (channel, type pair, offset cell).  The thread of a cell at
 // or before its mirror (types swapped, offset negated) sums the cell's pairs
@@ -310,14 +329,10 @@ constexpr unsigned kFxXcds = 8;  // accelerator dies (XCDs), each with its own L
 __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   const int nl2 = a.NL * a.NL;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * nl2;
-  // Workgroups go to the XCDs round-robin by linear index; all blocks of one
-  // channel take the same residue mod kFxXcds, so one XCD's L2 serves that
-  // channel's visibilities
-  const unsigned nblk = static_cast<unsigned>((cells + 255) / 256);
-  const unsigned xcd = blockIdx.x % kFxXcds, s = blockIdx.x / kFxXcds;
-  const int c = static_cast<int>(xcd + kFxXcds * (s / nblk));
-  if (c >= a.n_launch) return;
-  const size_t i = static_cast<size_t>(s % nblk) * 256 + threadIdx.x;
+  int c;
+  unsigned blk;
+  if (!xcd_channel(blockIdx.x, static_cast<unsigned>((cells + 255) / 256), a.n_launch, &c, &blk)) return;
+  const size_t i = static_cast<size_t>(blk) * 256 + threadIdx.x;
   if (i >= cells) return;
   const int tp = static_cast<int>(i / nl2), off = static_cast<int>(i % nl2);
   const size_t m = static_cast<size_t>((tp % a.n_types) * a.n_types + tp / a.n_types) * nl2 + (nl2 - 1 - off);
@@ -514,18 +529,20 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
       a.N > 256 || a.NL != 2 * a.L - 1 || a.n_types < 1 || a.n_types > kMaxTypesDev)
     return hipErrorInvalidValue;
   if (ci4) {
-    const unsigned nt = static_cast<unsigned>((a.n_ant + kI8Tile - 1) / kI8Tile);
-    hipLaunchKernelGGL(fx_correlate_i8_kernel, dim3(nt * (nt + 1) / 2, 1, static_cast<unsigned>(a.n_launch)), dim3(256),
-                       0, st, a);
+    const size_t nt = static_cast<size_t>((a.n_ant + kI8Tile - 1) / kI8Tile);
+    const size_t blocks = xcd_grid(nt * (nt + 1) / 2, a.n_launch);
+    if (blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fx_correlate_i8_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
   } else {
-    const unsigned nt = static_cast<unsigned>((a.n_ant + kC64Tile - 1) / kC64Tile);
-    hipLaunchKernelGGL(fx_correlate_kernel, dim3(nt * (nt + 1) / 2, 1, static_cast<unsigned>(a.n_launch)), dim3(256),
-                       0, st, a);
+    const size_t nt = static_cast<size_t>((a.n_ant + kC64Tile - 1) / kC64Tile);
+    const size_t blocks = xcd_grid(nt * (nt + 1) / 2, a.n_launch);
+    if (blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fx_correlate_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const size_t cells = static_cast<size_t>(a.n_types) * a.n_types * a.NL * a.NL;
-  const size_t bin_blocks = ((cells + 255) / 256) * kFxXcds * ((a.n_launch + kFxXcds - 1) / kFxXcds);
+  const size_t bin_blocks = xcd_grid((cells + 255) / 256, a.n_launch);
   if (bin_blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>(bin_blocks)), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
