@@ -368,61 +368,84 @@ __global__ __launch_bounds__(256) void fx_bin_kernel(FxArgs a) {
   if (m != i) H[m] = make_float2(static_cast<float>(x), static_cast<float>(-y));
 }
 
-// One workgroup per (16 x 16 block of lag cells, channel), one thread per cell.
-// Per type pair the block's window of H (with a halo of the pair response's
-// side) and the response itself are staged in LDS; cells of H outside the lag
-// grid read as zero.  The pair responses obey X_qp(-u) = conj X_pq(u) and the
-// binned sums H_qp(-d) = conj H_pq(d) (centred offsets), so the lag grid obeys
+// One workgroup per (16 x 64 block of lag cells, channel); each thread owns
+// four horizontally adjacent cells.  Per type pair the block's window of H
+// (with a halo of the pair response's side) and the response itself are
+// staged in LDS; cells of H outside the lag grid read as zero.  Along a
+// response row the four cells' window values slide by one column per tap, so
+// a row of `side` taps reads side + 3 window values instead of 4 side.  The
+// pair responses obey X_qp(-u) = conj X_pq(u) and the binned sums
+// H_qp(-d) = conj H_pq(d) (centred offsets), so the lag grid obeys
 // R(-l) = conj R(l): blocks past the zero lag return at once, and each cell
 // before it also writes its mirror.
-constexpr int kLagTile = 16;
+constexpr int kLagRows = 16, kLagCols = 64, kLagCells = 4;   // block of lag cells; cells per thread
 
 __global__ __launch_bounds__(256) void fx_lag_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
   const int NL = a.NL, nt = a.n_types, c = blockIdx.z;
-  const int ht = kLagTile + a.xs - 1;             // widest window
-  float2* Ht = fx_lds;                            // [ht][ht]
-  float2* Xt = fx_lds + ht * ht;                  // [side][side]
-  const int tyl = threadIdx.x / kLagTile, txl = threadIdx.x % kLagTile;
-  const int ty0 = blockIdx.y * kLagTile, tx0 = blockIdx.x * kLagTile;
+  const int hw = kLagCols + a.xs - 1;             // window row pitch (widest window)
+  float2* Ht = fx_lds;                            // [kLagRows + xs - 1][hw]
+  float2* Xt = fx_lds + (kLagRows + a.xs - 1) * hw;   // [side][side]
+  const int tyl = threadIdx.x / (kLagCols / kLagCells), txg = threadIdx.x % (kLagCols / kLagCells);
+  const int ty0 = blockIdx.y * kLagRows, tx0 = blockIdx.x * kLagCols;
   const int mid = NL / 2;                         // the zero lag, L - 1
-  // R(-l) = conj R(l): only cells (ly, lx) at or before their mirror
-  // (NL - 1 - ly, NL - 1 - lx) are summed; blocks with none of them stop here
-  if (ty0 > mid || (ty0 == mid && tx0 > mid)) return;
+  if (ty0 > mid || (ty0 == mid && tx0 > mid)) return;   // no cell at or before its mirror
   const size_t plane = static_cast<size_t>(NL) * NL;
-  double x = 0.0, y = 0.0;
+  double x[kLagCells] = {}, y[kLagCells] = {};
   for (int tp = 0; tp < nt * nt; ++tp) {
-    const int kb = a.ktype_k[tp % nt], side = a.ktype_k[tp / nt] + kb - 1, ext = kLagTile + side - 1;
+    const int kb = a.ktype_k[tp % nt], side = a.ktype_k[tp / nt] + kb - 1;
+    const int ey = kLagRows + side - 1, ex = kLagCols + side - 1;
     const int hy0 = ty0 + kb - side, hx0 = tx0 + kb - side;
     const float2* H = a.H + (static_cast<size_t>(c) * nt * nt + tp) * plane;
     const float2* X = a.xcorr + static_cast<size_t>(tp) * a.xs * a.xs;
     __syncthreads();   // the previous pair's windows are no longer read
-    for (int i = threadIdx.x; i < ext * ext; i += blockDim.x) {
-      const int hy = hy0 + i / ext, hx = hx0 + i % ext;
-      Ht[(i / ext) * ht + i % ext] =
+    for (int i = threadIdx.x; i < ey * ex; i += blockDim.x) {
+      const int hy = hy0 + i / ex, hx = hx0 + i % ex;
+      Ht[(i / ex) * hw + i % ex] =
           (hy >= 0 && hy < NL && hx >= 0 && hx < NL) ? H[static_cast<size_t>(hy) * NL + hx] : make_float2(0.f, 0.f);
     }
     for (int i = threadIdx.x; i < side * side; i += blockDim.x) Xt[i] = X[(i / side) * a.xs + i % side];
     __syncthreads();
-    // H row of response row u: ly - u + kb - 1, i.e. window row tyl - u + side - 1;
-    // one pair's response sum in float32, the pairs combined in float64
-    float px = 0.f, py = 0.f;
-    for (int u = 0; u < side; ++u)
+    // cell (tyl, 4 txg + j) at response tap (u, v) reads window cell
+    // (tyl - u + side - 1, 4 txg + j - v + side - 1); one pair's response sum
+    // in float32, the pairs combined in float64
+    float px[kLagCells] = {}, py[kLagCells] = {};
+    for (int u = 0; u < side; ++u) {
+      const float2* hrow = Ht + (tyl - u + side - 1) * hw + kLagCells * txg + side - 1;
+      float2 h0 = hrow[0], h1 = hrow[1], h2 = hrow[2], h3 = hrow[3];
       for (int v = 0; v < side; ++v) {
-        const float2 h = Ht[(tyl - u + side - 1) * ht + (txl - v + side - 1)], w = Xt[u * side + v];
-        px = fmaf(w.x, h.x, fmaf(-w.y, h.y, px));
-        py = fmaf(w.x, h.y, fmaf(w.y, h.x, py));
+        const float2 w = Xt[u * side + v];
+        px[0] = fmaf(w.x, h0.x, fmaf(-w.y, h0.y, px[0]));
+        py[0] = fmaf(w.x, h0.y, fmaf(w.y, h0.x, py[0]));
+        px[1] = fmaf(w.x, h1.x, fmaf(-w.y, h1.y, px[1]));
+        py[1] = fmaf(w.x, h1.y, fmaf(w.y, h1.x, py[1]));
+        px[2] = fmaf(w.x, h2.x, fmaf(-w.y, h2.y, px[2]));
+        py[2] = fmaf(w.x, h2.y, fmaf(w.y, h2.x, py[2]));
+        px[3] = fmaf(w.x, h3.x, fmaf(-w.y, h3.y, px[3]));
+        py[3] = fmaf(w.x, h3.y, fmaf(w.y, h3.x, py[3]));
+        h3 = h2;
+        h2 = h1;
+        h1 = h0;
+        if (v + 1 < side) h0 = hrow[-(v + 1)];
       }
-    x += px;
-    y += py;
+    }
+#pragma unroll
+    for (int j = 0; j < kLagCells; ++j) {
+      x[j] += px[j];
+      y[j] += py[j];
+    }
   }
-  const int ly = ty0 + tyl, lx = tx0 + txl;
-  const bool canonical = ly < mid || (ly == mid && lx <= mid);
-  if (ly < NL && lx < NL && canonical) {
-    float2* R = a.R + static_cast<size_t>(c) * plane;
-    R[static_cast<size_t>(ly) * NL + lx] = make_float2(static_cast<float>(x), static_cast<float>(y));
+  const int ly = ty0 + tyl;
+  float2* R = a.R + static_cast<size_t>(c) * plane;
+#pragma unroll
+  for (int j = 0; j < kLagCells; ++j) {
+    const int lx = tx0 + kLagCells * txg + j;
+    const bool canonical = ly < mid || (ly == mid && lx <= mid);
+    if (ly >= NL || lx >= NL || !canonical) continue;
+    R[static_cast<size_t>(ly) * NL + lx] = make_float2(static_cast<float>(x[j]), static_cast<float>(y[j]));
     if (ly != mid || lx != mid)
-      R[static_cast<size_t>(NL - 1 - ly) * NL + (NL - 1 - lx)] = make_float2(static_cast<float>(x), static_cast<float>(-y));
+      R[static_cast<size_t>(NL - 1 - ly) * NL + (NL - 1 - lx)] =
+          make_float2(static_cast<float>(x[j]), static_cast<float>(-y[j]));
   }
 }
 
@@ -546,10 +569,12 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   if (bin_blocks > 0x7FFFFFFFu) return hipErrorInvalidValue;
   hipLaunchKernelGGL(fx_bin_kernel, dim3(static_cast<unsigned>(bin_blocks)), dim3(256), 0, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const unsigned lag_tiles = static_cast<unsigned>((a.NL + kLagTile - 1) / kLagTile);
-  const int ht = kLagTile + a.xs - 1;
-  const size_t lag_lds = sizeof(float2) * static_cast<size_t>(ht * ht + a.xs * a.xs);
-  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_tiles, lag_tiles, a.n_launch), dim3(kLagTile * kLagTile), lag_lds, st, a);
+  const unsigned lag_bx = static_cast<unsigned>((a.NL + kLagCols - 1) / kLagCols);
+  const unsigned lag_by = static_cast<unsigned>((a.NL + kLagRows - 1) / kLagRows);
+  const size_t lag_lds =
+      sizeof(float2) * static_cast<size_t>((kLagRows + a.xs - 1) * (kLagCols + a.xs - 1) + a.xs * a.xs);
+  hipLaunchKernelGGL(fx_lag_kernel, dim3(lag_bx, lag_by, a.n_launch), dim3(kLagRows * kLagCols / kLagCells), lag_lds,
+                     st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t row_lds = sizeof(float2) * static_cast<size_t>(a.N) * (kFxRowLines + 1);
   const unsigned row_blocks = static_cast<unsigned>((a.L + kFxRowLines - 1) / kFxRowLines);   // rows 0 .. L - 1
