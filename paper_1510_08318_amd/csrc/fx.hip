@@ -515,7 +515,7 @@ __global__ __launch_bounds__(256) void fx_row_kernel(FxArgs a) {
 // Z(., q) + i Z(., q + cw), and the real and imaginary parts of the result are
 // the two image columns.  The lag columns are gathered through lag_point's
 // mapping, and the scaled results written as row segments of the image.
-__device__ __forceinline__ int fx_col_width(int N) { return N < 16 ? 1 : (N / 8 < 32 ? N / 8 : 32); }
+__device__ __forceinline__ int fx_col_width(int N) { return N < 16 ? 1 : (N / 8 < 16 ? N / 8 : 16); }
 
 __global__ __launch_bounds__(256) void fx_col_kernel(FxArgs a) {
   extern __shared__ float2 fx_lds[];
@@ -580,7 +580,7 @@ hipError_t launch_fx(const FxArgs& a, bool ci4, hipStream_t st) {
   const unsigned row_blocks = static_cast<unsigned>((a.L + kFxRowLines - 1) / kFxRowLines);   // rows 0 .. L - 1
   hipLaunchKernelGGL(fx_row_kernel, dim3(row_blocks, a.n_launch), dim3(256), row_lds, st, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const int cw = a.N < 16 ? 1 : std::min(a.N / 8, 32);   // fx_col_width
+  const int cw = a.N < 16 ? 1 : std::min(a.N / 8, 16);   // fx_col_width
   const size_t col_lds = sizeof(float2) * static_cast<size_t>(a.N) * (cw + 1);
   if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fx_col_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(col_lds))) != hipSuccess)
