@@ -101,9 +101,8 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   const int a0 = ta * kC64Tile, b0 = tb * kC64Tile, c = a.c0 + cl;
   const float2* E = reinterpret_cast<const float2*>(a.E);
   double acc[2][2][4][2] = {};
-  // staging: thread = (antenna an, samples sg + kC64Rows i); each thread keeps
-  // its two antennas' gains, and the next chunk's samples load into registers
-  // while the current chunk's products run
+  // staging: thread = (antenna an, samples sg + kC64Rows i), so each thread
+  // keeps its two antennas' gains for the whole integration
   constexpr int kC64Rows = 256 / kC64Tile, kC64Per = kFxChunk / kC64Rows;
   const int an = tid % kC64Tile, sg = tid / kC64Tile;
   const int ia = a0 + an, ib = b0 + an;
@@ -111,7 +110,7 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
   const float2 ga = (a.gains && ia < na) ? a.gains[static_cast<size_t>(c) * na + ia] : one;
   const float2 gb = (a.gains && ib < na) ? a.gains[static_cast<size_t>(c) * na + ib] : one;
   float2 pa[kC64Per], pb[kC64Per];
-  auto load_chunk = [&](int64_t t0) {
+  auto load_chunk = [&](int64_t t0) {   // all of a chunk's loads in flight at once
 #pragma unroll
     for (int i = 0; i < kC64Per; ++i) {
       const int64_t ts = t0 + sg + kC64Rows * i;
@@ -123,15 +122,14 @@ __global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
       pb[i] = okb ? vb : make_float2(0.f, 0.f);
     }
   };
-  load_chunk(0);
   for (int64_t t0 = 0; t0 < a.n_time; t0 += kFxChunk) {
+    load_chunk(t0);
 #pragma unroll
     for (int i = 0; i < kC64Per; ++i) {
       ea[sg + kC64Rows * i][an] = cmul(ga, pa[i]);
       eb[sg + kC64Rows * i][an] = cmul(gb, pb[i]);
     }
     __syncthreads();
-    if (t0 + kFxChunk < a.n_time) load_chunk(t0 + kFxChunk);
     f32x4 re[2][2], im[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
