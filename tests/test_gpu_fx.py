@@ -30,14 +30,23 @@ def run_fx(torch, moff, w, extra_flags=0):
         return out.cpu().numpy()
 
 
+# 4+4-bit samples over two 64-antenna correlator tiles (the second ragged) and
+# 70 samples (one full 64-sample step and a ragged one), two table types
+FX_CASES = dict(CASES, hetero_n100_ci4_t70=lambda: synth.random_case(
+    25, 100, 64, 2, 70, [synth.random_kernel(np.random.default_rng(8), 3), synth.random_kernel(np.random.default_rng(9), 2)],
+    fmt=synth.IN_CI4, extent_m=40.0, cell_m=1.5))
+
+
 @pytest.mark.parametrize("case", ["config1", "config2_sub", "config5_sub", "hetero_n8", "hetero_n16",
-                                  "hetero_n32_ci4"])
+                                  "hetero_n32_ci4", "hetero_n128_4types", "hetero_n100_ci4_t70"])
 def test_fx_route_matches_oracle_fx(torch, moff, case):
     """Device FX image against the oracle's FX route (zero spacings left out):
-    one and two table types, 4+4-bit and complex64 samples, gains, grids 8-256,
-    antenna counts that do not fill a 32-wide correlator tile, T not a multiple
-    of the 32-sample chunk."""
-    w = CASES[case]()
+    one to four table types of different sizes (the binning and the lag grid
+    are formed for half the cells and mirrored across type pairs (p, q) and
+    (q, p)), 4+4-bit and complex64 samples, gains, grids 8-256, antenna counts
+    that leave the last 64-wide correlator tile ragged, T not a multiple of the
+    32-sample chunk or the 64-sample step."""
+    w = FX_CASES[case]()
     C = w.geom.n_chan
     got = run_fx(torch, moff, w)
     assert np.isfinite(got).all()
