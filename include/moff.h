@@ -57,7 +57,7 @@ typedef enum {
   MOFF_ERR_INVALID_ARG = 1,         /* null pointer, non-positive size, bad flag, bad kernel table */
   MOFF_ERR_GRID_NOT_POW2 = 2,       /* grid_n not a power of two in [8, 256] */
   MOFF_ERR_FOOTPRINT_OVERFLOW = 3,  /* footprints do not fit in the grid_n/2 aperture region */
-  MOFF_ERR_UNSUPPORTED = 4,         /* valid request this build does not implement (sizes, host-only plan) */
+  MOFF_ERR_UNSUPPORTED = 4,         /* valid request the library does not implement (sizes, host-only plan) */
   MOFF_ERR_NOMEM = 5,               /* host or device allocation failed */
   MOFF_ERR_HIP = 6                  /* a HIP runtime call or kernel launch failed */
 } moff_status;
