@@ -83,7 +83,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kC64Tile = 64;               // antennas per side of a tile
 constexpr int kC64Pitch = kC64Tile + 16;   // float2 per LDS row: two samples' 16 rows hit distinct banks
 
-__global__ __launch_bounds__(256) void fx_correlate_kernel(FxArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void fx_correlate_kernel(FxArgs a) {
   __shared__ float2 ea[kFxChunk][kC64Pitch], eb[kFxChunk][kC64Pitch];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wa = wave >> 1, wb = wave & 1, r16 = lane & 15, kk = lane >> 4;
