@@ -165,11 +165,16 @@ moff_status moff_plan_create(const moff_geometry* geom, int hip_device, moff_pla
 moff_status moff_plan_destroy(moff_plan plan);
 
 /*
- * Host copies of the plan's placement results. Any output may be NULL.
- *   cells        : int32 [n_ant][2] = (ix0_a, iy0_a) lower-left footprint cell
+ * Host copies of the plan's placement results (Sec. 3, antenna-to-grid
+ * mapping: each antenna's footprint is placed at its nearest grid cells, once
+ * per geometry).  Any output may be NULL.
+ *   cells        : int32 [n_ant][2] = (ix0_a, iy0_a) lower-left footprint cell,
+ *                  by the placement rule stated with moff_geometry
  *   cell_m       : grid spacing used, metres
  *   lm_per_pixel : float64 [n_chan], direction-cosine step lambda_c / (N cell)
+ *                  of the zero-padded transform (Sec. 3, spatial transform)
  *   grid_n       : N
+ * Valid on host-only plans too.  Errors: MOFF_ERR_INVALID_ARG for a NULL plan.
  */
 moff_status moff_plan_query(moff_plan plan, int32_t* cells, double* cell_m,
                             double* lm_per_pixel, int32_t* grid_n);
@@ -301,19 +306,38 @@ moff_status moff_image(moff_plan plan, const void* E_dev, int64_t n_time,
                        const float* gains_dev, float* image_dev, void* hip_stream);
 
 /*
- * Streaming form: add the frames of E to running sums.
+ * Streaming form of the squaring and time averaging (Sec. 3, squaring at every
+ * time stamp and accumulation over the integration): add the frames of E to
+ * running sums.
  *   S_dev : float32 [n_chan][N][N], S += sum_t |Y|^2
  *   A_dev : float64 [n_chan][n_ktypes], A += sum_t sum_{a of type p} |e|^2
- * accumulate(E1) then accumulate(E2) equals accumulate(E1 ++ E2) up to rounding.
+ *           (the self power that moff_finalize removes, Sec. 4.2)
+ * E_dev, n_time, gains_dev as for moff_image.  accumulate(E1) then
+ * accumulate(E2) equals accumulate(E1 ++ E2) up to rounding.  Within one call
+ * |Y|^2 is summed in float32 over blocks of at most 128 samples per pixel and
+ * the blocks in float64, so one call adds at most about 128 units of float32
+ * rounding relative to the summed power; each call then rounds S once more,
+ * so a caller streaming a long integration in many short calls adds one unit
+ * per call (keep S in float64 on the caller's side, or make fewer, longer
+ * calls, when that matters).
+ * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
+ * MOFF_ERR_UNSUPPORTED for a host-only plan or n_time * n_chan >= 2^31.
  */
 moff_status moff_accumulate(moff_plan plan, const void* E_dev, int64_t n_time,
                             const float* gains_dev, float* S_dev, double* A_dev,
                             void* hip_stream);
 
 /*
+ * Self-power removal and averaging of streamed sums (Sec. 4.2: each antenna's
+ * own power response, A[:, p] times P_p, is subtracted; Sec. 5,
+ * eq. wt-dirty-image-EPIC for the pair normalisation):
  * image = (S - sum_p A[:, p] P_p) / n_time_total (times 1/(n_ant(n_ant-1)) with
- * MOFF_NORM_PAIRS; without the subtraction under MOFF_AUTOCORR_NONE).
- * S_dev, A_dev as produced by moff_accumulate; image_dev float32 [n_chan][N][N].
+ * MOFF_NORM_PAIRS; without the subtraction under MOFF_AUTOCORR_NONE; the
+ * uv-plane rule under MOFF_AUTOCORR_UV).
+ * S_dev, A_dev as produced by moff_accumulate; image_dev float32 [n_chan][N][N],
+ * 16-byte aligned, overwritten.  n_time_total is any count >= 1 (it only scales).
+ * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or
+ * n_time_total < 1; MOFF_ERR_UNSUPPORTED for a host-only plan.
  */
 moff_status moff_finalize(moff_plan plan, const float* S_dev, const double* A_dev,
                           int64_t n_time_total, float* image_dev, void* hip_stream);
@@ -376,7 +400,11 @@ moff_status moff_image_staged(moff_plan plan, const void* E_dev, int64_t n_time,
  * The zero-spacing (a == b) terms are kept under MOFF_AUTOCORR_NONE and left
  * out otherwise, which is the exact self-power removal: the result then equals
  * moff_image's default image to rounding.  MOFF_AUTOCORR_UV and the
- * MOFF_MFMA_* flags do not apply here (float32 products, float64 sums).
+ * MOFF_MFMA_* flags do not apply here.  Arithmetic: 4+4-bit cross-products
+ * are summed exactly in int32; complex64 cross-products are summed in float32
+ * over chunks of 32 samples on the matrix cores and in float64 across chunks;
+ * each pair's lag response is summed in float32, and binning, pair
+ * combination and the transform's sums are float64.
  * MOFF_NORM_PAIRS scales as for moff_image.
  * Cost: O(n_chan (n_time n_ant^2 + n_ant^2 + N^2 log N)) work.  Channels run in
  * chunks whose workspace, 8 (n_ant^2 + (n_types^2 + 1) (2L - 1)^2 + (2L - 1) N)

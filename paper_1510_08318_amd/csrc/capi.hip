@@ -255,7 +255,8 @@ moff::MfmaArgs mfma_args(moff_plan p, const void* E, int64_t n_time, const float
 // One launch of the plan's fused kernel (float32 FFT or reduced-precision MFMA
 // transform) writing `out` / `outA` in epilogue `mode`.
 hipError_t launch_fused_kernel(moff_plan p, const LaunchConfig& lc, const void* E, int64_t n_time,
-                               const float* gains, float* out, double* outA, int mode, hipStream_t st) {
+                               const float* gains, float* out, double* outA, int mode, double* run64,
+                               hipStream_t st) {
   const HostPlan& hp = p->hp;
   const bool ci4 = hp.flags & MOFF_IN_CI4;
   if (is_mfma(hp)) {
@@ -273,19 +274,51 @@ hipError_t launch_fused_kernel(moff_plan p, const LaunchConfig& lc, const void* 
   a.out = out;
   a.outA = outA;
   a.mode = mode;
+  a.acc64 = run64;
   return moff::launch_fused(a, hp.N, lc.variant, ci4, lc.grid, st);
 }
 
+// Scratch a fused call needs: per-slice partial sums (more than one slice) and
+// the float64 running sums of blocked accumulation (a float32-path slice longer
+// than kBlockFrames samples).
+struct FusedScratch {
+  size_t s_bytes, a_bytes, run_bytes;
+  size_t total() const { return s_bytes + a_bytes + run_bytes; }
+};
+
+FusedScratch fused_scratch(const HostPlan& hp, const LaunchConfig& lc, int64_t n_time) {
+  const size_t pixels = static_cast<size_t>(hp.N) * hp.N * hp.n_chan * lc.slices;
+  FusedScratch f{};
+  if (lc.slices > 1) {
+    f.s_bytes = sizeof(float) * pixels;
+    f.a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * lc.slices;
+  }
+  const int64_t longest = (n_time + lc.slices - 1) / lc.slices;
+  if (!is_mfma(hp) && longest > moff::kBlockFrames) f.run_bytes = sizeof(double) * pixels;
+  return f;
+}
+
+// One fused call in configuration lc.  Its scratch comes from `scratch`
+// (at least fused_scratch(...).total() bytes, 256-byte aligned) or, when that
+// is null, from the plan's workspace, grown on demand.
 moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, int64_t n_time, const float* gains,
-                          float* out, double* outA, bool final_image, hipStream_t st) {
+                          float* out, double* outA, bool final_image, hipStream_t st, void* scratch = nullptr) {
   const HostPlan& hp = p->hp;
   if (footprint(p, lc.variant).lds > size_t(159) * 1024) return MOFF_ERR_UNSUPPORTED;
   const double scale = image_scale(hp, n_time);
   const int subtract = (hp.flags & MOFF_AUTOCORR_NONE) ? 0 : 1;
+  const FusedScratch fs = fused_scratch(hp, lc, n_time);
+  char* ws = static_cast<char*>(scratch);
+  if (!ws && fs.total() > 0) {
+    moff_status ms = ensure_workspace(p, fs.total());
+    if (ms != MOFF_OK) return ms;
+    ws = static_cast<char*>(p->d_ws);
+  }
+  double* run64 = fs.run_bytes ? reinterpret_cast<double*>(ws + fs.s_bytes + fs.a_bytes) : nullptr;
   if (lc.slices == 1) {
     if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
     hipError_t e = launch_fused_kernel(p, lc, E, n_time, gains, out, outA,
-                                       final_image ? moff::kModeFinal : moff::kModeAccum, st);
+                                       final_image ? moff::kModeFinal : moff::kModeAccum, run64, st);
     if (e != hipSuccess) return MOFF_ERR_HIP;
     if (p->timing) {
       if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -293,15 +326,10 @@ moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, in
     }
     return MOFF_OK;
   }
-  const size_t npix = static_cast<size_t>(hp.N) * hp.N;
-  const size_t s_bytes = sizeof(float) * npix * hp.n_chan * lc.slices;
-  const size_t a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * lc.slices;
-  moff_status ms = ensure_workspace(p, s_bytes + a_bytes);
-  if (ms != MOFF_OK) return ms;
-  float* S_part = static_cast<float*>(p->d_ws);
-  double* A_part = reinterpret_cast<double*>(static_cast<char*>(p->d_ws) + s_bytes);
+  float* S_part = reinterpret_cast<float*>(ws);
+  double* A_part = reinterpret_cast<double*>(ws + fs.s_bytes);
   if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-  hipError_t e = launch_fused_kernel(p, lc, E, n_time, gains, S_part, A_part, moff::kModePartial, st);
+  hipError_t e = launch_fused_kernel(p, lc, E, n_time, gains, S_part, A_part, moff::kModePartial, run64, st);
   if (e != hipSuccess) return MOFF_ERR_HIP;
   if (p->timing) {
     if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -895,9 +923,11 @@ moff_status moff_accumulate(moff_plan p, const void* E, int64_t n_time, const fl
 
 moff_status moff_finalize(moff_plan p, const float* S, const double* A, int64_t n_time_total, float* image,
                           void* stream) {
-  moff_status s = check_compute(p, n_time_total);
-  if (s != MOFF_OK) return s;
-  if (!S || !A || !image) return MOFF_ERR_INVALID_ARG;
+  // Only scales and subtracts per pixel: no per-sample indexing, so no limit on
+  // n_time_total beyond being a positive count.
+  if (!p) return MOFF_ERR_INVALID_ARG;
+  if (p->device < 0) return MOFF_ERR_UNSUPPORTED;
+  if (n_time_total < 1 || !S || !A || !image || !aligned16(S) || !aligned16(image)) return MOFF_ERR_INVALID_ARG;
   DeviceGuard guard(p->device);
   if (!guard.ok()) return MOFF_ERR_HIP;
   const HostPlan& hp = p->hp;

@@ -30,7 +30,18 @@ struct FusedArgs {
   double scale;
   int subtract;
   int mode;                    // kModePartial / kModeAccum / kModeFinal
+  // Blocked accumulation: a workgroup whose slice holds more than kBlockFrames
+  // samples adds its float32 register sums into float64 running sums every
+  // kBlockFrames samples (acc64: N^2 doubles per (column class, channel,
+  // slice) work item, private to the item's workgroup).  Null when no slice
+  // is that long.
+  double* acc64;
 };
+
+// Samples summed in float32 registers before they are added to a float64
+// running sum: the float32 part then contributes at most (kBlockFrames - 1)
+// units of rounding relative to the accumulated power of a pixel.
+constexpr int kBlockFrames = 128;
 
 struct ReduceArgs {
   const float* S_part;

@@ -10,8 +10,10 @@
 //   grid_kernel, self_power_kernel, fft2_kernel, detect_kernel, finalize_kernel
 //                     the same steps one at a time through HBM (staged path).
 //
-// No global atomics anywhere: every output element has exactly one writer and
-// every sum is taken in a fixed order, so results are bitwise reproducible.
+// Every output element has exactly one writer and every sum is taken in a
+// fixed order, so results are bitwise reproducible.  The only global atomics
+// are the no-return float64 adds of blocked accumulation, each into a running
+// sum that one lane alone writes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -80,8 +82,17 @@ constexpr int gather_batch() {
 // fused kernel
 // ---------------------------------------------------------------------------
 
+// Waves per SIMD the fused kernel's registers are sized for: at N = 128,
+// shape variant 0 fits four (128 registers), which several workgroups per CU
+// need to hide one another's gather latency.
+template <int N, int V>
+constexpr int fused_waves_per_simd() {
+  return (N == 128 && V == 0) ? 4 : 1;
+}
+
 template <int N, int V, bool CI4>
-__global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<N, V>())))
+void fused_kernel(FusedArgs a) {
   using C = FT<N, V>;
   constexpr int NT = C::NT;
   extern __shared__ float2 lds[];
@@ -129,6 +140,12 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
 #pragma unroll
     for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
     double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+    // float64 running sums of this workgroup's pixels (blocked accumulation),
+    // laid out [item][acc index][lane]: a uniform base per accumulator index
+    // plus the lane's offset, so no per-lane address stays live in the loop
+    double* run64 = a.acc64 ? a.acc64 + static_cast<size_t>(item) * C::NACC * NT : nullptr;
+    bool flushed = false;
+    int in_block = 0;
 
     __syncthreads();
     for (int64_t t = t0; t < t1; ++t) {
@@ -148,6 +165,29 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
       row_stage<N, V>(G, twr, fin);
       __syncthreads();
       col_stage<N, V>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
+      // blocked accumulation: fold the block's float32 sums into float64
+      if (a.acc64 && ++in_block == kBlockFrames && t + 1 < t1) {   // uniform branch
+        // An opaque zero defined here keeps the compiler from hoisting the
+        // flush's addresses out of the time loop (they would hold 2 NACC
+        // registers for the whole loop).
+        int zero;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+        double* base = run64 + zero + tid;
+        // The first block is stored, later ones added (no-return float64 adds:
+        // each address has this one lane as its only writer, so the order of
+        // additions is fixed).
+        if (!flushed) {
+#pragma unroll
+          for (int idx = 0; idx < C::NACC; ++idx) base[idx * NT] = static_cast<double>(acc[idx]);
+        } else {
+#pragma unroll
+          for (int idx = 0; idx < C::NACC; ++idx) unsafeAtomicAdd(base + idx * NT, static_cast<double>(acc[idx]));
+        }
+#pragma unroll
+        for (int idx = 0; idx < C::NACC; ++idx) acc[idx] = 0.f;
+        flushed = true;
+        in_block = 0;
+      }
     }
 
     block_sum4<NT>(pw, Atot);
@@ -160,17 +200,22 @@ __global__ __launch_bounds__((FT<N, V>::NT)) void fused_kernel(FusedArgs a) {
       const int q = C::SX * col + w;
       const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
       const size_t pix = static_cast<size_t>(pr) * N + pq;
+      // (read at device scope: the adds were performed in L2)
+      const double sum = static_cast<double>(acc[idx]) +
+                         (flushed ? __hip_atomic_load(run64 + idx * NT + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                  : 0.0);
       if (a.mode == kModePartial) {
         // Partial sums are stored class-major within each image row (this
         // class's M columns contiguous, pq = SX * pcol + w), so that every
         // 128-byte line has one writer; the reduction reads them back in
         // pixel order.
         const size_t ppix = static_cast<size_t>(pr) * N + static_cast<size_t>(w) * C::M + ((col + C::M / 2) & (C::M - 1));
-        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + ppix] = acc[idx];
+        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + ppix] = static_cast<float>(sum);
       } else if (a.mode == kModeAccum) {
-        a.out[static_cast<size_t>(c) * img_stride + pix] += acc[idx];
+        float& o = a.out[static_cast<size_t>(c) * img_stride + pix];
+        o = static_cast<float>(static_cast<double>(o) + sum);
       } else {
-        double v = acc[idx];
+        double v = sum;
         if (a.subtract)
           for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
         a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);

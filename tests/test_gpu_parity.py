@@ -175,6 +175,56 @@ def test_accumulate_split_equals_whole(torch, moff):
     assert_image_close(whole, ref, pbar, label="whole")
 
 
+def test_long_integration_one_slice(torch, moff):
+    """A long integration in one time slice (Sec. 3 time averaging): 100,000
+    samples summed by a single workgroup per column class.  The float32
+    register sums are folded into float64 every 128 samples, so the
+    accumulation adds well under 1e-6 here; one float32 sum over all samples
+    would add about 9e-6 on this input (measured by a CPU simulation of that
+    summation order).  The oracle runs over time chunks and sums S and A,
+    which are linear in the frames."""
+    T, chunk = 100_000, 5_000
+    w = synth.make_config(1, n_time=T)
+    print(f"long integration: config 1, T = {T}, one slice", flush=True)
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        p.set_config(0, 1)
+        assert p.config(T)["slices"] == 1
+        got = p.image(to_dev(torch, w.E))
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()[0].astype(np.float64)
+    P = oracle.plan(w.geom)
+    S, A = 0.0, 0.0
+    for t0 in range(0, T, chunk):
+        _, parts = oracle.moff_channel(w.geom, w.E[t0:t0 + chunk], w.gains, 0, P, keep=True)
+        S, A = S + parts["S"], A + parts["A"]
+    ref = (S - np.tensordot(A, parts["P"], axes=1)) / T
+    pbar = S / T
+    e_inf = np.abs(got - ref).max() / np.abs(pbar).max()
+    e_2 = np.linalg.norm(got - ref) / np.linalg.norm(pbar)
+    assert e_inf <= TOL and e_2 <= TOL, (e_inf, e_2)
+    assert e_inf <= 2e-6, f"accumulation error {e_inf:.3g}: float32 sums are not blocked"
+
+
+def test_finalize_long_integration_count(torch, moff):
+    """moff_finalize only scales and subtracts: a total sample count beyond
+    2^31 / n_chan (a long streamed integration) is accepted and gives
+    (S - sum_p A_p P_p) / T from the streamed sums."""
+    w = synth.make_config(5, n_time=3, n_chan=2)
+    T_total = (1 << 31) // w.geom.n_chan + 1
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        S = torch.zeros((2, 256, 256), dtype=torch.float32, device="cuda:0")
+        A = torch.zeros((2, 2), dtype=torch.float64, device="cuda:0")
+        p.accumulate(E, S, A, gains=to_dev(torch, w.gains))
+        img = p.finalize(S, A, T_total)
+        torch.cuda.synchronize()
+        S, A, img = S.cpu().numpy().astype(np.float64), A.cpu().numpy(), img.cpu().numpy()
+        Pp = np.stack([p.power_pattern(k) for k in range(2)])
+    ref = (S - np.einsum("cp,pij->cij", A, Pp)) / T_total
+    scale = np.abs(S).max() / T_total
+    assert np.abs(img - ref).max() <= 1e-6 * scale
+
+
 @pytest.mark.parametrize("flag", ["autocorr_none", "norm_pairs"])
 def test_flags(torch, moff, flag):
     w = synth.make_config(1, n_time=16)
