@@ -306,6 +306,29 @@ moff_status moff_image(moff_plan plan, const void* E_dev, int64_t n_time,
                        const float* gains_dev, float* image_dev, void* hip_stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream or graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): moff_image
+ * with no allocation.  Same arguments, output and errors as moff_image; the
+ * result equals moff_image's up to float32 rounding order (bitwise when both
+ * use the same launch configuration).  Its scratch -- the per-slice partial
+ * sums and float64 running sums of the fused call -- lives in one fixed
+ * MOFF_NOALLOC_SCRATCH_BYTES device array per GPU, taken when the first plan
+ * on that GPU is created and held until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocating call.  The plan's launch
+ * configuration is used with fewer time slices when its scratch would not fit.
+ * Every call on one GPU (from any plan) shares that array and overwrites it
+ * without clearing (nothing in it needs to start at zero), so calls that
+ * overlap on one GPU race: serialise them on one stream.
+ * Errors as moff_image, plus MOFF_ERR_UNSUPPORTED when even one time slice
+ * needs more scratch than MOFF_NOALLOC_SCRATCH_BYTES (more than 128 samples
+ * with 8 n_chan N^2 bytes above it), under MOFF_AUTOCORR_UV, or on a device
+ * ordinal of 64 or more.
+ */
+#define MOFF_NOALLOC_SCRATCH_BYTES (128u << 20)
+moff_status moff_image_noalloc(moff_plan plan, const void* E_dev, int64_t n_time,
+                               const float* gains_dev, float* image_dev, void* hip_stream);
+
+/*
  * Streaming form of the squaring and time averaging (Sec. 3, squaring at every
  * time stamp and accumulation over the integration): add the frames of E to
  * running sums.

@@ -211,6 +211,17 @@ class Plan:
         _lib.moff_image(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
         return out
 
+    def image_noalloc(self, E, gains=None, out=None, stream=None):
+        """As image(), with every scratch buffer in the library's fixed per-GPU
+        array (moff_image_noalloc); `out` must be given when nothing may be allocated."""
+        torch = self._torch()
+        pE, T = self._E(E)
+        if out is None:
+            out = self._new((self.n_chan, self.N, self.N), torch.float32)
+        po = self._dev(out, "out", (self.n_chan, self.N, self.N), torch.float32)
+        _lib.moff_image_noalloc(self.handle, pE, T, self._gains(gains), po, self._stream(stream))
+        return out
+
     def accumulate(self, E, S, A, gains=None, stream=None):
         torch = self._torch()
         pE, T = self._E(E)

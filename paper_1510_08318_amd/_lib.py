@@ -68,6 +68,8 @@ SIGNATURES = {
     "moff_plan_last_kernel_ms": (ctypes.c_int, [ctypes.c_void_p, c_f64p]),
     "moff_image": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "moff_image_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
     "moff_accumulate": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "moff_finalize": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -195,6 +197,10 @@ def moff_plan_last_kernel_ms(plan):
 
 def moff_image(plan, E, n_time, gains, image, stream):
     _call("moff_image", plan, E, n_time, gains, image, stream)
+
+
+def moff_image_noalloc(plan, E, n_time, gains, image, stream):
+    _call("moff_image_noalloc", plan, E, n_time, gains, image, stream)
 
 
 def moff_accumulate(plan, E, n_time, gains, S, A, stream):

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -59,6 +60,32 @@ struct moff_plan_s {
 };
 
 namespace {
+
+// Fixed device scratch of moff_image_noalloc (for callers that cannot
+// allocate): the per-slice partial sums and float64 running sums of its fused
+// call.  Each GPU the library runs on holds its own copy until the process
+// ends.  Host code never passes this name to a kernel: it is a host-side
+// stand-in, and the device address of each GPU's copy comes from
+// hipGetSymbolAddress (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[MOFF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current: looked up
+// once per device (at plan creation) and kept.
+moff_status noalloc_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return MOFF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MOFF_ERR_HIP;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MOFF_OK;
+}
 
 // Run f with the plan's device current, restoring the caller's device after.
 class DeviceGuard {
@@ -553,6 +580,10 @@ moff_status plan_create_body(const moff_geometry* geom, int hip_device, moff_pla
     }
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess) p->cu_count = prop.multiProcessorCount;
+    if (hip_device < kMaxDevices) {
+      void* sp = nullptr;
+      up(noalloc_scratch(hip_device, &sp));
+    }
     up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
     up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
     up(upload(&p->d_Pn, hp.Pn.data(), sizeof(double) * hp.Pn.size()));
@@ -909,6 +940,33 @@ moff_status moff_image(moff_plan p, const void* E, int64_t n_time, const float* 
   s = fused_run(p, E, n_time, gains, S, A, false, st);
   if (s != MOFF_OK) return s;
   return uv_finalize(p, S, n_time, image, st);
+}
+
+moff_status moff_image_noalloc(moff_plan p, const void* E, int64_t n_time, const float* gains, float* image,
+                               void* stream) {
+  moff_status s = check_compute(p, n_time);
+  if (s != MOFF_OK) return s;
+  if (!E || !image || !aligned16(image) || (gains && !aligned16(gains))) return MOFF_ERR_INVALID_ARG;
+  const HostPlan& hp = p->hp;
+  if (uv_rule(hp)) return MOFF_ERR_UNSUPPORTED;
+  DeviceGuard guard(p->device);
+  if (!guard.ok()) return MOFF_ERR_HIP;
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (p->device < kMaxDevices) ptr = g_scratch_ptr[p->device];
+  }
+  if (!ptr) return MOFF_ERR_UNSUPPORTED;   // set at plan creation; absent only beyond kMaxDevices
+  // The plan's launch configuration, with fewer time slices while its scratch
+  // would not fit (results differ only in float32 rounding order).
+  LaunchConfig lc = launch_config(p, n_time);
+  const int per_slice = lc.grid / lc.slices;
+  while (lc.slices > 1 && fused_scratch(hp, lc, n_time).total() > MOFF_NOALLOC_SCRATCH_BYTES) {
+    --lc.slices;
+    lc.grid = per_slice * lc.slices;
+  }
+  if (fused_scratch(hp, lc, n_time).total() > MOFF_NOALLOC_SCRATCH_BYTES) return MOFF_ERR_UNSUPPORTED;
+  return fused_run_cfg(p, lc, E, n_time, gains, image, nullptr, true, static_cast<hipStream_t>(stream), ptr);
 }
 
 moff_status moff_accumulate(moff_plan p, const void* E, int64_t n_time, const float* gains, float* S, double* A,
