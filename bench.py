@@ -1,24 +1,31 @@
 """Throughput of the fused MOFF imaging path on one MI355X.
 
-A step images one integration of the LWA-shaped workload: 256 antennas in a
-100 m disc, 3x3 dipole illumination, 128 channels over 40-80 MHz, 1000 time
-samples of 4+4-bit complex input, 128 x 128 padded grid: 128,000 frames per step
-(gridding, padded 2-D FFT, squaring, accumulation and self-power removal for every
-(time, channel) frame).  Inputs are synthetic, seeded, and resident in HBM before
-timing starts.
+A step images one integration of the HERA-shaped workload: 350 dishes on a
+hexagonal grid of 14.6 m pitch, 7x7 Airy-like illumination tables, 1024
+channels over 100-200 MHz, 256 time samples of 4+4-bit complex input, 256 x 256
+padded grid: 262,144 frames per step (gridding, padded 2-D FFT, squaring,
+accumulation and self-power removal for every (time, channel) frame), all
+channels in one autotuned launch.  Inputs are synthetic, seeded, and resident
+in HBM before timing starts.  The line also carries, in `extra`, the time of
+the fused gain adjoint (moff_gain_vjp) on the calibration workload (1024
+antennas, 256 channels, 128 samples, 256 grid, complex64 with gains).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--staged]
                     [--config 1..5] [--precision f32|f16|bf16] [--adjoint] [--fx]
+                    [--adjoint-config 0..5] [--launch V,S]
 
+--config picks another workload (2: LWA-shaped, 128 grid; 5: calibration).
 --precision f16 / bf16 runs the reduced-precision path (16-bit gridded fields,
 dense DFT on the matrix cores, float32 accumulation; grid 64 or 128) and also
 times the float32 path on the same input; the CPU-baseline leg's oracle images
 then give the per-image error of both.  The CPU leg also times the oracle on
 one core and the paper's own CPU form of the pipeline (sparse gridding matrix
-+ scipy.fft, float64 and float32, all cores and one), in `extra`.  --fx also times the visibility route
-(moff_image_fx: correlate all antenna pairs, grid the visibilities, one
-transform per channel) on the same input, the method MOFF is compared with in
-the paper.  Prints one JSON line.
++ scipy.fft, float64 and float32, all cores and one), in `extra`.  --fx also
+times the visibility route (moff_image_fx: correlate all antenna pairs, grid
+the visibilities, one transform per channel) on the same input, the method
+MOFF is compared with in the paper.  --adjoint times the gain adjoint on the
+benchmark workload itself; --adjoint-config 0 skips the calibration-workload
+adjoint.  Prints one JSON line.
 """
 import argparse
 import json
@@ -132,6 +139,71 @@ def measured_traffic(config, prec, launch, default_grid):
     if kib is None:
         return None
     return int(round((kib[0] * FETCH_SCALE + kib[1] * WRITE_SCALE) * 1024))
+
+
+def adjoint_frame_flops(N, nnz):
+    """Algorithmic work per frame of the gain adjoint: the forward transform and
+    its adjoint (2 x 5 N^2 log2 N^2, Sec. 6.1 convention), gridding and
+    degridding (8 flops per tap each) and the pixel-wise product R * Y
+    (2 flops per pixel)."""
+    return 2 * 5 * N * N * math.log2(N * N) + 16 * nnz + 2 * N * N
+
+
+def time_adjoint_workload(cfg, steps):
+    """Tuned fused gain adjoint (moff_gain_vjp) on workload `cfg`: ms per call
+    between events on the current stream, the fused kernel's own duration (plan
+    events) and its algorithmic rate."""
+    import numpy as np
+    import torch
+    import paper_1510_08318_amd as moff
+    import synth
+    w = synth.make_config(cfg)
+    T, C, Na = w.E.shape
+    N = w.geom.grid_n
+    dev = "cuda:0"
+    E = torch.from_numpy(w.E).to(dev)
+    g = torch.from_numpy(w.gains).to(dev) if w.gains is not None else \
+        torch.ones((C, Na), dtype=torch.complex64, device=dev)
+    plan = moff.Plan.from_geometry(w.geom, device=0)
+    plan.autotune(E, g)                       # image launch and the adjoint's register budget
+    R = torch.randn((C, N, N), dtype=torch.float32, device=dev, generator=torch.Generator(dev).manual_seed(7))
+    grad = torch.empty((C, Na), dtype=torch.complex64, device=dev)
+    plan.gain_vjp(E, g, R, out=grad)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    reps = max(3, min(steps, 10))
+    a0 = torch.cuda.Event(enable_timing=True)
+    a1 = torch.cuda.Event(enable_timing=True)
+    a0.record(stream)
+    for _ in range(reps):
+        plan.gain_vjp(E, g, R, out=grad)
+    a1.record(stream)
+    torch.cuda.synchronize()
+    ms = a0.elapsed_time(a1) / reps
+    plan.set_timing(True)
+    kms = []
+    for _ in range(reps):
+        plan.gain_vjp(E, g, R, out=grad)
+        kms.append(plan.last_kernel_ms())
+    plan.set_timing(False)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean(kms))
+    nnz = int(sum(w.geom.ktype_k[t] ** 2 for t in w.geom.ant_ktype))
+    flops = adjoint_frame_flops(N, nnz) * T * C
+    out = {"workload": workload_name(cfg), "ms": round(ms, 4), "kernel_ms": round(k_ms, 4),
+           "frames_per_s": T * C / (ms / 1e3), "waves_per_simd": plan.adjoint_waves()[0],
+           "algorithmic_flops_per_frame": adjoint_frame_flops(N, nnz),
+           "achieved_tflops": flops / (k_ms / 1e3) / 1e12,
+           "frac_of_fp32_peak": flops / (k_ms / 1e3) / 1e12 / PEAK_FP32_TFLOPS}
+    plan.close()
+    del E, g, R, grad
+    torch.cuda.empty_cache()
+    return out
+
+
+def workload_name(cfg):
+    import synth
+    return synth.CONFIG_NAMES[cfg]
 
 
 def frame_flops(N, nnz):
@@ -348,13 +420,16 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="also time the staged (per-step HBM) pipeline")
     ap.add_argument("--fx", action="store_true", help="also time the visibility (FX) route on the same input")
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--grid", type=int, default=0, help="override the workload's grid size")
     ap.add_argument("--precision", choices=("f32", "f16", "bf16"), default=None,
                     help="f32: float32 FFT path; f16 / bf16: matrix-core DFT path (default: f16 for config 4)")
     ap.add_argument("--no-tune", action="store_true", help="skip the launch autotuner (heuristic configuration)")
+    ap.add_argument("--launch", default="", help="fixed launch shape 'variant,slices' instead of the autotuner")
     ap.add_argument("--adjoint", action="store_true",
                     help="also time the gain adjoint (moff_gain_vjp) on the same workload")
+    ap.add_argument("--adjoint-config", type=int, default=5,
+                    help="workload on which the fused gain adjoint is timed for `extra` (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -388,7 +463,11 @@ def main():
     frames = T * C
     stream = torch.cuda.current_stream()
 
-    ms_per_step, k_ms, launch = time_plan(plan, E, gains, out, args.steps, args.warmup, not args.no_tune)
+    if args.launch:
+        v, sl = (int(x) for x in args.launch.split(","))
+        plan.set_config(v, sl)
+    tune = not (args.no_tune or args.launch)
+    ms_per_step, k_ms, launch = time_plan(plan, E, gains, out, args.steps, args.warmup, tune)
     value = frames / (ms_per_step / 1e3)
     extra = {"fused_kernel_ms": round(k_ms, 4), "frames_per_step": frames,
              "algorithmic_flops_per_frame": frame_flops(N, nnz)}
@@ -476,6 +555,12 @@ def main():
         extra["adjoint_fused_vs_staged_max_rel_diff"] = float(
             ((grads[False] - grads[True]).abs().max() / grads[True].abs().max()).item())
 
+    if args.adjoint_config:
+        extra["adjoint_ms"] = None
+        adj = time_adjoint_workload(args.adjoint_config, args.steps)
+        extra["adjoint_ms"] = adj["ms"]
+        extra["adjoint_calibration"] = adj
+
     cpu = None
     if not args.no_cpu:
         cpu, ref_images = cpu_baseline(w)
@@ -488,7 +573,7 @@ def main():
         del ref_images
 
     line = {
-        "metric": "MOFF frames/s (grid x channels per time sample)",
+        "metric": "MOFF frames/s (grid\u00d7channels per time sample) + % HBM roofline; adjoint ms",
         "value": value,
         "unit": "frames/s",
         "n_gpus": 1,
