@@ -320,7 +320,7 @@ moff_status moff_image(moff_plan plan, const void* E_dev, int64_t n_time,
  * without clearing (nothing in it needs to start at zero), so calls that
  * overlap on one GPU race: serialise them on one stream.
  * Errors as moff_image, plus MOFF_ERR_UNSUPPORTED when even one time slice
- * needs more scratch than MOFF_NOALLOC_SCRATCH_BYTES (more than 128 samples
+ * needs more scratch than MOFF_NOALLOC_SCRATCH_BYTES (more than 256 samples
  * with 8 n_chan N^2 bytes above it), under MOFF_AUTOCORR_UV, or on a device
  * ordinal of 64 or more.
  */
@@ -337,12 +337,13 @@ moff_status moff_image_noalloc(moff_plan plan, const void* E_dev, int64_t n_time
  *           (the self power that moff_finalize removes, Sec. 4.2)
  * E_dev, n_time, gains_dev as for moff_image.  accumulate(E1) then
  * accumulate(E2) equals accumulate(E1 ++ E2) up to rounding.  Within one call
- * |Y|^2 is summed in float32 over blocks of at most 128 samples per pixel and
- * the blocks in float64, so one call adds at most about 128 units of float32
- * rounding relative to the summed power; each call then rounds S once more,
- * so a caller streaming a long integration in many short calls adds one unit
- * per call (keep S in float64 on the caller's side, or make fewer, longer
- * calls, when that matters).
+ * |Y|^2 is summed in float32 over blocks of at most 256 samples per pixel and
+ * the blocks in float64: one call adds at most 255 units of float32 rounding
+ * (2^-24) relative to the summed power in the worst case, about 5 units
+ * typically, however long the call; each call then rounds S once more, so a
+ * caller streaming a long integration in many short calls adds one unit per
+ * call (keep S in float64 on the caller's side, or make fewer, longer calls,
+ * when that matters).
  * Errors: MOFF_ERR_INVALID_ARG for null or misaligned pointers or n_time < 1;
  * MOFF_ERR_UNSUPPORTED for a host-only plan or n_time * n_chan >= 2^31.
  */

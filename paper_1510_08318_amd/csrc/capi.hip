@@ -22,7 +22,8 @@ struct moff_plan_s {
   HostPlan hp;
   int device = -1;
   // device tables
-  GatherEntry* d_prog[moff::kMaxVariants] = {};
+  uint4* d_prog[moff::kMaxVariants] = {};       // HostPlan::Variant::prog4
+  int* d_cell0[moff::kMaxVariants] = {};
   float2* d_weights[moff::kMaxVariants] = {};
   float2* d_tw = nullptr;
   double* d_Pp = nullptr;
@@ -122,6 +123,7 @@ void free_device(moff_plan p) {
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
     if (p->d_prog[v]) (void)hipFree(p->d_prog[v]);
+    if (p->d_cell0[v]) (void)hipFree(p->d_cell0[v]);
     if (p->d_weights[v]) (void)hipFree(p->d_weights[v]);
   }
   if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -219,6 +221,16 @@ KernelFootprint footprint(moff_plan p, int variant) {
 
 int n_variants(const HostPlan& hp) { return is_mfma(hp) ? 1 : static_cast<int>(hp.variants.size()); }
 
+// Workgroups of a fused launch with `slices` time slices.  The float32 kernel
+// places the column classes of one (channel, slice) on one XCD and pads the
+// (channel, slice) count to a multiple of 8 (moff::kXcds); padding workgroups
+// exit at once.
+int launch_grid(const HostPlan& hp, int variant, int slices) {
+  if (is_mfma(hp)) return hp.n_chan * slices;
+  const int cs = hp.n_chan * slices;
+  return hp.variants[variant].shape.SX * ((cs + moff::kXcds - 1) / moff::kXcds * moff::kXcds);
+}
+
 // Launch configuration for n_time frames: the tuned or set choice, else a
 // heuristic: shape variant 0 and enough time slices for about two rounds of
 // resident workgroups.  One work item (column class, channel, time slice) per
@@ -233,7 +245,7 @@ LaunchConfig launch_config(moff_plan p, int64_t n_time) {
   if (slices <= 0) slices = (2 * resident + per_slice - 1) / per_slice;
   slices = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>({static_cast<int64_t>(slices), n_time, 256})));
   lc.slices = slices;
-  lc.grid = per_slice * slices;
+  lc.grid = launch_grid(hp, lc.variant, slices);
   return lc;
 }
 
@@ -244,6 +256,7 @@ moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_ti
   a.E = E;
   a.gains = reinterpret_cast<const float2*>(gains);
   a.prog = p->d_prog[variant];
+  a.cell0 = p->d_cell0[variant];
   a.prog_len = V.prog_len;
   a.weights = p->d_weights[variant];
   a.n_weights = V.n_weights();
@@ -372,7 +385,6 @@ moff_status fused_run_cfg(moff_plan p, const LaunchConfig& lc, const void* E, in
   r.n_chan = hp.n_chan;
   r.n_types = hp.n_ktypes;
   r.slices = lc.slices;
-  r.sx = is_mfma(hp) ? 1 : moff::frame_shape(hp.N, lc.variant).SX;
   r.final_image = final_image ? 1 : 0;
   r.subtract = subtract;
   r.scale = scale;
@@ -467,6 +479,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.E = E;
     a.gains = reinterpret_cast<const float2*>(gains);
     a.prog = p->d_prog[0];
+    a.cell0 = p->d_cell0[0];
     a.prog_len = V.prog_len;
     a.weights = p->d_weights[0];
     a.n_weights = V.n_weights();
@@ -571,7 +584,8 @@ moff_status plan_create_body(const moff_geometry* geom, int hip_device, moff_pla
       if (s == MOFF_OK) s = r;
     };
     for (size_t v = 0; v < hp.variants.size(); ++v) {
-      up(upload(&p->d_prog[v], hp.variants[v].prog.data(), sizeof(GatherEntry) * hp.variants[v].prog.size()));
+      up(upload(&p->d_prog[v], hp.variants[v].prog4.data(), sizeof(uint32_t) * hp.variants[v].prog4.size()));
+      up(upload(&p->d_cell0[v], hp.variants[v].cell0.data(), sizeof(int32_t) * hp.variants[v].cell0.size()));
       up(upload(&p->d_weights[v], hp.variants[v].weights.data(), sizeof(float) * hp.variants[v].weights.size()));
     }
     if (hp.mfma.prec) {
@@ -960,10 +974,9 @@ moff_status moff_image_noalloc(moff_plan p, const void* E, int64_t n_time, const
   // The plan's launch configuration, with fewer time slices while its scratch
   // would not fit (results differ only in float32 rounding order).
   LaunchConfig lc = launch_config(p, n_time);
-  const int per_slice = lc.grid / lc.slices;
   while (lc.slices > 1 && fused_scratch(hp, lc, n_time).total() > MOFF_NOALLOC_SCRATCH_BYTES) {
     --lc.slices;
-    lc.grid = per_slice * lc.slices;
+    lc.grid = launch_grid(hp, lc.variant, lc.slices);
   }
   if (fused_scratch(hp, lc, n_time).total() > MOFF_NOALLOC_SCRATCH_BYTES) return MOFF_ERR_UNSUPPORTED;
   return fused_run_cfg(p, lc, E, n_time, gains, image, nullptr, true, static_cast<hipStream_t>(stream), ptr);

@@ -50,12 +50,9 @@ struct Root16 {
   }
 };
 
-// a * exp(+2 pi i K / R), R dividing 16.
-template <int R, int K>
-__device__ __forceinline__ float2 rot(float2 a) {
-  static_assert(16 % R == 0, "rotation order must divide 16");
-  constexpr int k = ((K % R) + R) % R;
-  constexpr int k16 = k * (16 / R);
+// a * exp(+2 pi i K16 / 16), 0 <= K16 < 16.
+template <int k16>
+__device__ __forceinline__ float2 rot16(float2 a) {
   if constexpr (k16 == 0) {
     return a;
   } else if constexpr (k16 == 4) {
@@ -75,6 +72,37 @@ __device__ __forceinline__ float2 rot(float2 a) {
   } else {
     constexpr float c = Root16::re(k16), s = Root16::im(k16);
     return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  }
+}
+
+// cos / sin of 2 pi k / 32 (k < 32), exact decimal expansions of the
+// thirty-second roots of unity; sin(2 pi k / 32) = cos(2 pi (k - 8) / 32).
+struct Root32 {
+  static constexpr float c1 = 0.98078528040323044913f;  // cos(pi / 16)
+  static constexpr float s1 = 0.19509032201612826785f;  // sin(pi / 16)
+  static constexpr float c3 = 0.83146961230254523708f;  // cos(3 pi / 16)
+  static constexpr float s3 = 0.55557023301960222474f;  // sin(3 pi / 16)
+  static constexpr float re(int k) {
+    constexpr float t[32] = {1.f,       c1,  Root16::c1,  c3,  Root16::r2,  s3,  Root16::s1,  s1,
+                             0.f,       -s1, -Root16::s1, -s3, -Root16::r2, -c3, -Root16::c1, -c1,
+                             -1.f,      -c1, -Root16::c1, -c3, -Root16::r2, -s3, -Root16::s1, -s1,
+                             0.f,       s1,  Root16::s1,  s3,  Root16::r2,  c3,  Root16::c1,  c1};
+    return t[k & 31];
+  }
+  static constexpr float im(int k) { return re((k - 8) & 31); }
+};
+
+// a * exp(+2 pi i K / R), R dividing 32.
+template <int R, int K>
+__device__ __forceinline__ float2 rot(float2 a) {
+  static_assert(32 % R == 0, "rotation order must divide 32");
+  constexpr int k = ((K % R) + R) % R;
+  constexpr int k32 = k * (32 / R);
+  if constexpr (k32 % 2 != 0) {     // an odd thirty-second root
+    constexpr float c = Root32::re(k32), s = Root32::im(k32);
+    return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+  } else {
+    return rot16<k32 / 2>(a);
   }
 }
 

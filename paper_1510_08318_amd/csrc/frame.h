@@ -148,6 +148,58 @@ __device__ __forceinline__ void row_stage(float2* G, const float2* twr, const fl
   }
 }
 
+// Row stage of column class W known at compile time: the same transform as
+// row_stage, with the fold factor of input n1, w_N^{QR n1 W} =
+// exp(+2 pi i n1 W / (N / QR)), applied as a constant rotation (none for
+// class 0, whose per-lane fold twiddle is 1 as well).
+template <int N, int V, int W>
+__device__ __forceinline__ void row_stage_w(float2* G, const float2* twr) {
+  using C = FT<N, V>;
+  constexpr bool kFold = C::SX > 1 && W != 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / C::RPW;
+#pragma unroll
+  for (int rs = 0; rs < C::RSTEPS; ++rs) {
+    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    if (C::RGUARD && row >= C::L) continue;
+    float2* R = G + row * C::P;
+    float2 x[C::JAR][C::PR];
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja)
+      static_for<0, C::PRNZ>([&](auto nc) {
+        constexpr int n1 = decltype(nc)::value;
+        x[ja][n1] = R[sub + C::LPR * ja + C::QR * n1];
+        if constexpr (kFold) x[ja][n1] = rot<N / C::QR, n1 * W>(x[ja][n1]);
+      });
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja) {
+      const int n2 = sub + C::LPR * ja;
+      dft_pruned<C::PR, C::PRNZ>(x[ja]);
+#pragma unroll
+      for (int q1 = (kFold ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twr[q1 * C::QR + n2]);
+    }
+    wave_sync();
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja)
+#pragma unroll
+      for (int q1 = 0; q1 < C::PR; ++q1) R[sub + C::LPR * ja + q1 * C::QR] = x[ja][q1];
+    wave_sync();
+    float2 y[C::JBR][C::QR];
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb)
+#pragma unroll
+      for (int k = 0; k < C::QR; ++k) y[jb][k] = R[(sub + C::LPR * jb) * C::QR + k];
+    wave_sync();
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb) {
+      Dft<C::QR>::run(y[jb]);
+#pragma unroll
+      for (int q2 = 0; q2 < C::QR; ++q2) R[sub + C::LPR * jb + C::PR * q2] = y[jb][q2];
+    }
+    wave_sync();
+  }
+}
+
 // Column stage: Y[r][m] = sum_{iy < L} Z[iy][m] w_N^{iy r} for r < N, in place,
 // handing every output to sink(acc_index, r, m, value) with acc_index in [0, NACC).
 // Pass A (job n2): the pruned radix-PC DFT over rows QC n1 + n2, split by the

@@ -12,10 +12,15 @@ namespace moff {
 
 enum { kModePartial = 0, kModeAccum = 1, kModeFinal = 2 };
 
+// XCDs of the device: workgroups are dispatched to them round-robin by index,
+// so workgroups whose indices agree modulo kXcds share one L2.
+constexpr int kXcds = 8;
+
 struct FusedArgs {
   const void* E;               // [T][C][n_ant] c64 or ci4
   const float2* gains;         // [C][n_ant] or nullptr
-  const GatherEntry* prog;     // [SX][prog_len][NT]
+  const uint4* prog;           // [SX][prog_len / 4][NT] (HostPlan::Variant::prog4)
+  const int* cell0;            // [SX][NT] first folded cell of each lane
   int prog_len;
   const float2* weights;       // [SX][n_weights]
   int n_weights;
@@ -39,9 +44,14 @@ struct FusedArgs {
 };
 
 // Samples summed in float32 registers before they are added to a float64
-// running sum: the float32 part then contributes at most (kBlockFrames - 1)
-// units of rounding relative to the accumulated power of a pixel.
-constexpr int kBlockFrames = 128;
+// running sum.  The float32 part then contributes at most (kBlockFrames - 1)
+// units of rounding (2^-24 each) relative to the accumulated power of a pixel
+// in the worst case, and about sqrt(kBlockFrames) / 3 units for roundings of
+// random sign; the float64 running sums keep that from growing with the
+// length of the integration.  A block of 256 covers the HERA-shaped and
+// calibration integrations (256 and 128 samples) in one slice without a
+// running-sum round trip through memory.
+constexpr int kBlockFrames = 256;
 
 struct ReduceArgs {
   const float* S_part;
@@ -50,7 +60,6 @@ struct ReduceArgs {
   float* out;
   double* outA;
   int N, n_chan, n_types, slices;
-  int sx;                      // column classes of the partials' row layout (1: pixel order)
   int final_image, subtract;
   double scale;
 };
@@ -175,7 +184,8 @@ hipError_t launch_uv_adjoint_shift(const UvArgs& a, hipStream_t st);
 struct AdjFusedArgs {
   const void* E;               // [T][C][n_ant] c64 or ci4
   const float2* gains;         // [C][n_ant] or nullptr
-  const GatherEntry* prog;     // [SX][prog_len][NT] (the forward gather program)
+  const uint4* prog;           // [SX][prog_len / 4][NT] (the forward gather program)
+  const int* cell0;            // [SX][NT]
   int prog_len;
   const float2* weights;       // [SX][n_weights]
   int n_weights;

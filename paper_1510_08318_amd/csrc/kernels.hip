@@ -23,6 +23,19 @@
 #include "ingest.h"
 #include "kernels.h"
 
+#ifndef GATHER_BATCH_256
+#define GATHER_BATCH_256 16
+#endif
+#ifndef GATHER_SUB_128
+#define GATHER_SUB_128 4
+#endif
+#ifndef GATHER_SUB_256
+#define GATHER_SUB_256 8
+#endif
+#ifndef FUSED_PREFETCH
+#define FUSED_PREFETCH 0
+#endif
+
 namespace moff {
 
 namespace {
@@ -36,44 +49,68 @@ __device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
 // Gather-gridding of one frame into the folded grid: each lane walks its slice
 // of the cell-keyed program, multiplies the calibrated antenna field by the
 // tap weight, and stores each finished cell sum.  Every folded cell is written.
-// The program sits in global memory (L2-resident: it is the same for every
-// frame), so its entries are read B at a time in one batch of loads, not one
-// dependent round trip per few entries; entries past the program's end read as
-// padding (the zero sample, no store), so the batch has no trip-count branches.
-template <int NT, int B>
-__device__ __forceinline__ void gather_frame(const GatherEntry* __restrict__ prog, int prog_len,
-                                             const float2* e, const float2* W, float2* G, uint32_t zero_entry) {
+// A lane's cells are consecutive in row-major order from its first cell, so
+// an entry carries only the antenna slot, the weight index and a "cell
+// complete" bit (4 bytes), and the k-th store of a lane goes to cell
+// cell0 + k.  The program sits in global memory (L2-resident: it is the same
+// for every frame) and is read B entries at a time, four per 16-byte load;
+// entries past the program's end read as padding (the zero sample, no store),
+// so a batch has no trip-count branches.  The samples, weights and grid are
+// disjoint LDS arrays (restrict), and the samples and weights of S entries are
+// read before any of their stores: a conditional store starts a new basic
+// block, and reads placed after it would each wait for a full LDS round trip.
+template <int NT, int B, int S, int NZR, int ZP>
+__device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, int prog_len, int cell0,
+                                             const float2* __restrict__ e, const float2* __restrict__ W,
+                                             float2* __restrict__ G, uint32_t zero_entry) {
+  static_assert(B % 4 == 0 && B % S == 0, "batches hold whole 16-byte loads and LDS sub-batches");
   float2 acc = make_float2(0.f, 0.f);
-  for (int k0 = 0; k0 < prog_len; k0 += B) {
-    GatherEntry ent[B];
+  int cell = cell0;
+  const int len4 = prog_len / 4;
+  for (int k0 = 0; k0 < len4; k0 += B / 4) {
+    uint32_t ent[B];
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-      const int k = min(k0 + i, prog_len - 1);
-      ent[i] = prog[static_cast<size_t>(k) * NT];
-      if (k0 + i >= prog_len) ent[i].x = zero_entry;
+    for (int j = 0; j < B / 4; ++j) {
+      uint4 q = prog[static_cast<size_t>(min(k0 + j, len4 - 1)) * NT];
+      if (k0 + j >= len4) q = make_uint4(zero_entry, zero_entry, zero_entry, zero_entry);
+      ent[4 * j] = q.x;
+      ent[4 * j + 1] = q.y;
+      ent[4 * j + 2] = q.z;
+      ent[4 * j + 3] = q.w;
     }
 #pragma unroll
-    for (int i = 0; i < B; ++i) {
-      const float2 ev = e[ent[i].x & 0xFFFu];
-      const float2 wv = W[(ent[i].x >> 12) & 0x7FFu];
-      acc.x = fmaf(ev.x, wv.x, fmaf(-ev.y, wv.y, acc.x));
-      acc.y = fmaf(ev.x, wv.y, fmaf(ev.y, wv.x, acc.y));
-      if (ent[i].x & kStoreBit) {
-        G[ent[i].y] = acc;
-        acc = make_float2(0.f, 0.f);
+    for (int s0 = 0; s0 < B; s0 += S) {
+      float2 ev[S], wv[S];
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        ev[i] = e[ent[s0 + i] & 0xFFFu];
+        wv[i] = W[(ent[s0 + i] >> 12) & 0x7FFu];
+      }
+#pragma unroll
+      for (int i = 0; i < S; ++i) {
+        acc.x = fmaf(ev[i].x, wv[i].x, fmaf(-ev[i].y, wv[i].y, acc.x));
+        acc.y = fmaf(ev[i].x, wv[i].y, fmaf(ev[i].y, wv[i].x, acc.y));
+        if (ent[s0 + i] & kStoreBit) {
+          G[cell + (cell / NZR) * (ZP - NZR)] = acc;   // folded cell (iy, n') at iy ZP + n'
+          ++cell;
+          acc = make_float2(0.f, 0.f);
+        }
       }
     }
   }
 }
 
-// Entries per batch of program reads.  At N = 128 the program (about 20
-// entries per lane) fits one batch, and the registers it takes are free during
-// the gridding (the transform's temporaries are not live then).  Elsewhere
-// batches of 4 measured faster: at N = 256 the programs are 70-90 entries long
-// and large batches raised register pressure in kernels already at 256 VGPRs.
-template <int N>
+// Entries per batch of program reads (B) and per LDS sub-batch (S).  At
+// N = 128 the program (about 20 entries per lane) fits one batch, and the
+// registers it takes are free during the gridding (the transform's
+// temporaries are not live then).
+template <int N, int V = 0>
 constexpr int gather_batch() {
-  return N == 128 ? 24 : 4;
+  return N == 128 ? 24 : N == 256 ? GATHER_BATCH_256 : 8;
+}
+template <int N, int V = 0>
+constexpr int gather_sub() {
+  return N == 128 ? GATHER_SUB_128 : N == 256 ? GATHER_SUB_256 : 4;
 }
 
 }  // namespace
@@ -90,20 +127,43 @@ constexpr int fused_waves_per_simd() {
   return (N == 128 && V == 0) ? 4 : 1;
 }
 
-template <int N, int V, bool CI4>
-__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<N, V>())))
-void fused_kernel(FusedArgs a) {
+// Samples of the next frame each lane loads ahead (antennas tid + k NT,
+// k < kPrefetch), so that their latency overlaps the current frame's transform.
+constexpr int kPrefetch = FUSED_PREFETCH;
+
+// A raw sample held in registers between its load and its use: the byte of a
+// 4+4-bit sample, or a complex64 value.
+template <bool CI4>
+struct RawSample {
+  float2 v;
+  __device__ __forceinline__ void load(const void* E, size_t idx) { v = reinterpret_cast<const float2*>(E)[idx]; }
+  __device__ __forceinline__ float2 value() const { return v; }
+};
+template <>
+struct RawSample<true> {
+  int b;
+  __device__ __forceinline__ void load(const void* E, size_t idx) { b = reinterpret_cast<const int8_t*>(E)[idx]; }
+  __device__ __forceinline__ float2 value() const {
+    // real part in the high nibble, imaginary part in the low nibble
+    return make_float2(static_cast<float>(b >> 4), static_cast<float>(static_cast<int8_t>(b << 4) >> 4));
+  }
+};
+
+// One work item of the fused kernel: column class W (a compile-time constant,
+// so the row stage's fold factors are constant rotations), channel c and a
+// slice of time samples.
+template <int N, int V, bool CI4, int W>
+__device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, double* Atot, int c, int slice,
+                                           int item) {
   using C = FT<N, V>;
   constexpr int NT = C::NT;
-  extern __shared__ float2 lds[];
-  __shared__ double Atot[kMaxTypesDev];
   const int tid = threadIdx.x;
 
   float2* G = lds;                          // [L][P], row pitch P = M + 1
   float2* twr = G + C::GRID;                // [PR * QR]
   float2* twc = twr + C::TWR;               // [PC * QC]
-  float2* W = twc + C::TWC;                 // [n_weights]
-  float2* gl = W + a.n_weights;             // [n_ant] gains of the current channel
+  float2* Wt = twc + C::TWC;                // [n_weights]
+  float2* gl = Wt + a.n_weights;            // [n_ant] gains of the current channel
   float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
   int* ty = reinterpret_cast<int*>(e + a.n_ant + 1);  // [n_ant]
 
@@ -112,123 +172,152 @@ void fused_kernel(FusedArgs a) {
   const int64_t T = a.n_time;
   const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
   const size_t img_stride = static_cast<size_t>(N) * N;
-  const int n_items = C::SX * a.n_chan * a.slices;
 
-  // One work item (column class w, channel c, time slice) per workgroup.  (A
-  // persistent loop over items makes the compiler keep far more registers live
-  // -- 127 -> 256 VGPRs at N = 64 -- so launches are instead sized in whole
-  // rounds of resident workgroups by the autotuner.)
+  build_twiddles<N, V>(a.tw, W, twr, twc);
+  for (int i = tid; i < a.n_weights; i += NT) Wt[i] = a.weights[static_cast<size_t>(W) * a.n_weights + i];
+  for (int i = tid; i < a.n_ant; i += NT)
+    gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
+
+  const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
+  const uint4* prog = a.prog + static_cast<size_t>(W) * (a.prog_len / 4) * NT + tid;
+  const int cell0 = a.cell0[W * NT + tid];
+
+  float acc[C::NACC];
+#pragma unroll
+  for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
+  double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  // float64 running sums of this workgroup's pixels (blocked accumulation),
+  // laid out [item][acc index][lane]: a uniform base per accumulator index
+  // plus the lane's offset, so no per-lane address stays live in the loop
+  double* run64 = a.acc64 ? a.acc64 + static_cast<size_t>(item) * C::NACC * NT : nullptr;
+  bool flushed = false;
+  int in_block = 0;
+
+  // the first frame's samples
+  RawSample<CI4> raw[kPrefetch > 0 ? kPrefetch : 1];
   {
-    const int item = blockIdx.x;
-    if (item >= n_items) return;
-    const int w = item % C::SX;
-    const int c = (item / C::SX) % a.n_chan;
-    const int slice = item / (C::SX * a.n_chan);
-
-    __syncthreads();   // the previous item is done with every LDS table
-    build_twiddles<N, V>(a.tw, w, twr, twc);
-    float2 fin[C::PRNZ];
-    fold_factors<N, V>(a.tw, w, fin);
-    for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
-    for (int i = tid; i < a.n_ant; i += NT)
-      gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
-
-    const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
-    const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
-
-    float acc[C::NACC];
+    const size_t base = static_cast<size_t>(t0) * frame_stride + static_cast<size_t>(c) * a.n_ant;
 #pragma unroll
-    for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
-    double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
-    // float64 running sums of this workgroup's pixels (blocked accumulation),
-    // laid out [item][acc index][lane]: a uniform base per accumulator index
-    // plus the lane's offset, so no per-lane address stays live in the loop
-    double* run64 = a.acc64 ? a.acc64 + static_cast<size_t>(item) * C::NACC * NT : nullptr;
-    bool flushed = false;
-    int in_block = 0;
+    for (int k = 0; k < kPrefetch; ++k)
+      if (tid + k * NT < a.n_ant && t0 < t1) raw[k].load(a.E, base + tid + k * NT);
+  }
 
+  __syncthreads();
+  for (int64_t t = t0; t < t1; ++t) {
+    // ingest + calibration: e = g * E, and the self power of each antenna type
+    const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
+    auto take = [&](int i, float2 raw_v) {
+      const float2 v = c_mul(gl[i], raw_v);
+      e[i] = v;
+      const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
+      const int tp = ty[i];
+#pragma unroll
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+    };
+#pragma unroll
+    for (int k = 0; k < kPrefetch; ++k)
+      if (tid + k * NT < a.n_ant) take(tid + k * NT, raw[k].value());
+    for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
     __syncthreads();
-    for (int64_t t = t0; t < t1; ++t) {
-      // ingest + calibration: e = g * E, and the self power of each antenna type
-      const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-      for (int i = tid; i < a.n_ant; i += NT) {
-        const float2 v = c_mul(gl[i], load_sample(a.E, base + i, CI4));
-        e[i] = v;
-        const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
-        const int tp = ty[i];
+    gather_frame<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, a.prog_len, cell0, e, Wt, G,
+                                                                           static_cast<uint32_t>(a.n_ant));
+    // the next frame's samples load while this frame is transformed (after
+    // the gather, so that its program loads do not wait for them)
+    if (t + 1 < t1) {
 #pragma unroll
-        for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
-      }
-      __syncthreads();
-      gather_frame<NT, gather_batch<N>()>(prog, a.prog_len, e, W, G, static_cast<uint32_t>(a.n_ant));
-      __syncthreads();
-      row_stage<N, V>(G, twr, fin);
-      __syncthreads();
-      col_stage<N, V>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
-      // blocked accumulation: fold the block's float32 sums into float64
-      if (a.acc64 && ++in_block == kBlockFrames && t + 1 < t1) {   // uniform branch
-        // An opaque zero defined here keeps the compiler from hoisting the
-        // flush's addresses out of the time loop (they would hold 2 NACC
-        // registers for the whole loop).
-        int zero;
-        asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
-        double* base = run64 + zero + tid;
-        // The first block is stored, later ones added (no-return float64 adds:
-        // each address has this one lane as its only writer, so the order of
-        // additions is fixed).
-        if (!flushed) {
-#pragma unroll
-          for (int idx = 0; idx < C::NACC; ++idx) base[idx * NT] = static_cast<double>(acc[idx]);
-        } else {
-#pragma unroll
-          for (int idx = 0; idx < C::NACC; ++idx) unsafeAtomicAdd(base + idx * NT, static_cast<double>(acc[idx]));
-        }
-#pragma unroll
-        for (int idx = 0; idx < C::NACC; ++idx) acc[idx] = 0.f;
-        flushed = true;
-        in_block = 0;
-      }
+      for (int k = 0; k < kPrefetch; ++k)
+        if (tid + k * NT < a.n_ant) raw[k].load(a.E, base + frame_stride + tid + k * NT);
     }
-
-    block_sum4<NT>(pw, Atot);
-
+    __syncthreads();
+    row_stage_w<N, V, W>(G, twr);
+    __syncthreads();
+    col_stage<N, V>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });
+    // blocked accumulation: fold the block's float32 sums into float64
+    if (a.acc64 && ++in_block == kBlockFrames && t + 1 < t1) {   // uniform branch
+      // An opaque zero defined here keeps the compiler from hoisting the
+      // flush's addresses out of the time loop (they would hold 2 NACC
+      // registers for the whole loop).
+      int zero;
+      asm volatile("s_mov_b32 %0, 0" : "=s"(zero));
+      double* blk = run64 + zero + tid;
+      // The first block is stored, later ones added (no-return float64 adds:
+      // each address has this one lane as its only writer, so the order of
+      // additions is fixed).
+      if (!flushed) {
 #pragma unroll
-    for (int idx = 0; idx < C::NACC; ++idx) {
-      int r, col;
-      acc_pixel<N, V>(idx, r, col);
-      if (C::CGUARD && col >= C::M) continue;
-      const int q = C::SX * col + w;
-      const int pr = (r + N / 2) & (N - 1), pq = (q + N / 2) & (N - 1);
-      const size_t pix = static_cast<size_t>(pr) * N + pq;
-      // (read at device scope: the adds were performed in L2)
-      const double sum = static_cast<double>(acc[idx]) +
-                         (flushed ? __hip_atomic_load(run64 + idx * NT + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                  : 0.0);
-      if (a.mode == kModePartial) {
-        // Partial sums are stored class-major within each image row (this
-        // class's M columns contiguous, pq = SX * pcol + w), so that every
-        // 128-byte line has one writer; the reduction reads them back in
-        // pixel order.
-        const size_t ppix = static_cast<size_t>(pr) * N + static_cast<size_t>(w) * C::M + ((col + C::M / 2) & (C::M - 1));
-        a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + ppix] = static_cast<float>(sum);
-      } else if (a.mode == kModeAccum) {
-        float& o = a.out[static_cast<size_t>(c) * img_stride + pix];
-        o = static_cast<float>(static_cast<double>(o) + sum);
+        for (int idx = 0; idx < C::NACC; ++idx) blk[idx * NT] = static_cast<double>(acc[idx]);
       } else {
-        double v = sum;
-        if (a.subtract)
-          for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
-        a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+#pragma unroll
+        for (int idx = 0; idx < C::NACC; ++idx) unsafeAtomicAdd(blk + idx * NT, static_cast<double>(acc[idx]));
       }
-    }
-    if (w == 0 && tid < a.n_types) {
-      if (a.mode == kModePartial) {
-        a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
-      } else if (a.mode == kModeAccum) {
-        a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
-      }
+#pragma unroll
+      for (int idx = 0; idx < C::NACC; ++idx) acc[idx] = 0.f;
+      flushed = true;
+      in_block = 0;
     }
   }
+
+  block_sum4<NT>(pw, Atot);
+
+  // The transform runs on the transposed aperture (the host plan's programs):
+  // its folded axis m is the image row, r = SX m + W, and its column-stage
+  // output index is the image column, so this workgroup owns whole image rows
+  // and every 128-byte line of the output has one writer.
+#pragma unroll
+  for (int idx = 0; idx < C::NACC; ++idx) {
+    int r, col;
+    acc_pixel<N, V>(idx, r, col);
+    if (C::CGUARD && col >= C::M) continue;
+    const int pr = (C::SX * col + W + N / 2) & (N - 1), pq = (r + N / 2) & (N - 1);
+    const size_t pix = static_cast<size_t>(pr) * N + pq;
+    // (read at device scope: the adds were performed in L2)
+    const double sum = static_cast<double>(acc[idx]) +
+                       (flushed ? __hip_atomic_load(run64 + idx * NT + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                : 0.0);
+    if (a.mode == kModePartial) {
+      a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = static_cast<float>(sum);
+    } else if (a.mode == kModeAccum) {
+      float& o = a.out[static_cast<size_t>(c) * img_stride + pix];
+      o = static_cast<float>(static_cast<double>(o) + sum);
+    } else {
+      double v = sum;
+      if (a.subtract)
+        for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
+      a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+    }
+  }
+  if (W == 0 && tid < a.n_types) {
+    if (a.mode == kModePartial) {
+      a.outA[(static_cast<size_t>(slice) * a.n_chan + c) * a.n_types + tid] = Atot[tid];
+    } else if (a.mode == kModeAccum) {
+      a.outA[static_cast<size_t>(c) * a.n_types + tid] += Atot[tid];
+    }
+  }
+}
+
+// One work item (output class w, channel c, time slice) per workgroup.  (A
+// persistent loop over items makes the compiler keep far more registers live
+// -- 127 -> 256 VGPRs at N = 64 -- so launches are instead sized in whole
+// rounds of resident workgroups by the autotuner.)  The SX classes of one
+// (channel, slice) take workgroup indices kXcds apart, so they run on one XCD
+// and its L2 serves the channel's samples to all of them; the grid pads the
+// (channel, slice) count to a multiple of kXcds.
+template <int N, int V, bool CI4>
+__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<N, V>())))
+void fused_kernel(FusedArgs a) {
+  using C = FT<N, V>;
+  extern __shared__ float2 lds[];
+  __shared__ double Atot[kMaxTypesDev];
+  const int b = blockIdx.x;
+  const int w = (b / kXcds) % C::SX;
+  const int cs = (b / (kXcds * C::SX)) * kXcds + b % kXcds;   // channel-slice index
+  if (cs >= a.n_chan * a.slices) return;
+  const int c = cs % a.n_chan, slice = cs / a.n_chan;
+  const int item = cs * C::SX + w;
+  static_for<0, C::SX>([&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    if (w == W) fused_item<N, V, CI4, W>(a, lds, Atot, c, slice, item);
+  });
 }
 
 // ---------------------------------------------------------------------------
@@ -279,9 +368,10 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
   for (int idx = 0; idx < C::NACC; ++idx) {
     int r, col;
     acc_pixel<N, V>(idx, r, col);
-    const int q = C::SX * col + w;
-    rr[idx] = (C::CGUARD && col >= C::M) ? 0.f
-                                         : Rc[static_cast<size_t>((r + N / 2) & (N - 1)) * N + ((q + N / 2) & (N - 1))];
+    // transposed aperture, as in the forward kernel: image row SX col + w, image column r
+    rr[idx] = (C::CGUARD && col >= C::M)
+                  ? 0.f
+                  : Rc[static_cast<size_t>((C::SX * col + w + N / 2) & (N - 1)) * N + ((r + N / 2) & (N - 1))];
   }
 
   // this lane's antennas for the degridding
@@ -297,7 +387,8 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
   const int64_t T = a.n_time;
   const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
   const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
-  const GatherEntry* prog = a.prog + static_cast<size_t>(w) * a.prog_len * NT + tid;
+  const uint4* prog = a.prog + static_cast<size_t>(w) * (a.prog_len / 4) * NT + tid;
+  const int cell0 = a.cell0[w * NT + tid];
 
   __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
@@ -310,7 +401,8 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
       Er[s] = ant != kAdjEmpty ? load_sample(a.E, base + ant, CI4) : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    gather_frame<NT, gather_batch<N>()>(prog, a.prog_len, e, W, G, static_cast<uint32_t>(a.n_ant));
+    gather_frame<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, a.prog_len, cell0, e, W, G,
+                                                                           static_cast<uint32_t>(a.n_ant));
     __syncthreads();
     row_stage<N, V>(G, twr, fin);
     __syncthreads();
@@ -326,11 +418,12 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
       const int off = (s0[s] >> 12) & 0xFFFu, k = (s0[s] >> 24) & 0xFu;
       const int ix0 = s1[s] & 0xFFFFu, iy0 = s1[s] >> 16;
       float dx = 0.f, dy = 0.f;
-      for (int u = 0; u < k; ++u) {
-        const float2* Grow = G + (iy0 + u) * C::P;
-        for (int v = 0; v < k; ++v) {
-          const int ix = ix0 + v;
-          const int j = ix / C::M, n = ix - j * C::M;
+      // transposed aperture: folded-grid row ix, folded axis along y
+      for (int v = 0; v < k; ++v) {
+        const float2* Grow = G + (ix0 + v) * C::P;
+        for (int u = 0; u < k; ++u) {
+          const int iy = iy0 + u;
+          const int j = iy / C::M, n = iy - j * C::M;
           const float2 g = Grow[n];
           const float2 wt = W[j * a.n_taps + off + u * k + v];
           dx = fmaf(g.x, wt.x, fmaf(g.y, wt.y, dx));
@@ -376,19 +469,15 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const double2* Dp, 
   D[i] = make_double2(x, y);
 }
 
-// Sum per-slice partials in slice order; then remove self power and average
-// (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).  Partials
-// are laid out class-major within each row when a.sx > 1 (pixel column
-// pq = sx * j + k stored at k * (N / sx) + j).
+// Sum per-slice partials (pixel order) in slice order; then remove self power
+// and average (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const size_t npix = static_cast<size_t>(a.N) * a.N;
   const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
   if (i >= npix * a.n_chan) return;
   const size_t c = i / npix, pix = i % npix;
-  const int pr = static_cast<int>(pix / a.N), pq = static_cast<int>(pix % a.N);
-  const size_t ppix = static_cast<size_t>(pr) * a.N + static_cast<size_t>(pq % a.sx) * (a.N / a.sx) + pq / a.sx;
   double s = 0.0;
-  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + ppix];
+  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + pix];
   double A[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < a.n_types; ++p)
     for (int sl = 0; sl < a.slices; ++sl) A[p] += a.A_part[(static_cast<size_t>(sl) * a.n_chan + c) * a.n_types + p];
@@ -791,7 +880,6 @@ int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
-  if (a.sx < 1 || a.N % a.sx != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
   return hipGetLastError();
 }

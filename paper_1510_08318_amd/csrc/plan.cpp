@@ -423,21 +423,26 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         }
       }
 
-    // folded cells (iy, n'), n' < NZR, row-major; entries from cells (iy, n' + j M), j ascending,
-    // antenna ascending within a cell.  Every folded cell is written every frame (an empty one by a
-    // single entry that reads the all-zero antenna slot).
+    // The fused transform runs on the transposed aperture: folded-grid row a is
+    // aperture column ix = a, and the folded axis runs along y, so a workgroup's
+    // output class is a residue class of image rows and it writes whole image
+    // rows.  Folded cells (a, n'), n' < NZR, row-major; entries from aperture
+    // cells (iy, ix) = (n' + j M, a), j ascending, antenna ascending within a
+    // cell.  Every folded cell is written every frame (an empty one by a single
+    // entry that reads the all-zero antenna slot).
+    auto csr_cell = [&](int a, int m) { return m * L + a; };   // CSR index of aperture cell (iy = m, ix = a)
     const int ncell = L * V.NZR;
     std::vector<int> cost(ncell);
     int maxc = 0;
-    for (int iy = 0; iy < L; ++iy)
+    for (int a = 0; a < L; ++a)
       for (int n = 0; n < V.NZR; ++n) {
         int c = 0;
         for (int j = 0; j < V.NJ; ++j) {
-          int ix = n + j * V.M;
-          if (ix < L) c += P.csr_ptr[iy * L + ix + 1] - P.csr_ptr[iy * L + ix];
+          int m = n + j * V.M;
+          if (m < L) c += P.csr_ptr[csr_cell(a, m) + 1] - P.csr_ptr[csr_cell(a, m)];
         }
         maxc = std::max(maxc, c);
-        cost[iy * V.NZR + n] = std::max(1, c);
+        cost[a * V.NZR + n] = std::max(1, c);
       }
     P.max_cell_entries = maxc;
     // smallest per-lane load B for which a contiguous greedy split needs <= NT lanes
@@ -461,10 +466,11 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
       else lo = mid + 1;
     }
     const long long B = lo;
-    V.prog_len = static_cast<int>(B);
+    V.prog_len = static_cast<int>((B + 3) / 4 * 4);
     if (V.prog_len > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
     const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
     V.prog.assign(static_cast<size_t>(S.SX) * V.prog_len * S.NT, GatherEntry{zero_slot, 0});
+    V.cell0.assign(static_cast<size_t>(S.SX) * S.NT, 0);
     for (int w = 0; w < S.SX; ++w) {
       GatherEntry* base = &V.prog[static_cast<size_t>(w) * V.prog_len * S.NT];
       int lane = 0, k = 0;
@@ -474,15 +480,16 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
           ++lane;
           k = 0;
           cur = 0;
+          V.cell0[static_cast<size_t>(w) * S.NT + lane] = i;
         }
         cur += cost[i];
-        const int iy = i / V.NZR, n = i % V.NZR;
-        const uint32_t dst = static_cast<uint32_t>(iy * V.ZP + n);
+        const int a = i / V.NZR, n = i % V.NZR;
+        const uint32_t dst = static_cast<uint32_t>(a * V.ZP + n);
         int emitted = 0;
         for (int j = 0; j < V.NJ; ++j) {
-          int ix = n + j * V.M;
-          if (ix >= L) continue;
-          for (int e = P.csr_ptr[iy * L + ix]; e < P.csr_ptr[iy * L + ix + 1]; ++e) {
+          int m = n + j * V.M;
+          if (m >= L) continue;
+          for (int e = P.csr_ptr[csr_cell(a, m)]; e < P.csr_ptr[csr_cell(a, m) + 1]; ++e) {
             uint32_t wi = static_cast<uint32_t>(j * P.n_taps + P.csr_tap[e]);
             base[static_cast<size_t>(k) * S.NT + lane] = GatherEntry{static_cast<uint32_t>(P.csr_ant[e]) | (wi << 12), dst};
             ++k;
@@ -496,6 +503,14 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
       }
     }
+    // device form: x words, four consecutive entries of a lane side by side
+    V.prog4.assign(V.prog.size(), zero_slot);
+    const int K4 = V.prog_len / 4;
+    for (int w = 0; w < S.SX; ++w)
+      for (int k = 0; k < V.prog_len; ++k)
+        for (int lane = 0; lane < S.NT; ++lane)
+          V.prog4[((static_cast<size_t>(w) * K4 + k / 4) * S.NT + lane) * 4 + k % 4] =
+              V.prog[(static_cast<size_t>(w) * V.prog_len + k) * S.NT + lane].x;
     build_adjoint_slots(P, S.NT, &V.slots);
     P.variants.push_back(std::move(V));
   }

@@ -67,8 +67,13 @@ struct HostPlan {
   struct Variant {
     FrameShape shape{};
     int M = 0, NZR = 0, NJ = 0, ZP = 0;       // ZP: LDS row pitch of the folded grid
-    int prog_len = 0;                        // entries per lane (padded)
-    std::vector<GatherEntry> prog;           // [SX][prog_len][NT]
+    int prog_len = 0;                        // entries per lane (padded to a multiple of 4)
+    std::vector<GatherEntry> prog;           // [SX][prog_len][NT], host form with each store's LDS cell
+    // Device form: the x words only, four consecutive entries of a lane side by
+    // side, [SX][prog_len / 4][NT][4]; a lane's stores fill consecutive folded
+    // cells (iy, n') in row-major order from its first cell cell0[w][lane].
+    std::vector<uint32_t> prog4;
+    std::vector<int32_t> cell0;              // [SX][NT]
     std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
     int n_weights() const { return NJ * n_taps_; }
     int n_taps_ = 0;

@@ -115,7 +115,8 @@ def test_error_codes(moff):
 @pytest.mark.parametrize("case", ["config1", "config2", "config5", "hetero_small", "n8", "n16"])
 def test_gather_program_replays_oracle_grid(moff, case):
     """Replaying the fused kernel's gather program on the CPU (float64) gives the
-    oracle's gridded field, folded onto the workgroup's output-column class."""
+    oracle's gridded field, transposed (folded-grid row = aperture column x) and
+    folded along y onto the workgroup's class of image rows."""
     rng = np.random.default_rng(5)
     if case == "config1":
         w = synth.make_config(1, n_time=2)
@@ -131,7 +132,7 @@ def test_gather_program_replays_oracle_grid(moff, case):
         w = synth.random_case(4, 5, N, 1, 2, [synth.random_kernel(rng, 2)], extent_m=1.5, cell_m=1.0)
     P = oracle.plan(w.geom)
     e = oracle.calibrated_field(w.E, w.gains, w.geom.flags, 0)
-    Eg = oracle.grid_field(e, P)[0]
+    Eg = oracle.grid_field(e, P)[0].T           # [ix][iy]: the fused programs' transposed aperture
     N, L = P["N"], P["L"]
     with host_plan(moff, w.geom) as p:
       for variant in (0, 1):
@@ -161,7 +162,7 @@ def test_gather_program_replays_oracle_grid(moff, case):
                 G[y[k][s]] = acc[s]
                 stored[y[k][s]] += 1
                 acc[s] = 0
-            # folded reference: sum_j exp(2 pi i j w / SX) Eg[iy, n + j M]
+            # folded reference: sum_j exp(2 pi i j w / SX) Eg^T[ix, n + j M]
             ref = np.zeros((L, NZR), complex)
             for j in range(max(1, L // M)):
                 ref += np.exp(2j * np.pi * j * cls / SX) * Eg[:, j * M:j * M + NZR]
@@ -171,6 +172,18 @@ def test_gather_program_replays_oracle_grid(moff, case):
             got = G[slot]
             assert (stored[slot] == 1).all() and stored.sum() == L * NZR
             assert np.max(np.abs(got - ref)) <= 1e-6 * max(1.0, np.abs(ref).max())
+            # The device keeps only the x words: a lane's k-th store goes to the
+            # folded cell after its first one, so each lane's stores must fill
+            # consecutive cells (row-major over (iy, n')), and batches of four
+            # entries must tile the program.
+            assert prog.shape[0] % 4 == 0
+            for lane in range(prog.shape[1]):
+                dst = y[:, lane][st[:, lane] == 1]
+                if len(dst) == 0:
+                    continue
+                cells = (dst // ZP) * NZR + dst % ZP
+                assert (dst % ZP < NZR).all()
+                assert (np.diff(cells) == 1).all(), (cls, lane)
 
 
 def test_uv_rule_flag_validation(moff):

@@ -178,10 +178,10 @@ def test_accumulate_split_equals_whole(torch, moff):
 def test_long_integration_one_slice(torch, moff):
     """A long integration in one time slice (Sec. 3 time averaging): 100,000
     samples summed by a single workgroup per column class.  The float32
-    register sums are folded into float64 every 128 samples, so the
-    accumulation adds well under 1e-6 here; one float32 sum over all samples
-    would add about 9e-6 on this input (measured by a CPU simulation of that
-    summation order).  The oracle runs over time chunks and sums S and A,
+    register sums are folded into float64 every 256 samples, so the
+    accumulation adds well under 1e-6 here (2e-8 in a CPU simulation of that
+    summation order); one float32 sum over all samples would add about 9e-6
+    on this input (the same simulation).  The oracle runs over time chunks and sums S and A,
     which are linear in the frames."""
     T, chunk = 100_000, 5_000
     w = synth.make_config(1, n_time=T)

@@ -3,7 +3,7 @@ against moff_image through the C ABI, and against the FP64 oracle.
 
 Two calls in a row on one plan, the second with a smaller input, each with a
 launch configuration whose scratch holds per-slice partial sums; the first
-also holds float64 running sums (slices longer than 128 samples).  The same
+also holds float64 running sums (slices longer than 256 samples).  The same
 launch configuration gives the same kernels and summation order, so the two
 entry points must agree bitwise; both must meet the 1e-5 parity bar of the
 other GPU tests.  A request whose scratch cannot fit is rejected before any
@@ -50,12 +50,12 @@ def check_oracle(w, got, T):
 
 
 def test_noalloc_matches_image_two_calls(torch, moff):
-    w = synth.make_config(2, n_time=300, n_chan=4)
-    print("noalloc: config-2 subset, 4 channels, T = 300 then 200, 2 slices", flush=True)
+    w = synth.make_config(2, n_time=600, n_chan=4)
+    print("noalloc: config-2 subset, 4 channels, T = 600 then 400, 2 slices", flush=True)
     with moff.Plan.from_geometry(w.geom, device=0) as p:
         p.set_config(0, 2)
         E = to_dev(torch, w.E)
-        for T in (300, 200):           # the second call smaller: 100 samples per slice
+        for T in (600, 400):           # the second call smaller: 200 samples per slice
             Et = E[:T].contiguous()
             ref_dev = p.image(Et)
             out = torch.full_like(ref_dev, float("nan"))
@@ -85,12 +85,12 @@ def test_noalloc_gains_and_one_slice(torch, moff):
 
 
 def test_noalloc_rejects_oversized_scratch(torch, moff):
-    # 300 channels of a 256 grid with 129 samples in one slice need
+    # 300 channels of a 256 grid with 257 samples in one slice need
     # 8 * 300 * 256^2 bytes of float64 running sums: more than the fixed array
     w = synth.make_config(3, n_time=2, n_chan=300)
     with moff.Plan.from_geometry(w.geom, device=0) as p:
         p.set_config(1, 1)
-        E = torch.zeros((129, 300, w.geom.n_ant), dtype=torch.uint8, device="cuda:0")
+        E = torch.zeros((257, 300, w.geom.n_ant), dtype=torch.uint8, device="cuda:0")
         out = torch.empty((300, 256, 256), dtype=torch.float32, device="cuda:0")
         with pytest.raises(moff.MoffError) as ei:
             p.image_noalloc(E, out=out)
