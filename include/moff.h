@@ -249,13 +249,14 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * the stream.  It first runs the default shape for about 200 ms so that no
  * candidate is timed on a cold device, then takes each candidate's time as the
  * best of three batches of three back-to-back calls; later results do not depend on the choice beyond float32
- * rounding order.  Where the fused gain adjoint is built with more than one
- * register budget (grid_n 128 and 256, see moff_plan_set_adjoint_waves) and
- * the plan has no MOFF_MFMA_* flag, it also times
- * moff_gain_vjp with each, on the same samples and gains with the tuned image
- * as the pixel sensitivities, and keeps the fastest.  moff_plan_set_config forces a choice (slices = 0:
- * heuristic); moff_plan_get_config reports the configuration a call with
- * n_time samples would use.  Any output of get_config may be NULL.
+ * rounding order.  Unless the plan has a MOFF_MFMA_* flag, it also times the
+ * fused gain adjoint (moff_gain_vjp) for every shape variant and register
+ * budget it is built with (see moff_plan_set_adjoint_waves), on the same
+ * samples and gains with the tuned image as the pixel sensitivities, and
+ * keeps the fastest.  moff_plan_set_config forces a choice (slices = 0:
+ * heuristic) and gives the adjoint the same shape variant; moff_plan_get_config
+ * reports the configuration a call with n_time samples would use.  Any output
+ * of get_config may be NULL.
  */
 moff_status moff_plan_autotune(moff_plan plan, const void* E_dev, int64_t n_time, const float* gains_dev,
                                void* hip_stream);
@@ -263,14 +264,14 @@ moff_status moff_plan_autotune(moff_plan plan, const void* E_dev, int64_t n_time
 /*
  * Register budget of the fused gain adjoint (moff_gain_vjp): the least number
  * of waves per SIMD its registers are sized for (1, the default: as many as the
- * kernel wants).  At grid_n 256 the adjoint wants more registers than two waves
- * per SIMD can hold: 1 keeps the excess in the accumulation registers, 2 spills
- * it to scratch memory and runs two waves.  At grid_n 128 it fits two waves,
- * and 3 spills a little to run three.  Which is fastest depends on the
- * workload; results are the same either way.  max_waves_per_simd = 3 at
- * grid_n 128, 2 at 256, 1 otherwise; set_adjoint_waves returns
- * MOFF_ERR_UNSUPPORTED above it and MOFF_ERR_INVALID_ARG below 1.  Outputs of
- * get_adjoint_waves may be NULL.
+ * kernel wants).  The adjoint reads its pixel sensitivities and its antennas'
+ * descriptors from memory as each frame needs them, so at every grid size it
+ * fits two waves per SIMD without spilling; at grid_n 128 a budget of 3 runs
+ * three waves (the smaller shape variant without spilling).  Which is fastest
+ * depends on the workload; results are the same either way.
+ * max_waves_per_simd = 3 at grid_n 128, 2 at 256, 1 otherwise;
+ * set_adjoint_waves returns MOFF_ERR_UNSUPPORTED above it and
+ * MOFF_ERR_INVALID_ARG below 1.  Outputs of get_adjoint_waves may be NULL.
  */
 moff_status moff_plan_set_adjoint_waves(moff_plan plan, int32_t waves_per_simd);
 moff_status moff_plan_get_adjoint_waves(moff_plan plan, int32_t* waves_per_simd, int32_t* max_waves_per_simd);

@@ -23,6 +23,7 @@ struct moff_plan_s {
   int device = -1;
   // device tables
   uint4* d_prog[moff::kMaxVariants] = {};       // HostPlan::Variant::prog4
+  float4* d_progw[moff::kMaxVariants] = {};     // HostPlan::Variant::progw (null: complex weights)
   int* d_cell0[moff::kMaxVariants] = {};
   float2* d_weights[moff::kMaxVariants] = {};
   float2* d_tw = nullptr;
@@ -38,7 +39,7 @@ struct moff_plan_s {
   GatherEntry* d_mfma_prog = nullptr;   // reduced-precision path (MOFF_MFMA_*)
   uint16_t* d_mfma_dft = nullptr;
   double* d_Pn = nullptr;               // uv-plane autocorrelation rule (MOFF_AUTOCORR_UV)
-  uint32_t* d_adj_slots = nullptr;      // fused adjoint: antennas per lane (variant 0); null if they do not fit
+  uint32_t* d_adj_slots[moff::kMaxVariants] = {};   // fused adjoint: antennas per lane; null if they do not fit
   // visibility route (moff_image_fx), built on first use
   int* d_fx_ptr = nullptr;
   int* d_fx_ab = nullptr;
@@ -58,6 +59,7 @@ struct moff_plan_s {
   int slices = 0;           // time slices; 0 = heuristic
   bool tuned = false;
   int adj_waves = 1;        // fused adjoint: waves per SIMD its registers are sized for
+  int adj_variant = 0;      // fused adjoint: shape variant (set with the image's, or tuned on its own)
 };
 
 namespace {
@@ -118,12 +120,14 @@ void free_device(moff_plan p) {
   void* ptrs[] = {p->d_tw,        p->d_Pp,        p->d_ant_type, p->d_ktab,        p->d_csr_ptr,
                   p->d_csr_ant,   p->d_csr_tap,   p->d_ant_cells, p->d_ktype_k,    p->d_ktype_off,
                   p->d_mfma_prog, p->d_mfma_dft,  p->d_Pn,        p->d_ws,         p->d_aux,
-                  p->d_adj_slots, p->d_fx_ptr,    p->d_fx_ab,     p->d_fx_x};
+                  p->d_fx_ptr,    p->d_fx_ab,     p->d_fx_x};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   for (int v = 0; v < moff::kMaxVariants; ++v) {
     if (p->d_prog[v]) (void)hipFree(p->d_prog[v]);
     if (p->d_cell0[v]) (void)hipFree(p->d_cell0[v]);
+    if (p->d_progw[v]) (void)hipFree(p->d_progw[v]);
+    if (p->d_adj_slots[v]) (void)hipFree(p->d_adj_slots[v]);
     if (p->d_weights[v]) (void)hipFree(p->d_weights[v]);
   }
   if (p->ev0) (void)hipEventDestroy(p->ev0);
@@ -256,6 +260,7 @@ moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_ti
   a.E = E;
   a.gains = reinterpret_cast<const float2*>(gains);
   a.prog = p->d_prog[variant];
+  a.progw = p->d_progw[variant];
   a.cell0 = p->d_cell0[variant];
   a.prog_len = V.prog_len;
   a.weights = p->d_weights[variant];
@@ -334,7 +339,8 @@ FusedScratch fused_scratch(const HostPlan& hp, const LaunchConfig& lc, int64_t n
     f.a_bytes = sizeof(double) * hp.n_chan * hp.n_ktypes * lc.slices;
   }
   const int64_t longest = (n_time + lc.slices - 1) / lc.slices;
-  if (!is_mfma(hp) && longest > moff::kBlockFrames) f.run_bytes = sizeof(double) * pixels;
+  if (!is_mfma(hp) && longest > moff::kBlockFrames)
+    f.run_bytes = sizeof(double) * moff::fused_lane_values(hp.N, lc.variant) * hp.n_chan * lc.slices;
   return f;
 }
 
@@ -460,32 +466,39 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
   gf.subtract = (hp.flags & (MOFF_AUTOCORR_NONE | MOFF_AUTOCORR_UV)) ? 0 : 1;
   gf.scale = 2.0 * image_scale(hp, n_time);
 
-  const size_t lds = moff::fused_lds_bytes(hp.N, 0, V.n_weights(), hp.n_ant);
-  if (!force_staged && p->d_adj_slots && lds <= size_t(159) * 1024) {
+  const int av = std::min<int>(p->adj_variant, static_cast<int>(hp.variants.size()) - 1);
+  const HostPlan::Variant& AV = hp.variants[av];
+  const size_t lds = moff::fused_lds_bytes(hp.N, av, AV.n_weights(), hp.n_ant);
+  if (!force_staged && p->d_adj_slots[av] && lds <= size_t(159) * 1024 &&
+      moff::adjoint_fused_blocks_per_cu(hp.N, av, ci4, p->adj_waves, lds) > 0) {
     // fused: every frame's grid, field and adjoint stay in LDS
-    const int per_slice = V.shape.SX * hp.n_chan;
+    const int per_slice = AV.shape.SX * hp.n_chan;
     const int resident =
-        std::max(1, moff::adjoint_fused_blocks_per_cu(hp.N, 0, ci4, p->adj_waves, lds)) * std::max(1, p->cu_count);
+        std::max(1, moff::adjoint_fused_blocks_per_cu(hp.N, av, ci4, p->adj_waves, lds)) * std::max(1, p->cu_count);
     const int slices = static_cast<int>(
         std::max<int64_t>(1, std::min<int64_t>({(2 * resident + per_slice - 1) / per_slice, n_time, 64})));
-    const int parts = slices * V.shape.SX;
+    const int parts = slices * AV.shape.SX;
     const size_t na = static_cast<size_t>(hp.n_chan) * hp.n_ant;
-    s = ensure_workspace(p, sizeof(double2) * na * (parts + 1) + sizeof(double) * na);
+    const size_t d_bytes = (sizeof(double2) * na * (parts + 1) + sizeof(double) * na + 255) / 256 * 256;
+    s = ensure_workspace(p, d_bytes + sizeof(float) * moff::fused_lane_values(hp.N, av) * hp.n_chan);
     if (s != MOFF_OK) return s;
     double2* Dp = static_cast<double2*>(p->d_ws);
     double2* D = Dp + na * parts;
     double* Q = reinterpret_cast<double*>(D + na);
+    float* Rl = reinterpret_cast<float*>(static_cast<char*>(p->d_ws) + d_bytes);
+    if (moff::launch_adjoint_sensitivity(R, hp.N, av, hp.n_chan, Rl, st) != hipSuccess) return MOFF_ERR_HIP;
     moff::AdjFusedArgs a{};
     a.E = E;
     a.gains = reinterpret_cast<const float2*>(gains);
-    a.prog = p->d_prog[0];
-    a.cell0 = p->d_cell0[0];
-    a.prog_len = V.prog_len;
-    a.weights = p->d_weights[0];
-    a.n_weights = V.n_weights();
+    a.prog = p->d_prog[av];
+    a.progw = p->d_progw[av];
+    a.cell0 = p->d_cell0[av];
+    a.prog_len = AV.prog_len;
+    a.weights = p->d_weights[av];
+    a.n_weights = AV.n_weights();
     a.tw = p->d_tw;
-    a.slots = p->d_adj_slots;
-    a.R = R;
+    a.slots = p->d_adj_slots[av];
+    a.Rl = Rl;
     a.n_ant = hp.n_ant;
     a.n_chan = hp.n_chan;
     a.n_taps = hp.n_taps;
@@ -493,7 +506,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.slices = slices;
     a.Dp = Dp;
     if (p->timing && hipEventRecord(p->ev0, st) != hipSuccess) return MOFF_ERR_HIP;
-    if (moff::launch_adjoint_fused(a, hp.N, 0, ci4, p->adj_waves, per_slice * slices, st) != hipSuccess)
+    if (moff::launch_adjoint_fused(a, hp.N, av, ci4, p->adj_waves, per_slice * slices, st) != hipSuccess)
       return MOFF_ERR_HIP;
     if (p->timing) {
       if (hipEventRecord(p->ev1, st) != hipSuccess) return MOFF_ERR_HIP;
@@ -586,6 +599,8 @@ moff_status plan_create_body(const moff_geometry* geom, int hip_device, moff_pla
     for (size_t v = 0; v < hp.variants.size(); ++v) {
       up(upload(&p->d_prog[v], hp.variants[v].prog4.data(), sizeof(uint32_t) * hp.variants[v].prog4.size()));
       up(upload(&p->d_cell0[v], hp.variants[v].cell0.data(), sizeof(int32_t) * hp.variants[v].cell0.size()));
+      if (!hp.variants[v].progw.empty())
+        up(upload(&p->d_progw[v], hp.variants[v].progw.data(), sizeof(float) * hp.variants[v].progw.size()));
       up(upload(&p->d_weights[v], hp.variants[v].weights.data(), sizeof(float) * hp.variants[v].weights.size()));
     }
     if (hp.mfma.prec) {
@@ -601,8 +616,9 @@ moff_status plan_create_body(const moff_geometry* geom, int hip_device, moff_pla
     up(upload(&p->d_tw, hp.twiddle.data(), sizeof(float) * hp.twiddle.size()));
     up(upload(&p->d_Pp, Pp.data(), sizeof(double) * Pp.size()));
     up(upload(&p->d_Pn, hp.Pn.data(), sizeof(double) * hp.Pn.size()));
-    if (!hp.variants[0].slots.empty())
-      up(upload(&p->d_adj_slots, hp.variants[0].slots.data(), sizeof(uint32_t) * hp.variants[0].slots.size()));
+    for (size_t v = 0; v < hp.variants.size(); ++v)
+      if (!hp.variants[v].slots.empty())
+        up(upload(&p->d_adj_slots[v], hp.variants[v].slots.data(), sizeof(uint32_t) * hp.variants[v].slots.size()));
     up(upload(&p->d_ant_type, hp.ant_ktype.data(), sizeof(int) * hp.ant_ktype.size()));
     up(upload(&p->d_ktab, hp.kvals.data(), sizeof(float) * hp.kvals.size()));
     up(upload(&p->d_csr_ptr, hp.csr_ptr.data(), sizeof(int) * hp.csr_ptr.size()));
@@ -767,6 +783,7 @@ moff_status moff_plan_mfma_tables(moff_plan p, uint32_t* prog, uint16_t* dft, in
 moff_status moff_plan_set_config(moff_plan p, int32_t variant, int32_t slices) {
   if (!p || variant < 0 || variant >= n_variants(p->hp) || slices < 0 || slices > 256) return MOFF_ERR_INVALID_ARG;
   p->variant = variant;
+  p->adj_variant = variant;
   p->slices = slices;
   p->tuned = false;
   return MOFF_OK;
@@ -870,31 +887,39 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   // where more than one is built, time each on the same input with the tuned
   // forward image as the pixel sensitivities, and keep the fastest.  Not for
   // the reduced-precision plans, whose tuning is about their image path.
-  int bw = p->adj_waves;
+  int bw = p->adj_waves, bav = p->adj_variant;
   const int wmax = moff::adjoint_waves_max(hp.N);
-  if (result == MOFF_OK && wmax > 1 && p->d_adj_slots && !is_mfma(hp)) {
+  const bool ci4 = hp.flags & MOFF_IN_CI4;
+  if (result == MOFF_OK && !is_mfma(hp)) {
     p->variant = bv;
     p->slices = bs;
     float* grad = nullptr;
     if (hipMalloc(reinterpret_cast<void**>(&grad), sizeof(float) * 2 * hp.n_chan * hp.n_ant) != hipSuccess)
       result = MOFF_ERR_NOMEM;
     float best_adj = 1e30f;
-    for (int wv = 1; wv <= wmax && result == MOFF_OK; ++wv) {
-      p->adj_waves = wv;
-      result = gain_vjp(p, E, n_time, gains, img, grad, st, false);   // warm-up (and workspace)
-      float ms = 1e30f;
-      for (int rep = 0; rep < 2 && result == MOFF_OK; ++rep) {
-        if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
-        if (result == MOFF_OK) result = gain_vjp(p, E, n_time, gains, img, grad, st, false);
-        if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
-        if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
-        float one = 0.f;
-        if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
-        if (result == MOFF_OK) ms = std::min(ms, one);
-      }
-      if (result == MOFF_OK && ms < best_adj) {
-        best_adj = ms;
-        bw = wv;
+    for (int av = 0; av < n_variants(hp) && result == MOFF_OK; ++av) {
+      const size_t alds = moff::fused_lds_bytes(hp.N, av, hp.variants[av].n_weights(), hp.n_ant);
+      if (!p->d_adj_slots[av] || alds > size_t(159) * 1024) continue;
+      for (int wv = 1; wv <= wmax && result == MOFF_OK; ++wv) {
+        if (moff::adjoint_fused_blocks_per_cu(hp.N, av, ci4, wv, alds) <= 0) continue;
+        p->adj_variant = av;
+        p->adj_waves = wv;
+        result = gain_vjp(p, E, n_time, gains, img, grad, st, false);   // warm-up (and workspace)
+        float ms = 1e30f;
+        for (int rep = 0; rep < 2 && result == MOFF_OK; ++rep) {
+          if (hipEventRecord(e0, st) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK) result = gain_vjp(p, E, n_time, gains, img, grad, st, false);
+          if (result == MOFF_OK && hipEventRecord(e1, st) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK && hipEventSynchronize(e1) != hipSuccess) result = MOFF_ERR_HIP;
+          float one = 0.f;
+          if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
+          if (result == MOFF_OK) ms = std::min(ms, one);
+        }
+        if (result == MOFF_OK && ms < best_adj) {
+          best_adj = ms;
+          bw = wv;
+          bav = av;
+        }
       }
     }
     (void)hipStreamSynchronize(st);
@@ -909,11 +934,13 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
     p->variant = saved_v;
     p->slices = saved_s;
     p->adj_waves = 1;
+    p->adj_variant = saved_v;
     return result;
   }
   p->variant = bv;
   p->slices = bs;
   p->adj_waves = bw;
+  p->adj_variant = bav;
   p->tuned = true;
   return MOFF_OK;
 }

@@ -263,8 +263,22 @@ __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& s
   }
 }
 
-// Output pixel coordinates (r, m) of accumulator `idx` for this lane; the
+// Output pixel coordinates (r, m) of accumulator `idx` for thread `tid`; the
 // same mapping col_stage hands to its sink.
+template <int N, int V>
+__host__ __device__ __forceinline__ void acc_pixel_of(int tid, int idx, int& r, int& col) {
+  using C = FT<N, V>;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int q2 = idx % C::QC;
+  const int jb = (idx / C::QC) % C::JB;
+  const int s = (idx / (C::QC * C::JB)) % 2;
+  const int cs = idx / (C::QC * C::JB * 2);
+  const int j = lane / C::CPW + C::LPC * jb;
+  col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
+  r = 2 * j + s + C::PC * q2;
+}
+
+// The same for this lane.
 template <int N, int V>
 __device__ __forceinline__ void acc_pixel(int idx, int& r, int& col) {
   using C = FT<N, V>;
@@ -348,12 +362,15 @@ __device__ __forceinline__ void col_stage_adjoint(float2* G, const float2* twc, 
 }
 
 // Column stage followed by its adjoint, column by column in place: the forward
-// pruned column DFT, each output pixel scaled by this lane's sensitivity
-// rr[acc_index] (the pixels col_stage hands to its sink), and the adjoint back
-// to Z'[iy][m] for iy < L.  The same as col_stage into a buffer, a pixel-wise
-// product and col_stage_adjoint from it, without holding the column's outputs.
-template <int N, int V>
-__device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc, const float (&rr)[FT<N, V>::NACC]) {
+// pruned column DFT, each output pixel scaled by its sensitivity, and the
+// adjoint back to Z'[iy][m] for iy < L.  The same as col_stage into a buffer,
+// a pixel-wise product and col_stage_adjoint from it, without holding the
+// column's outputs.  The sensitivities of pass-B job (cs, s, jb) -- the QC
+// pixels col_stage hands to its sink with accumulator indices
+// ((cs * 2 + s) * JB + jb) * QC + q2 -- come from rload(cs, s, jb, r), called
+// before that job's forward transform so that a load from memory overlaps it.
+template <int N, int V, class RLoad>
+__device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc, RLoad&& rload) {
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::CPW;
@@ -398,15 +415,14 @@ __device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc
       for (int jb = 0; jb < C::JB; ++jb) {
         const int j = sub + C::LPC * jb;
         const int q1 = 2 * j + s;
+        float rr[C::QC];
+        rload(cs, s, jb, rr);
         float2 v[C::QC];
 #pragma unroll
         for (int k = 0; k < C::QC; ++k) v[k] = Zb[(C::LPC * jb * C::QC + k) * C::P];
         Dft<C::QC>::run(v);
 #pragma unroll
-        for (int q2 = 0; q2 < C::QC; ++q2) {
-          const float r = rr[((cs * 2 + s) * C::JB + jb) * C::QC + q2];
-          v[q2] = make_float2(v[q2].x * r, v[q2].y * r);
-        }
+        for (int q2 = 0; q2 < C::QC; ++q2) v[q2] = make_float2(v[q2].x * rr[q2], v[q2].y * rr[q2]);
         idft<C::QC>(v);
 #pragma unroll
         for (int n2 = 0; n2 < C::QC; ++n2) {
@@ -479,6 +495,54 @@ __device__ __forceinline__ void row_stage_adjoint(float2* G, const float2* twr, 
         if constexpr (C::SX > 1) o = c_mul_conj(o, fin[n1]);
         R[sub + C::LPR * ja + C::QR * n1] = o;
       }
+    }
+    wave_sync();
+  }
+}
+
+// Row stage adjoint of column class W known at compile time (the adjoint of
+// row_stage_w): the fold factor of output n' < NZR is conj(w_N^{QR n1 W}),
+// applied as a constant rotation.
+template <int N, int V, int W>
+__device__ __forceinline__ void row_stage_adjoint_w(float2* G, const float2* twr) {
+  using C = FT<N, V>;
+  constexpr bool kFold = C::SX > 1 && W != 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int sub = lane / C::RPW;
+#pragma unroll
+  for (int rs = 0; rs < C::RSTEPS; ++rs) {
+    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    if (C::RGUARD && row >= C::L) continue;
+    float2* R = G + row * C::P;
+    float2 y[C::JBR][C::QR];
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb)
+#pragma unroll
+      for (int q2 = 0; q2 < C::QR; ++q2) y[jb][q2] = R[sub + C::LPR * jb + C::PR * q2];
+    wave_sync();
+#pragma unroll
+    for (int jb = 0; jb < C::JBR; ++jb) {
+      const int q1 = sub + C::LPR * jb;
+      idft<C::QR>(y[jb]);
+#pragma unroll
+      for (int n2 = 0; n2 < C::QR; ++n2) {
+        if (kFold || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twr[q1 * C::QR + n2]);
+        R[q1 * C::QR + n2] = y[jb][n2];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int ja = 0; ja < C::JAR; ++ja) {
+      float2 x[C::PR];
+#pragma unroll
+      for (int q1 = 0; q1 < C::PR; ++q1) x[q1] = R[sub + C::LPR * ja + q1 * C::QR];
+      idft<C::PR>(x);
+      static_for<0, C::PRNZ>([&](auto nc) {
+        constexpr int n1 = decltype(nc)::value;
+        float2 o = x[n1];
+        if constexpr (kFold) o = rot<N / C::QR, -(n1 * W)>(o);
+        R[sub + C::LPR * ja + C::QR * n1] = o;
+      });
     }
     wave_sync();
   }

@@ -20,6 +20,7 @@ struct FusedArgs {
   const void* E;               // [T][C][n_ant] c64 or ci4
   const float2* gains;         // [C][n_ant] or nullptr
   const uint4* prog;           // [SX][prog_len / 4][NT] (HostPlan::Variant::prog4)
+  const float4* progw;         // entry weights laid out like prog (HostPlan::Variant::progw) or nullptr
   const int* cell0;            // [SX][NT] first folded cell of each lane
   int prog_len;
   const float2* weights;       // [SX][n_weights]
@@ -185,13 +186,14 @@ struct AdjFusedArgs {
   const void* E;               // [T][C][n_ant] c64 or ci4
   const float2* gains;         // [C][n_ant] or nullptr
   const uint4* prog;           // [SX][prog_len / 4][NT] (the forward gather program)
+  const float4* progw;         // its entry weights, or nullptr
   const int* cell0;            // [SX][NT]
   int prog_len;
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]
   const uint32_t* slots;       // [NT][kAdjSlots][2] (HostPlan::Variant::slots)
-  const float* R;              // [C][N][N] dL/dI
+  const float* Rl;             // [C][SX][NACC * NT] dL/dI per lane (launch_adjoint_sensitivity)
   int n_ant, n_chan, n_taps;
   int64_t n_time;
   int slices;
@@ -201,6 +203,13 @@ struct AdjFusedArgs {
 int adjoint_waves_max(int N);
 hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int wps, int grid, hipStream_t st);
 int adjoint_fused_blocks_per_cu(int N, int V, bool ci4, int wps, size_t lds);
+// Values one channel's workgroups of shape variant V hold per lane, summed
+// over the lanes and output classes: SX * NACC * NT (at least N^2; more where
+// some lanes of a small grid own no column).  The size, per channel and time
+// slice, of the blocked-accumulation running sums and of Rl.
+size_t fused_lane_values(int N, int V);
+// Rl [C][fused_lane_values(N, V)] for shape variant V from R [C][N][N].
+hipError_t launch_adjoint_sensitivity(const float* R, int N, int V, int n_chan, float* Rl, hipStream_t st);
 // Q[c][a] = sum_t |E[t][c][a]|^2 (float64); D[c][a] = sum_k Dp[k][c][a] over `parts` partials.
 hipError_t launch_antenna_power(const void* E, bool ci4, int64_t n_time, int n_chan, int n_ant, double* Q,
                                 hipStream_t st);

@@ -26,6 +26,9 @@
 #ifndef GATHER_BATCH_256
 #define GATHER_BATCH_256 16
 #endif
+#ifndef GATHER_BATCH_128
+#define GATHER_BATCH_128 24
+#endif
 #ifndef GATHER_SUB_128
 #define GATHER_SUB_128 4
 #endif
@@ -51,47 +54,65 @@ __device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
 // tap weight, and stores each finished cell sum.  Every folded cell is written.
 // A lane's cells are consecutive in row-major order from its first cell, so
 // an entry carries only the antenna slot, the weight index and a "cell
-// complete" bit (4 bytes), and the k-th store of a lane goes to cell
-// cell0 + k.  The program sits in global memory (L2-resident: it is the same
-// for every frame) and is read B entries at a time, four per 16-byte load;
-// entries past the program's end read as padding (the zero sample, no store),
-// so a batch has no trip-count branches.  The samples, weights and grid are
-// disjoint LDS arrays (restrict), and the samples and weights of S entries are
-// read before any of their stores: a conditional store starts a new basic
-// block, and reads placed after it would each wait for a full LDS round trip.
-template <int NT, int B, int S, int NZR, int ZP>
-__device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, int prog_len, int cell0,
-                                             const float2* __restrict__ e, const float2* __restrict__ W,
-                                             float2* __restrict__ G, uint32_t zero_entry) {
+// complete" bit (4 bytes, four per 16-byte load), and the k-th store of a lane
+// goes to cell cell0 + k.  With real weights (RW) each entry's weight comes
+// with it from the program (progw), which halves the LDS reads -- the
+// gather's limit -- and the multiply-adds; otherwise it is looked up in the
+// LDS weight table W.  The program sits in global memory (L2-resident: it is
+// the same for every frame) and is read B entries at a time; entries past the
+// program's end read as padding (the zero sample, no store), so a batch has no
+// trip-count branches.  The samples, weights and grid are disjoint LDS arrays
+// (restrict), and the LDS values of S entries are read before any of their
+// stores: a conditional store starts a new basic block, and reads placed after
+// it would each wait for a full LDS round trip.
+template <int NT, int B, int S, int NZR, int ZP, bool RW>
+__device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, const float4* __restrict__ progw,
+                                             int prog_len, int cell0, const float2* __restrict__ e,
+                                             const float2* __restrict__ W, float2* __restrict__ G,
+                                             uint32_t zero_entry) {
   static_assert(B % 4 == 0 && B % S == 0, "batches hold whole 16-byte loads and LDS sub-batches");
   float2 acc = make_float2(0.f, 0.f);
   int cell = cell0;
   const int len4 = prog_len / 4;
   for (int k0 = 0; k0 < len4; k0 += B / 4) {
     uint32_t ent[B];
+    float wt[RW ? B : 1];
 #pragma unroll
     for (int j = 0; j < B / 4; ++j) {
-      uint4 q = prog[static_cast<size_t>(min(k0 + j, len4 - 1)) * NT];
+      const size_t at = static_cast<size_t>(min(k0 + j, len4 - 1)) * NT;
+      uint4 q = prog[at];
       if (k0 + j >= len4) q = make_uint4(zero_entry, zero_entry, zero_entry, zero_entry);
       ent[4 * j] = q.x;
       ent[4 * j + 1] = q.y;
       ent[4 * j + 2] = q.z;
       ent[4 * j + 3] = q.w;
+      if constexpr (RW) {
+        const float4 qw = progw[at];
+        wt[4 * j] = qw.x;
+        wt[4 * j + 1] = qw.y;
+        wt[4 * j + 2] = qw.z;
+        wt[4 * j + 3] = qw.w;
+      }
     }
 #pragma unroll
     for (int s0 = 0; s0 < B; s0 += S) {
-      float2 ev[S], wv[S];
+      float2 ev[S], wv[RW ? 1 : S];
 #pragma unroll
       for (int i = 0; i < S; ++i) {
         ev[i] = e[ent[s0 + i] & 0xFFFu];
-        wv[i] = W[(ent[s0 + i] >> 12) & 0x7FFu];
+        if constexpr (!RW) wv[i] = W[(ent[s0 + i] >> 12) & 0x7FFu];
       }
 #pragma unroll
       for (int i = 0; i < S; ++i) {
-        acc.x = fmaf(ev[i].x, wv[i].x, fmaf(-ev[i].y, wv[i].y, acc.x));
-        acc.y = fmaf(ev[i].x, wv[i].y, fmaf(ev[i].y, wv[i].x, acc.y));
+        if constexpr (RW) {
+          acc.x = fmaf(ev[i].x, wt[s0 + i], acc.x);
+          acc.y = fmaf(ev[i].y, wt[s0 + i], acc.y);
+        } else {
+          acc.x = fmaf(ev[i].x, wv[i].x, fmaf(-ev[i].y, wv[i].y, acc.x));
+          acc.y = fmaf(ev[i].x, wv[i].y, fmaf(ev[i].y, wv[i].x, acc.y));
+        }
         if (ent[s0 + i] & kStoreBit) {
-          G[cell + (cell / NZR) * (ZP - NZR)] = acc;   // folded cell (iy, n') at iy ZP + n'
+          G[cell + (cell / NZR) * (ZP - NZR)] = acc;   // folded cell (a, n') at a ZP + n'
           ++cell;
           acc = make_float2(0.f, 0.f);
         }
@@ -100,13 +121,25 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, int
   }
 }
 
+// The gather with the weight path the plan provides (a uniform branch).
+template <int NT, int B, int S, int NZR, int ZP>
+__device__ __forceinline__ void gather_frame_any(const uint4* __restrict__ prog, const float4* __restrict__ progw,
+                                                 int prog_len, int cell0, const float2* __restrict__ e,
+                                                 const float2* __restrict__ W, float2* __restrict__ G,
+                                                 uint32_t zero_entry) {
+  if (progw)
+    gather_frame<NT, B, S, NZR, ZP, true>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+  else
+    gather_frame<NT, B, S, NZR, ZP, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+}
+
 // Entries per batch of program reads (B) and per LDS sub-batch (S).  At
 // N = 128 the program (about 20 entries per lane) fits one batch, and the
 // registers it takes are free during the gridding (the transform's
 // temporaries are not live then).
 template <int N, int V = 0>
 constexpr int gather_batch() {
-  return N == 128 ? 24 : N == 256 ? GATHER_BATCH_256 : 8;
+  return N == 128 ? GATHER_BATCH_128 : N == 256 ? GATHER_BATCH_256 : 8;
 }
 template <int N, int V = 0>
 constexpr int gather_sub() {
@@ -180,6 +213,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
 
   const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
   const uint4* prog = a.prog + static_cast<size_t>(W) * (a.prog_len / 4) * NT + tid;
+  const float4* progw = a.progw ? a.progw + static_cast<size_t>(W) * (a.prog_len / 4) * NT + tid : nullptr;
   const int cell0 = a.cell0[W * NT + tid];
 
   float acc[C::NACC];
@@ -219,8 +253,8 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
       if (tid + k * NT < a.n_ant) take(tid + k * NT, raw[k].value());
     for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
     __syncthreads();
-    gather_frame<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, a.prog_len, cell0, e, Wt, G,
-                                                                           static_cast<uint32_t>(a.n_ant));
+    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0, e,
+                                                                               Wt, G, static_cast<uint32_t>(a.n_ant));
     // the next frame's samples load while this frame is transformed (after
     // the gather, so that its program loads do not wait for them)
     if (t + 1 < t1) {
@@ -324,99 +358,95 @@ void fused_kernel(FusedArgs a) {
 // fused gain adjoint
 // ---------------------------------------------------------------------------
 
-// WPS: the least number of waves per SIMD the registers are sized for (1: as
-// many registers as the kernel wants).  At N = 256 the kernel wants more than
-// two waves' worth: WPS = 1 keeps the excess in the accumulation registers (one
-// wave per SIMD), WPS = 2 spills it to scratch memory and runs two.  At
-// N = 128 it wants two waves' worth, and WPS = 3 spills a little to run three.
-// Which is faster depends on the workload, so these are built and the plan's
-// autotuner picks one.
-template <int N, int V, bool CI4, int WPS>
-__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(WPS)))
-void adjoint_fused_kernel(AdjFusedArgs a) {
+// One work item of the fused gain adjoint: output class W (compile-time, as in
+// the forward kernel), channel c and a slice of time samples.  Per frame, in
+// LDS: ingest, gather-gridding with the forward program, the row stage, the
+// column round trip (forward column DFT, each pixel times its sensitivity,
+// adjoint column DFT), the row-stage adjoint and the degridding of this lane's
+// antennas.  The sensitivities come from memory per column job (Rl, laid out
+// by adjoint_sensitivity_kernel so that each lane's values are contiguous),
+// not from registers held for the whole launch.
+template <int N, int V, bool CI4, int W>
+__device__ __forceinline__ void adjoint_item(const AdjFusedArgs& a, float2* lds, int c, int slice) {
   using C = FT<N, V>;
   constexpr int NT = C::NT;
-  extern __shared__ float2 lds[];
   const int tid = threadIdx.x;
 
   float2* G = lds;                          // [L][P], row pitch P = M + 1
   float2* twr = G + C::GRID;                // [PR * QR]
   float2* twc = twr + C::TWR;               // [PC * QC]
-  float2* W = twc + C::TWC;                 // [n_weights]
-  float2* gl = W + a.n_weights;             // [n_ant] gains of the current channel
+  float2* Wt = twc + C::TWC;                // [n_weights]
+  float2* gl = Wt + a.n_weights;            // [n_ant] gains of the current channel
   float2* e = gl + a.n_ant;                 // [n_ant + 1], last slot stays zero
 
-  const int item = blockIdx.x;
-  if (item >= C::SX * a.n_chan * a.slices) return;
-  const int w = item % C::SX;
-  const int c = (item / C::SX) % a.n_chan;
-  const int slice = item / (C::SX * a.n_chan);
-  const size_t img_stride = static_cast<size_t>(N) * N;
-
-  build_twiddles<N, V>(a.tw, w, twr, twc);
-  float2 fin[C::PRNZ];
-  fold_factors<N, V>(a.tw, w, fin);
-  for (int i = tid; i < a.n_weights; i += NT) W[i] = a.weights[static_cast<size_t>(w) * a.n_weights + i];
+  build_twiddles<N, V>(a.tw, W, twr, twc);
+  for (int i = tid; i < a.n_weights; i += NT) Wt[i] = a.weights[static_cast<size_t>(W) * a.n_weights + i];
   for (int i = tid; i < a.n_ant; i += NT)
     gl[i] = a.gains ? a.gains[static_cast<size_t>(c) * a.n_ant + i] : make_float2(1.f, 0.f);
   if (tid == 0) e[a.n_ant] = make_float2(0.f, 0.f);
 
-  // sensitivities of the pixels this lane's column stage produces
-  float rr[C::NACC];
-  const float* Rc = a.R + static_cast<size_t>(c) * img_stride;
-#pragma unroll
-  for (int idx = 0; idx < C::NACC; ++idx) {
-    int r, col;
-    acc_pixel<N, V>(idx, r, col);
-    // transposed aperture, as in the forward kernel: image row SX col + w, image column r
-    rr[idx] = (C::CGUARD && col >= C::M)
-                  ? 0.f
-                  : Rc[static_cast<size_t>((C::SX * col + w + N / 2) & (N - 1)) * N + ((r + N / 2) & (N - 1))];
-  }
+  // this lane's sensitivities, in the layout of adjoint_sensitivity_kernel
+  const float* Rlane = a.Rl + (static_cast<size_t>(c) * C::SX + W) * C::NACC * NT;
 
-  // this lane's antennas for the degridding
-  uint32_t s0[kAdjSlots], s1[kAdjSlots];
+  // this lane's antennas for the degridding (their descriptors and samples are
+  // read again at the degridding, not held through the transforms)
   double2 D[kAdjSlots];
 #pragma unroll
-  for (int s = 0; s < kAdjSlots; ++s) {
-    s0[s] = a.slots[(static_cast<size_t>(tid) * kAdjSlots + s) * 2];
-    s1[s] = a.slots[(static_cast<size_t>(tid) * kAdjSlots + s) * 2 + 1];
-    D[s] = make_double2(0.0, 0.0);
-  }
+  for (int s = 0; s < kAdjSlots; ++s) D[s] = make_double2(0.0, 0.0);
+  const uint2* slots = reinterpret_cast<const uint2*>(a.slots) + static_cast<size_t>(tid) * kAdjSlots;
 
   const int64_t T = a.n_time;
   const int64_t t0 = slice * T / a.slices, t1 = (slice + 1) * T / a.slices;
   const size_t frame_stride = static_cast<size_t>(a.n_chan) * a.n_ant;
-  const uint4* prog = a.prog + static_cast<size_t>(w) * (a.prog_len / 4) * NT + tid;
-  const int cell0 = a.cell0[w * NT + tid];
+  const uint4* prog = a.prog + static_cast<size_t>(W) * (a.prog_len / 4) * NT + tid;
+  const float4* progw = a.progw ? a.progw + static_cast<size_t>(W) * (a.prog_len / 4) * NT + tid : nullptr;
+  const int cell0 = a.cell0[W * NT + tid];
 
   __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
     for (int i = tid; i < a.n_ant; i += NT) e[i] = c_mul(gl[i], load_sample(a.E, base + i, CI4));
+    __syncthreads();
+    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0, e,
+                                                                               Wt, G, static_cast<uint32_t>(a.n_ant));
+    __syncthreads();
+    row_stage_w<N, V, W>(G, twr);
+    __syncthreads();
+    col_stage_roundtrip<N, V>(G, twc, [&](int cs, int s, int jb, float (&rr)[C::QC]) {
+      const int idx0 = ((cs * 2 + s) * C::JB + jb) * C::QC;
+      if constexpr (C::QC % 4 == 0) {
+#pragma unroll
+        for (int k = 0; k < C::QC / 4; ++k) {
+          const float4 q = reinterpret_cast<const float4*>(Rlane)[static_cast<size_t>(idx0 / 4 + k) * NT + tid];
+          rr[4 * k] = q.x;
+          rr[4 * k + 1] = q.y;
+          rr[4 * k + 2] = q.z;
+          rr[4 * k + 3] = q.w;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < C::QC; ++k) rr[k] = Rlane[static_cast<size_t>(idx0 + k) * NT + tid];
+      }
+    });
+    __syncthreads();
+    // this lane's antennas and their raw samples load while the row-stage adjoint runs
+    uint2 sl[kAdjSlots];
     float2 Er[kAdjSlots];
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s) {
-      const uint32_t ant = s0[s] & 0xFFFu;
+      sl[s] = slots[s];
+      const uint32_t ant = sl[s].x & 0xFFFu;
       Er[s] = ant != kAdjEmpty ? load_sample(a.E, base + ant, CI4) : make_float2(0.f, 0.f);
     }
-    __syncthreads();
-    gather_frame<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, a.prog_len, cell0, e, W, G,
-                                                                           static_cast<uint32_t>(a.n_ant));
-    __syncthreads();
-    row_stage<N, V>(G, twr, fin);
-    __syncthreads();
-    col_stage_roundtrip<N, V>(G, twc, rr);
-    __syncthreads();
-    row_stage_adjoint<N, V>(G, twr, fin);
+    row_stage_adjoint_w<N, V, W>(G, twr);
     __syncthreads();
     // degridding: d = sum over the footprint of conj(weight) G', then D += conj(E) d
 #pragma unroll
     for (int s = 0; s < kAdjSlots; ++s) {
-      const uint32_t ant = s0[s] & 0xFFFu;
+      const uint32_t ant = sl[s].x & 0xFFFu;
       if (ant == kAdjEmpty) continue;
-      const int off = (s0[s] >> 12) & 0xFFFu, k = (s0[s] >> 24) & 0xFu;
-      const int ix0 = s1[s] & 0xFFFFu, iy0 = s1[s] >> 16;
+      const int off = (sl[s].x >> 12) & 0xFFFu, k = (sl[s].x >> 24) & 0xFu;
+      const int ix0 = sl[s].y & 0xFFFFu, iy0 = sl[s].y >> 16;
       float dx = 0.f, dy = 0.f;
       // transposed aperture: folded-grid row ix, folded axis along y
       for (int v = 0; v < k; ++v) {
@@ -425,7 +455,7 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
           const int iy = iy0 + u;
           const int j = iy / C::M, n = iy - j * C::M;
           const float2 g = Grow[n];
-          const float2 wt = W[j * a.n_taps + off + u * k + v];
+          const float2 wt = Wt[j * a.n_taps + off + u * k + v];
           dx = fmaf(g.x, wt.x, fmaf(g.y, wt.y, dx));
           dy = fmaf(g.y, wt.x, fmaf(-g.x, wt.y, dy));
         }
@@ -436,10 +466,62 @@ void adjoint_fused_kernel(AdjFusedArgs a) {
   }
 #pragma unroll
   for (int s = 0; s < kAdjSlots; ++s) {
-    const uint32_t ant = s0[s] & 0xFFFu;
+    const uint32_t ant = slots[s].x & 0xFFFu;
     if (ant == kAdjEmpty) continue;
-    a.Dp[(static_cast<size_t>(slice * C::SX + w) * a.n_chan + c) * a.n_ant + ant] = D[s];
+    a.Dp[(static_cast<size_t>(slice * C::SX + W) * a.n_chan + c) * a.n_ant + ant] = D[s];
   }
+}
+
+// WPS: the least number of waves per SIMD the registers are sized for (1: as
+// many registers as the kernel wants).  Built where it fits and chosen by the
+// plan's autotuner together with the shape variant.
+template <int N, int V, bool CI4, int WPS>
+__global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(WPS)))
+void adjoint_fused_kernel(AdjFusedArgs a) {
+  using C = FT<N, V>;
+  extern __shared__ float2 lds[];
+  const int item = blockIdx.x;
+  if (item >= C::SX * a.n_chan * a.slices) return;
+  const int w = item % C::SX;
+  const int c = (item / C::SX) % a.n_chan;
+  const int slice = item / (C::SX * a.n_chan);
+  static_for<0, C::SX>([&](auto wc) {
+    constexpr int W = decltype(wc)::value;
+    if (w == W) adjoint_item<N, V, CI4, W>(a, lds, c, slice);
+  });
+}
+
+// Sensitivities dL/dI [C][N][N] rearranged per (channel, output class) so that
+// each lane of the fused adjoint reads its column-job values contiguously:
+// Rl[c][w] holds NACC x NT floats, accumulator index idx of thread tid at
+// ((idx / 4) NT + tid) 4 + idx % 4 when QC is a multiple of 4 (one 16-byte
+// load per 4 values), else at idx NT + tid.  The pixel of (w, tid, idx) is the
+// one the fused kernels' column stage produces there (transposed aperture:
+// image row SX col + w, image column r); columns past M read 0.
+template <int N, int V>
+__global__ __launch_bounds__(256) void adjoint_sensitivity_kernel(const float* R, int n_chan, float* Rl) {
+  using C = FT<N, V>;
+  const size_t per_class = static_cast<size_t>(C::NACC) * C::NT;
+  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= per_class * C::SX * n_chan) return;
+  const size_t cw = i / per_class, k = i % per_class;
+  const int c = static_cast<int>(cw / C::SX), w = static_cast<int>(cw % C::SX);
+  int idx, tid;
+  if constexpr (C::QC % 4 == 0) {
+    idx = static_cast<int>((k / (4 * C::NT)) * 4 + k % 4);
+    tid = static_cast<int>((k / 4) % C::NT);
+  } else {
+    idx = static_cast<int>(k / C::NT);
+    tid = static_cast<int>(k % C::NT);
+  }
+  int r, col;
+  acc_pixel_of<N, V>(tid, idx, r, col);
+  float v = 0.f;
+  if (!(C::CGUARD && col >= C::M)) {
+    const int pr = (C::SX * col + w + N / 2) & (N - 1), pq = (r + N / 2) & (N - 1);
+    v = R[(static_cast<size_t>(c) * N + pr) * N + pq];
+  }
+  Rl[i] = v;
 }
 
 // One thread per (channel, antenna): Q = sum_t |E|^2 in float64.
@@ -818,9 +900,7 @@ const void* adjoint_fused_symbol_v(bool ci4, int wps) {
 const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4, int wps) {
   auto pick = [&](auto nc) -> const void* {
     constexpr int NN = decltype(nc)::value;
-    // variant 0 only: at N = 256 variant 1's 512-thread workgroups would spill the
-    // column round trip's state (forward inputs, adjoint sums, pixel sensitivities)
-    return V == 0 ? adjoint_fused_symbol_v<NN, 0>(ci4, wps) : nullptr;
+    return V == 0 ? adjoint_fused_symbol_v<NN, 0>(ci4, wps) : V == 1 ? adjoint_fused_symbol_v<NN, 1>(ci4, wps) : nullptr;
   };
   switch (N) {
     case 8: return pick(std::integral_constant<int, 8>{});
@@ -836,6 +916,57 @@ const void* adjoint_fused_kernel_symbol(int N, int V, bool ci4, int wps) {
 }  // namespace
 
 int adjoint_waves_max(int N) { return N == 128 ? 3 : N == 256 ? 2 : 1; }
+
+size_t fused_lane_values(int N, int V) {
+  auto go = [&](auto nc, auto vc) -> size_t {
+    constexpr int NN = decltype(nc)::value, VV = decltype(vc)::value;
+    if constexpr (frame_shape(NN, VV).N == NN) {
+      using C = FT<NN, VV>;
+      return static_cast<size_t>(C::SX) * C::NACC * C::NT;
+    } else {
+      return 0;
+    }
+  };
+  auto pick = [&](auto nc) -> size_t {
+    return V == 0 ? go(nc, std::integral_constant<int, 0>{}) : V == 1 ? go(nc, std::integral_constant<int, 1>{}) : 0;
+  };
+  switch (N) {
+    case 8: return pick(std::integral_constant<int, 8>{});
+    case 16: return pick(std::integral_constant<int, 16>{});
+    case 32: return pick(std::integral_constant<int, 32>{});
+    case 64: return pick(std::integral_constant<int, 64>{});
+    case 128: return pick(std::integral_constant<int, 128>{});
+    case 256: return pick(std::integral_constant<int, 256>{});
+    default: return 0;
+  }
+}
+
+hipError_t launch_adjoint_sensitivity(const float* R, int N, int V, int n_chan, float* Rl, hipStream_t st) {
+  auto go = [&](auto nc, auto vc) -> hipError_t {
+    constexpr int NN = decltype(nc)::value, VV = decltype(vc)::value;
+    if constexpr (frame_shape(NN, VV).N == NN) {
+      using C = FT<NN, VV>;
+      const size_t n = static_cast<size_t>(C::SX) * C::NACC * C::NT * n_chan;
+      hipLaunchKernelGGL((adjoint_sensitivity_kernel<NN, VV>), dim3(blocks_for(n)), dim3(256), 0, st, R, n_chan, Rl);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  };
+  auto pick = [&](auto nc) -> hipError_t {
+    return V == 0 ? go(nc, std::integral_constant<int, 0>{}) : V == 1 ? go(nc, std::integral_constant<int, 1>{})
+                                                                      : hipErrorInvalidValue;
+  };
+  switch (N) {
+    case 8: return pick(std::integral_constant<int, 8>{});
+    case 16: return pick(std::integral_constant<int, 16>{});
+    case 32: return pick(std::integral_constant<int, 32>{});
+    case 64: return pick(std::integral_constant<int, 64>{});
+    case 128: return pick(std::integral_constant<int, 128>{});
+    case 256: return pick(std::integral_constant<int, 256>{});
+    default: return hipErrorInvalidValue;
+  }
+}
 
 hipError_t launch_adjoint_fused(const AdjFusedArgs& a, int N, int V, bool ci4, int wps, int grid, hipStream_t st) {
   const void* k = adjoint_fused_kernel_symbol(N, V, ci4, wps);

@@ -511,6 +511,18 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         for (int lane = 0; lane < S.NT; ++lane)
           V.prog4[((static_cast<size_t>(w) * K4 + k / 4) * S.NT + lane) * 4 + k % 4] =
               V.prog[(static_cast<size_t>(w) * V.prog_len + k) * S.NT + lane].x;
+    // real weights: each entry's weight next to it (the all-zero slot's entries get 0)
+    bool real = true;
+    for (size_t i = 1; i < V.weights.size(); i += 2) real = real && V.weights[i] == 0.f;
+    if (real) {
+      V.progw.assign(V.prog4.size(), 0.f);
+      for (size_t i = 0; i < V.prog4.size(); ++i) {
+        const uint32_t x = V.prog4[i];
+        const int w = static_cast<int>(i / (static_cast<size_t>(K4) * S.NT * 4));
+        const uint32_t wi = (x >> 12) & 0x7FFu;
+        V.progw[i] = (x & 0xFFFu) == zero_slot ? 0.f : V.weights[(static_cast<size_t>(w) * V.n_weights() + wi) * 2];
+      }
+    }
     build_adjoint_slots(P, S.NT, &V.slots);
     P.variants.push_back(std::move(V));
   }

@@ -74,6 +74,10 @@ struct HostPlan {
     // cells (iy, n') in row-major order from its first cell cell0[w][lane].
     std::vector<uint32_t> prog4;
     std::vector<int32_t> cell0;              // [SX][NT]
+    // When every weight of every class is real (real tables, no fold factor),
+    // progw holds each entry's weight, laid out like prog4, so the kernel
+    // reads it with the entry instead of looking it up in LDS; else empty.
+    std::vector<float> progw;
     std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
     int n_weights() const { return NJ * n_taps_; }
     int n_taps_ = 0;

@@ -205,6 +205,22 @@ def test_long_integration_one_slice(torch, moff):
     assert e_inf <= 2e-6, f"accumulation error {e_inf:.3g}: float32 sums are not blocked"
 
 
+@pytest.mark.parametrize("N", [8, 16])
+def test_blocked_accumulation_small_grids(torch, moff, N):
+    """Grids whose workgroups have lanes without a column (the running sums
+    hold more values than pixels): 600 samples in one slice, so the float32
+    sums are folded into the float64 running sums twice."""
+    rng = np.random.default_rng(N)
+    w = synth.random_case(N, 5, N, 2, 600, [synth.random_kernel(rng, 2)], extent_m=N / 6.0, cell_m=1.0)
+    ref, pbar = oracle_channels(w, range(2))
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        p.set_config(0, 1)
+        got = p.image(to_dev(torch, w.E), gains=to_dev(torch, w.gains))
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+    assert_image_close(got, ref, pbar, label=f"N={N} blocked")
+
+
 def test_finalize_long_integration_count(torch, moff):
     """moff_finalize only scales and subtracts: a total sample count beyond
     2^31 / n_chan (a long streamed integration) is accepted and gives
@@ -315,15 +331,32 @@ def test_autotune_and_graph_replay(torch, moff):
 @pytest.mark.parametrize("cfg,chans", [(3, [0, 511, 1023]), (5, [0, 255])])
 def test_full_size_sampled_channels(torch, moff, cfg, chans):
     """HERA-shaped and calibration workloads at full size (every channel imaged in
-    one launch, autotuned), checked on channels the oracle computes one by one."""
+    one launch, autotuned), checked on channels the oracle computes one by one.
+    The same autotuned launch captured in a HIP graph gives the eager result
+    bitwise on three replays, with eager work between them."""
     w = synth.make_config(cfg)
     with moff.Plan.from_geometry(w.geom, device=0) as p:
         E = to_dev(torch, w.E)
         g = to_dev(torch, w.gains) if w.gains is not None else None
         p.autotune(E, g)
-        got = p.image(E, g)
+        out = p.image(E, g)                     # also sizes the workspace before capture
         torch.cuda.synchronize()
-        got = got.cpu().numpy()
+        eager = out.clone()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                p.image(E, g, out=out, stream=s)
+        torch.cuda.current_stream().wait_stream(s)
+        for rep in range(3):
+            out.fill_(float("nan"))             # eager work between replays
+            torch.cuda.synchronize()
+            graph.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), f"config {cfg}: graph replay {rep} differs from the eager call"
+        got = eager.cpu().numpy()
+        del graph
     assert np.isfinite(got).all()
     ref, pbar = oracle_channels(w, chans)
     assert_image_close(got[chans], ref, pbar, label=f"config{cfg} full")
