@@ -291,12 +291,21 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
     }
   }
 
+  // (its barriers also end every wave's use of the folded grid)
   block_sum4<NT>(pw, Atot);
 
   // The transform runs on the transposed aperture (the host plan's programs):
   // its folded axis m is the image row, r = SX m + W, and its column-stage
-  // output index is the image column, so this workgroup owns whole image rows
-  // and every 128-byte line of the output has one writer.
+  // output index is the image column, so this workgroup owns whole image rows.
+  // A lane's pixels are scattered over those rows, so finished float values
+  // are staged in LDS (the grid's space, [M][N + 4] floats) and written out
+  // row by row; only the in-place float64 update of accumulate mode writes
+  // per pixel.  Within a staged row, groups of four pixels are permuted by an
+  // XOR with the row's swizzle (a multiple of 4), which spreads one store
+  // instruction's 16 rows over the LDS banks.
+  float* stage = reinterpret_cast<float*>(lds);
+  static_assert(C::M * N * sizeof(float) <= C::GRID * sizeof(float2), "staging must fit in the grid");
+  auto swz = [](int col) { return (col << 2) & (N - 4); };
 #pragma unroll
   for (int idx = 0; idx < C::NACC; ++idx) {
     int r, col;
@@ -309,7 +318,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
                        (flushed ? __hip_atomic_load(run64 + idx * NT + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                 : 0.0);
     if (a.mode == kModePartial) {
-      a.out[(static_cast<size_t>(slice) * a.n_chan + c) * img_stride + pix] = static_cast<float>(sum);
+      stage[col * N + (pq ^ swz(col))] = static_cast<float>(sum);
     } else if (a.mode == kModeAccum) {
       float& o = a.out[static_cast<size_t>(c) * img_stride + pix];
       o = static_cast<float>(static_cast<double>(o) + sum);
@@ -317,7 +326,25 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
       double v = sum;
       if (a.subtract)
         for (int p = 0; p < a.n_types; ++p) v -= Atot[p] * a.Pp[p * img_stride + pix];
-      a.out[static_cast<size_t>(c) * img_stride + pix] = static_cast<float>(v * a.scale);
+      stage[col * N + (pq ^ swz(col))] = static_cast<float>(v * a.scale);
+    }
+  }
+  if (a.mode != kModeAccum) {
+    __syncthreads();
+    float* dst = a.out + (a.mode == kModePartial ? (static_cast<size_t>(slice) * a.n_chan + c) : static_cast<size_t>(c)) *
+                             img_stride;
+    if ((reinterpret_cast<uintptr_t>(dst) & 15) == 0) {
+      for (int i = tid; i < C::M * (N / 4); i += NT) {
+        const int col = i / (N / 4), q = 4 * (i % (N / 4));
+        const int pr = (C::SX * col + W + N / 2) & (N - 1);
+        *reinterpret_cast<float4*>(dst + static_cast<size_t>(pr) * N + q) =
+            *reinterpret_cast<const float4*>(stage + col * N + (q ^ swz(col)));
+      }
+    } else {
+      for (int i = tid; i < C::M * N; i += NT) {
+        const int col = i / N, q = i % N;
+        dst[static_cast<size_t>((C::SX * col + W + N / 2) & (N - 1)) * N + q] = stage[col * N + (q ^ swz(col))];
+      }
     }
   }
   if (W == 0 && tid < a.n_types) {
@@ -332,9 +359,11 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
 // One work item (output class w, channel c, time slice) per workgroup.  (A
 // persistent loop over items makes the compiler keep far more registers live
 // -- 127 -> 256 VGPRs at N = 64 -- so launches are instead sized in whole
-// rounds of resident workgroups by the autotuner.)  The SX classes of one
-// (channel, slice) take workgroup indices kXcds apart, so they run on one XCD
-// and its L2 serves the channel's samples to all of them; the grid pads the
+// rounds of resident workgroups by the autotuner.)  Workgroups are dealt to
+// the XCDs round-robin by index, so the decode gives each XCD a contiguous
+// range of (channel, slice) indices, with the SX classes of one index kXcds
+// apart: the classes share their samples in that XCD's L2, and neighbouring
+// channels share the 128-byte lines their samples straddle.  The grid pads the
 // (channel, slice) count to a multiple of kXcds.
 template <int N, int V, bool CI4>
 __global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<N, V>())))
@@ -342,9 +371,10 @@ void fused_kernel(FusedArgs a) {
   using C = FT<N, V>;
   extern __shared__ float2 lds[];
   __shared__ double Atot[kMaxTypesDev];
-  const int b = blockIdx.x;
-  const int w = (b / kXcds) % C::SX;
-  const int cs = (b / (kXcds * C::SX)) * kXcds + b % kXcds;   // channel-slice index
+  const int b = blockIdx.x, k = b / kXcds;
+  const int per_xcd = gridDim.x / (kXcds * C::SX);            // (channel, slice) indices per XCD
+  const int w = k % C::SX;
+  const int cs = (b % kXcds) * per_xcd + k / C::SX;           // channel-slice index
   if (cs >= a.n_chan * a.slices) return;
   const int c = cs % a.n_chan, slice = cs / a.n_chan;
   const int item = cs * C::SX + w;
@@ -866,6 +896,10 @@ hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hi
   const void* k = fused_kernel_symbol(N, V, ci4);
   if (!k) return hipErrorInvalidValue;
   const FrameShape S = frame_shape(N, V);
+  // the kernel's decode assumes SX classes times a whole number of XCD rounds
+  // covering every (channel, slice)
+  if (grid <= 0 || grid % (S.SX * kXcds) != 0 || static_cast<int64_t>(grid / S.SX) < static_cast<int64_t>(a.n_chan) * a.slices)
+    return hipErrorInvalidValue;
   const size_t lds = fused_lds_bytes(N, V, a.n_weights, a.n_ant);
   hipError_t err = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
   if (err != hipSuccess) return err;
