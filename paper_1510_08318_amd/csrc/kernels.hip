@@ -71,8 +71,9 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
                                              const float2* __restrict__ W, float2* __restrict__ G,
                                              uint32_t zero_entry) {
   static_assert(B % 4 == 0 && B % S == 0, "batches hold whole 16-byte loads and LDS sub-batches");
+  static_assert((NZR & (NZR - 1)) == 0, "folded rows are a power of two long");
   float2 acc = make_float2(0.f, 0.f);
-  int cell = cell0;
+  uint32_t cell = static_cast<uint32_t>(cell0);   // unsigned: the row split below is a shift
   const int len4 = prog_len / 4;
   for (int k0 = 0; k0 < len4; k0 += B / 4) {
     uint32_t ent[B];
@@ -581,27 +582,56 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const double2* Dp, 
   D[i] = make_double2(x, y);
 }
 
-// Sum per-slice partials (pixel order) in slice order; then remove self power
-// and average (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
+// Sum per-slice partials (pixel order) in slice order, four pixels per thread
+// (N^2 is a multiple of 4, and each slice's loads are independent so they are
+// issued four slices at a time); then remove self power and average
+// (MODE_FINAL) or add into the caller's running sums (MODE_ACCUM).
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a) {
   const size_t npix = static_cast<size_t>(a.N) * a.N;
-  const size_t i = static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x;
+  const size_t i = (static_cast<size_t>(blockIdx.x) * 256 + threadIdx.x) * 4;
   if (i >= npix * a.n_chan) return;
   const size_t c = i / npix, pix = i % npix;
-  double s = 0.0;
-  for (int sl = 0; sl < a.slices; ++sl) s += a.S_part[(static_cast<size_t>(sl) * a.n_chan + c) * npix + pix];
+  const size_t stride4 = static_cast<size_t>(a.n_chan) * npix / 4;   // one slice, in float4
+  const float4* src = reinterpret_cast<const float4*>(a.S_part) + i / 4;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  auto add = [&](float4 v) {
+    s[0] += v.x;
+    s[1] += v.y;
+    s[2] += v.z;
+    s[3] += v.w;
+  };
+  int sl = 0;
+  for (; sl + 4 <= a.slices; sl += 4) {
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = src[static_cast<size_t>(sl + k) * stride4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add(v[k]);
+  }
+  for (; sl < a.slices; ++sl) add(src[static_cast<size_t>(sl) * stride4]);
   double A[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
   for (int p = 0; p < a.n_types; ++p)
-    for (int sl = 0; sl < a.slices; ++sl) A[p] += a.A_part[(static_cast<size_t>(sl) * a.n_chan + c) * a.n_types + p];
+    for (int q = 0; q < a.slices; ++q) A[p] += a.A_part[(static_cast<size_t>(q) * a.n_chan + c) * a.n_types + p];
+  float r[4];
   if (a.final_image) {
-    double v = s;
-    if (a.subtract)
-      for (int p = 0; p < a.n_types; ++p) v -= A[p] * a.Pp[p * npix + pix];
-    a.out[i] = static_cast<float>(v * a.scale);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double v = s[k];
+      if (a.subtract)
+        for (int p = 0; p < a.n_types; ++p) v -= A[p] * a.Pp[p * npix + pix + k];
+      r[k] = static_cast<float>(v * a.scale);
+    }
   } else {
-    a.out[i] += static_cast<float>(s);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = a.out[i + k] + static_cast<float>(s[k]);
     if (pix == 0)
       for (int p = 0; p < a.n_types; ++p) a.outA[c * a.n_types + p] += A[p];
+  }
+  if ((reinterpret_cast<uintptr_t>(a.out + i) & 15) == 0) {
+    *reinterpret_cast<float4*>(a.out + i) = make_float4(r[0], r[1], r[2], r[3]);
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.out[i + k] = r[k];
   }
 }
 
@@ -1045,7 +1075,7 @@ int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
 }
 
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(static_cast<size_t>(a.N) * a.N * a.n_chan / 4)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
