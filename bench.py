@@ -41,77 +41,93 @@ PEAK_FP32_TFLOPS = 157.3     # MI355X FP32 vector peak (spec sheet)
 PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec sheet)
 
 # HBM traffic per launch of the timed kernel, measured with rocprofv3 --pmc
-# FETCH_SIZE and, in a second run, WRITE_SIZE on this script (KiB per dispatch;
-# profiles/fused_kernel_lwa_n128.md, profiles/mfma_kernel_lwa_f16_n128.md; the
-# HERA-shaped and calibration workloads in the same two runs of --config 3 / 5).
-# Scaled by what the same counters read for one 256 MiB device copy in the same
-# runs (FETCH_SIZE 131,089 KiB, WRITE_SIZE 262,144 KiB).  All entries are from
-# one set of runs on the current sources.  Keyed by (workload,
-# precision, shape variant, workgroups); valid only for the kernel sources they
-# were measured on, identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "2e00f0131f0f9e31"
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.0, 1.0
+# FETCH_SIZE and, in a second run, WRITE_SIZE on this script with the autotuner
+# on, so that every candidate launch shape is counted (KiB per dispatch; the
+# commands are in profiles/fused_kernel_hera_n256.md).  Scaled by what the same
+# counters read for one 256 MiB device copy in the same runs (FETCH_SIZE
+# 131,093 KiB, WRITE_SIZE 262,144 KiB).  All entries are from one set of runs on
+# the current sources.  Keyed by (workload, precision, shape variant,
+# workgroups); valid only for the kernel sources they were measured on,
+# identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
+TRAFFIC_SOURCES_SHA = "d2398072c85286ee"
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (32977, 16384),
-    (2, "f32", 0, 512): (32433, 16392),
-    (2, "f32", 0, 1024): (32433, 32784),
-    (2, "f32", 0, 2048): (32444, 65568),
-    (2, "f32", 0, 3072): (32435, 98352),
-    (2, "f32", 0, 4096): (32435, 131136),
-    (2, "f32", 0, 8192): (32434, 262272),
-    (2, "f32", 0, 16384): (32434, 524544),
-    (2, "f32", 1, 128): (17196, 8192),
-    (2, "f32", 1, 256): (16617, 16392),
-    (2, "f32", 1, 512): (16617, 32784),
-    (2, "f32", 1, 1024): (16630, 65569),
-    (2, "f32", 1, 1536): (16628, 98352),
-    (2, "f32", 1, 2048): (16618, 131136),
-    (2, "f32", 1, 4096): (16632, 262272),
-    (2, "f32", 1, 8192): (16631, 524544),
-    (3, "f32", 0, 4096): (261596, 1048576),
-    (3, "f32", 0, 8192): (244770, 524320),
-    (3, "f32", 0, 16384): (244752, 1048640),
-    (3, "f32", 0, 32768): (244769, 2097280),
-    (3, "f32", 0, 65536): (244752, 4194560),
-    (3, "f32", 0, 131072): (245074, 8389120),
-    (3, "f32", 0, 262144): (246018, 16778240),
-    (3, "f32", 1, 2048): (143948, 544739),
-    (3, "f32", 1, 4096): (131871, 559945),
-    (3, "f32", 1, 8192): (138357, 1123973),
-    (3, "f32", 1, 16384): (149761, 2252654),
-    (3, "f32", 1, 32768): (189602, 4507538),
-    (3, "f32", 1, 65536): (516351, 9044517),
-    (3, "f32", 1, 131072): (1012191, 18090008),
-    (4, "f16", 0, 128): (129019, 8192),
-    (4, "f16", 0, 256): (128460, 16392),
-    (4, "f16", 0, 512): (128672, 32785),
-    (4, "f16", 0, 768): (128884, 49177),
-    (4, "f16", 0, 1024): (129097, 65569),
-    (4, "f16", 0, 2048): (129624, 131136),
-    (4, "f16", 0, 4096): (129654, 262272),
-    (4, "f16", 0, 8192): (129875, 524544),
+    (2, "f32", 0, 256): (26244, 58368),
+    (2, "f32", 0, 512): (34429, 51202),
+    (2, "f32", 0, 1024): (19059, 36868),
+    (2, "f32", 0, 2048): (19828, 70953),
+    (2, "f32", 0, 3072): (20556, 105101),
+    (2, "f32", 0, 4096): (21176, 139454),
+    (2, "f32", 0, 8192): (22218, 276421),
+    (2, "f32", 0, 16384): (22515, 551295),
+    (2, "f32", 1, 128): (25495, 57344),
+    (2, "f32", 1, 256): (33171, 49154),
+    (2, "f32", 1, 512): (16843, 32772),
+    (2, "f32", 1, 1024): (16829, 65544),
+    (2, "f32", 1, 1536): (16796, 98316),
+    (2, "f32", 1, 2048): (16801, 131088),
+    (2, "f32", 1, 4096): (16843, 262176),
+    (2, "f32", 1, 8192): (16899, 524352),
+    (3, "f32", 0, 4096): (54335, 262144),
+    (3, "f32", 0, 8192): (49744, 524304),
+    (3, "f32", 0, 16384): (50593, 1048608),
+    (3, "f32", 0, 32768): (52622, 2097216),
+    (3, "f32", 0, 65536): (55795, 4194433),
+    (3, "f32", 0, 131072): (64402, 8388866),
+    (3, "f32", 0, 262144): (74285, 16777732),
+    (3, "f32", 1, 2048): (77735, 304961),
+    (3, "f32", 1, 4096): (68646, 608307),
+    (3, "f32", 1, 8192): (146551, 1220221),
+    (3, "f32", 1, 16384): (319296, 2441249),
+    (3, "f32", 1, 32768): (611450, 4882574),
+    (3, "f32", 1, 65536): (1255847, 9765175),
+    (3, "f32", 1, 131072): (2501776, 19530364),
     (4, "bf16", 0, 128): (129004, 8192),
     (4, "bf16", 0, 256): (128440, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
-    (4, "bf16", 0, 1024): (129078, 65569),
-    (4, "bf16", 0, 2048): (129610, 131136),
-    (4, "bf16", 0, 4096): (129651, 262272),
-    (4, "bf16", 0, 8192): (129881, 524544),
-    (5, "f32", 0, 1024): (548510, 262144),
-    (5, "f32", 0, 2048): (534243, 131088),
-    (5, "f32", 0, 4096): (543091, 262176),
-    (5, "f32", 0, 8192): (559808, 524352),
-    (5, "f32", 0, 16384): (591129, 1048704),
-    (5, "f32", 0, 32768): (656561, 2097408),
-    (5, "f32", 0, 65536): (787622, 4194816),
-    (5, "f32", 1, 512): (278633, 138240),
-    (5, "f32", 1, 1024): (275491, 145371),
-    (5, "f32", 1, 2048): (289296, 290795),
-    (5, "f32", 1, 4096): (320813, 581673),
-    (5, "f32", 1, 8192): (382058, 1163396),
-    (5, "f32", 1, 16384): (503031, 2326787),
-    (5, "f32", 1, 32768): (743760, 4653569),
+    (4, "bf16", 0, 1024): (129079, 65569),
+    (4, "bf16", 0, 2048): (129614, 131136),
+    (4, "bf16", 0, 4096): (129632, 262272),
+    (4, "bf16", 0, 8192): (130022, 524544),
+    (4, "f16", 0, 128): (129019, 8192),
+    (4, "f16", 0, 256): (128459, 16392),
+    (4, "f16", 0, 512): (128672, 32784),
+    (4, "f16", 0, 768): (128885, 49176),
+    (4, "f16", 0, 1024): (129098, 65569),
+    (4, "f16", 0, 2048): (129638, 131136),
+    (4, "f16", 0, 4096): (129659, 262272),
+    (4, "f16", 0, 8192): (130098, 524544),
+    (4, "f32", 0, 256): (138800, 58752),
+    (4, "f32", 0, 512): (147053, 51970),
+    (4, "f32", 0, 1024): (131867, 38404),
+    (4, "f32", 0, 2048): (133183, 74764),
+    (4, "f32", 0, 3072): (134450, 111129),
+    (4, "f32", 0, 4096): (135726, 147615),
+    (4, "f32", 0, 8192): (140808, 293257),
+    (4, "f32", 0, 16384): (151019, 585545),
+    (4, "f32", 1, 128): (137494, 57344),
+    (4, "f32", 1, 256): (145165, 49154),
+    (4, "f32", 1, 512): (128873, 32772),
+    (4, "f32", 1, 1024): (129352, 65544),
+    (4, "f32", 1, 1536): (129921, 98316),
+    (4, "f32", 1, 2048): (130324, 131088),
+    (4, "f32", 1, 4096): (131082, 262176),
+    (4, "f32", 1, 8192): (129210, 524352),
+    (5, "f32", 0, 1024): (158340, 65536),
+    (5, "f32", 0, 2048): (149476, 131080),
+    (5, "f32", 0, 4096): (159609, 262160),
+    (5, "f32", 0, 8192): (145079, 524320),
+    (5, "f32", 0, 16384): (153924, 1048640),
+    (5, "f32", 0, 32768): (171976, 2097280),
+    (5, "f32", 0, 65536): (201104, 4194560),
+    (5, "f32", 1, 512): (152600, 77824),
+    (5, "f32", 1, 1024): (156507, 155657),
+    (5, "f32", 1, 2048): (181819, 311314),
+    (5, "f32", 1, 4096): (232163, 622625),
+    (5, "f32", 1, 8192): (332641, 1245248),
+    (5, "f32", 1, 16384): (533862, 2490496),
+    (5, "f32", 1, 32768): (936295, 4980992),
 }
 
 
