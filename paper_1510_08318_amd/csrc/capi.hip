@@ -263,6 +263,7 @@ moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_ti
   a.progw = p->d_progw[variant];
   a.cell0 = p->d_cell0[variant];
   a.prog_len = V.prog_len;
+  a.wave_rows = V.wave_rows ? 1 : 0;
   a.weights = p->d_weights[variant];
   a.n_weights = V.n_weights();
   a.tw = p->d_tw;

@@ -47,7 +47,7 @@ struct FT {
   static constexpr int PR = S.PR, QR = S.QR, PC = S.PC, QC = S.QC;
   static constexpr int NZR = L < M ? L : M;
   static constexpr int PRNZ = NZR / QR;          // nonzero inputs of the row pass A
-  static constexpr int LPR = cmin(4, QR);        // lanes per row
+  static constexpr int LPR = row_lanes(S);       // lanes per row
   static constexpr int RPW = 64 / LPR;           // rows per wave per step
   static constexpr int JAR = QR / LPR;           // row pass-A jobs per lane
   static constexpr int JBR = PR / LPR;           // row pass-B jobs per lane

@@ -23,6 +23,7 @@ struct FusedArgs {
   const float4* progw;         // entry weights laid out like prog (HostPlan::Variant::progw) or nullptr
   const int* cell0;            // [SX][NT] first folded cell of each lane
   int prog_len;
+  int wave_rows;               // each wave grids only the rows it transforms (HostPlan::Variant::wave_rows)
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]

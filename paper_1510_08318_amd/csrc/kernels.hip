@@ -263,7 +263,10 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
       for (int k = 0; k < kPrefetch; ++k)
         if (tid + k * NT < a.n_ant) raw[k].load(a.E, base + frame_stride + tid + k * NT);
     }
-    __syncthreads();
+    // With wave-owned rows each wave has gridded exactly the rows it
+    // transforms next, so its own LDS order suffices (a uniform branch).
+    if (a.wave_rows) wave_sync();
+    else __syncthreads();
     row_stage_w<N, V, W>(G, twr);
     __syncthreads();
     col_stage<N, V>(G, twc, [&](int idx, int, int, float2 v) { acc[idx] = fmaf(v.x, v.x, fmaf(v.y, v.y, acc[idx])); });

@@ -319,13 +319,17 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
   P.lm_per_pixel.resize(P.n_chan);
   for (int c = 0; c < P.n_chan; ++c) P.lm_per_pixel[c] = (kC / P.freq_hz[c]) / (P.N * P.cell_m);
 
-  // ---- CSR keyed by aperture cell (stable counting sort: antenna-ascending within a cell)
+  // ---- CSR keyed by aperture cell (stable counting sort: antenna-ascending within a cell).
+  // Table entries that are exactly zero contribute nothing to the gridded field
+  // and are left out (the corners of a tapered table, for instance).
   const int L = P.L, N = P.N;
+  auto tap_nonzero = [&](int tap) { return P.kvals[2 * tap] != 0.0 || P.kvals[2 * tap + 1] != 0.0; };
   P.csr_ptr.assign(L * L + 1, 0);
   for (int a = 0; a < P.n_ant; ++a) {
-    int k = P.ktype_k[P.ant_ktype[a]];
+    int p = P.ant_ktype[a], k = P.ktype_k[p];
     for (int u = 0; u < k; ++u)
-      for (int v = 0; v < k; ++v) P.csr_ptr[(P.iy0[a] + u) * L + (P.ix0[a] + v) + 1]++;
+      for (int v = 0; v < k; ++v)
+        if (tap_nonzero(P.ktype_off[p] + u * k + v)) P.csr_ptr[(P.iy0[a] + u) * L + (P.ix0[a] + v) + 1]++;
   }
   for (int i = 0; i < L * L; ++i) P.csr_ptr[i + 1] += P.csr_ptr[i];
   P.csr_ant.resize(P.csr_ptr[L * L]);
@@ -336,10 +340,12 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
       int p = P.ant_ktype[a], k = P.ktype_k[p];
       for (int u = 0; u < k; ++u)
         for (int v = 0; v < k; ++v) {
+          const int tap = P.ktype_off[p] + u * k + v;
+          if (!tap_nonzero(tap)) continue;
           int cell = (P.iy0[a] + u) * L + (P.ix0[a] + v);
           int at = fill[cell]++;
           P.csr_ant[at] = a;
-          P.csr_tap[at] = P.ktype_off[p] + u * k + v;
+          P.csr_tap[at] = tap;
         }
     }
   }
@@ -445,37 +451,71 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         cost[a * V.NZR + n] = std::max(1, c);
       }
     P.max_cell_entries = maxc;
-    // smallest per-lane load B for which a contiguous greedy split needs <= NT lanes
-    auto lanes_needed = [&](long long B) {
-      int lanes = 1;
-      long long cur = 0;
-      for (int i = 0; i < ncell; ++i) {
-        if (cur + cost[i] > B) {
-          ++lanes;
-          cur = 0;
-        }
-        cur += cost[i];
-      }
-      return lanes;
+    // Lanes take contiguous runs of cells, split greedily by cost.  A segment
+    // is a range of cells split over a range of lanes.
+    struct Segment {
+      int begin, end, lane0, lanes;
     };
-    long long lo = *std::max_element(cost.begin(), cost.end());
-    long long hi = std::accumulate(cost.begin(), cost.end(), 0LL);
-    while (lo < hi) {
-      long long mid = (lo + hi) / 2;
-      if (lanes_needed(mid) <= S.NT) hi = mid;
-      else lo = mid + 1;
+    // smallest per-lane load B for which the greedy split of a segment needs
+    // no more than its lanes
+    auto min_load = [&](const Segment& g) {
+      auto lanes_needed = [&](long long B) {
+        int lanes = 1;
+        long long cur = 0;
+        for (int i = g.begin; i < g.end; ++i) {
+          if (cur + cost[i] > B) {
+            ++lanes;
+            cur = 0;
+          }
+          cur += cost[i];
+        }
+        return lanes;
+      };
+      if (g.begin >= g.end) return 0LL;
+      long long lo = *std::max_element(cost.begin() + g.begin, cost.begin() + g.end);
+      long long hi = std::accumulate(cost.begin() + g.begin, cost.begin() + g.end, 0LL);
+      while (lo < hi) {
+        long long mid = (lo + hi) / 2;
+        if (lanes_needed(mid) <= g.lanes) hi = mid;
+        else lo = mid + 1;
+      }
+      return lo;
+    };
+    std::vector<Segment> segs{Segment{0, ncell, 0, S.NT}};
+    long long B = min_load(segs[0]);
+    // Wave-owned rows: when the row stage gives each wave one block of RPW
+    // consecutive folded rows, each wave can grid exactly its own rows; the
+    // kernel then needs no workgroup barrier between the gather and the row
+    // stage.  Taken when the per-wave split lengthens the program by at most
+    // 1/16 (the densest wave sets the length).
+    const int NW = S.NT / 64, RPW = 64 / row_lanes(S);
+    V.wave_rows = false;
+    if (NW > 1 && NW * RPW >= L) {
+      std::vector<Segment> ws;
+      long long Bw = 0;
+      for (int w = 0; w < NW; ++w) {
+        const int r0 = std::min(L, w * RPW), r1 = std::min(L, (w + 1) * RPW);
+        ws.push_back(Segment{r0 * V.NZR, r1 * V.NZR, 64 * w, 64});
+        Bw = std::max(Bw, min_load(ws.back()));
+      }
+      if (16 * Bw <= 17 * B) {
+        segs = ws;
+        B = Bw;
+        V.wave_rows = true;
+      }
     }
-    const long long B = lo;
     V.prog_len = static_cast<int>((B + 3) / 4 * 4);
     if (V.prog_len > (1 << 20)) return fail(why, MOFF_ERR_UNSUPPORTED, "gather program too long");
     const uint32_t zero_slot = static_cast<uint32_t>(P.n_ant);
     V.prog.assign(static_cast<size_t>(S.SX) * V.prog_len * S.NT, GatherEntry{zero_slot, 0});
     V.cell0.assign(static_cast<size_t>(S.SX) * S.NT, 0);
     for (int w = 0; w < S.SX; ++w) {
+     for (const Segment& g : segs) {
       GatherEntry* base = &V.prog[static_cast<size_t>(w) * V.prog_len * S.NT];
-      int lane = 0, k = 0;
+      int lane = g.lane0, k = 0;
       long long cur = 0;
-      for (int i = 0; i < ncell; ++i) {
+      V.cell0[static_cast<size_t>(w) * S.NT + lane] = g.begin;
+      for (int i = g.begin; i < g.end; ++i) {
         if (cur + cost[i] > B) {
           ++lane;
           k = 0;
@@ -502,6 +542,7 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         }
         base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
       }
+     }
     }
     // device form: x words, four consecutive entries of a lane side by side
     V.prog4.assign(V.prog.size(), zero_slot);

@@ -78,6 +78,10 @@ struct HostPlan {
     // progw holds each entry's weight, laid out like prog4, so the kernel
     // reads it with the entry instead of looking it up in LDS; else empty.
     std::vector<float> progw;
+    // Every wave's lanes grid exactly the folded rows that wave transforms in
+    // the row stage (one block of 64 / row_lanes rows per wave), so no
+    // workgroup barrier is needed between the two.
+    bool wave_rows = false;
     std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
     int n_weights() const { return NJ * n_taps_; }
     int n_taps_ = 0;

@@ -16,6 +16,9 @@ struct FrameShape {
   int N = 0, NT = 0, SX = 0, PR = 0, QR = 0, PC = 0, QC = 0;
 };
 
+// Lanes per row of the row stage (RPW = 64 / row_lanes rows per wave and step).
+constexpr int row_lanes(const FrameShape& S) { return S.QR < 4 ? S.QR : 4; }
+
 // LDS row pitch of the folded grid (complex elements) for M output columns per
 // workgroup: odd, so that 16 lanes reading 16 different rows at the same column
 // hit 16 different banks.

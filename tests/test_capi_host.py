@@ -112,7 +112,7 @@ def test_error_codes(moff):
         assert st == 4
 
 
-@pytest.mark.parametrize("case", ["config1", "config2", "config5", "hetero_small", "n8", "n16"])
+@pytest.mark.parametrize("case", ["config1", "config2", "config3", "config5", "hetero_small", "n8", "n16"])
 def test_gather_program_replays_oracle_grid(moff, case):
     """Replaying the fused kernel's gather program on the CPU (float64) gives the
     oracle's gridded field, transposed (folded-grid row = aperture column x) and
@@ -122,6 +122,8 @@ def test_gather_program_replays_oracle_grid(moff, case):
         w = synth.make_config(1, n_time=2)
     elif case == "config2":
         w = synth.make_config(2, n_time=2, n_chan=1)
+    elif case == "config3":
+        w = synth.make_config(3, n_time=1, n_chan=1)
     elif case == "config5":
         w = synth.make_config(5, n_time=1, n_chan=1)
     elif case == "hetero_small":
@@ -207,3 +209,25 @@ def test_host_only_plan_rejects_compute(moff):
         assert L.moff_accumulate(p.handle, dummy, 2, None, dummy, dummy, None) == 4
         assert L.moff_gain_vjp(p.handle, dummy, 2, None, dummy, dummy, None) == 4
         assert L.moff_image_staged(p.handle, dummy, 2, None, dummy, None) == 4
+
+
+def test_wave_owned_rows_hera(moff):
+    """On the HERA-shaped layout the 512-thread shape's program gives every wave
+    exactly the 16 folded rows that wave transforms in the row stage (rows
+    16 w .. 16 w + 15 for wave w), which lets the kernel skip the workgroup
+    barrier between the gather and the row stage; every row is covered."""
+    w = synth.make_config(3, n_time=1, n_chan=1)
+    with host_plan(moff, w.geom) as p:
+        for cls in range(2):
+            prog, _, info = p.gather_program(cls, 1)
+            assert info["n_threads"] == 512
+            ZP = info["row_pitch"]
+            x, y = prog[..., 0], prog[..., 1]
+            rows_seen = set()
+            for lane in range(512):
+                dst = y[:, lane][(x[:, lane] >> 31) == 1]
+                rows = set((dst // ZP).tolist())
+                wave = lane // 64
+                assert rows <= set(range(16 * wave, 16 * wave + 16)), (cls, lane)
+                rows_seen |= rows
+            assert rows_seen == set(range(128))
