@@ -495,6 +495,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.progw = p->d_progw[av];
     a.cell0 = p->d_cell0[av];
     a.prog_len = AV.prog_len;
+    a.wave_rows = AV.wave_rows ? 1 : 0;
     a.weights = p->d_weights[av];
     a.n_weights = AV.n_weights();
     a.tw = p->d_tw;

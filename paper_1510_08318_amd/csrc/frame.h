@@ -108,7 +108,7 @@ __device__ __forceinline__ void row_stage(float2* G, const float2* twr, const fl
   const int sub = lane / C::RPW;
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
-    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    const int row = stage_row(C::S, rs, wave, lane % C::RPW);
     if (C::RGUARD && row >= C::L) continue;
     float2* R = G + row * C::P;
     float2 x[C::JAR][C::PR];
@@ -160,7 +160,7 @@ __device__ __forceinline__ void row_stage_w(float2* G, const float2* twr) {
   const int sub = lane / C::RPW;
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
-    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    const int row = stage_row(C::S, rs, wave, lane % C::RPW);
     if (C::RGUARD && row >= C::L) continue;
     float2* R = G + row * C::P;
     float2 x[C::JAR][C::PR];
@@ -463,7 +463,7 @@ __device__ __forceinline__ void row_stage_adjoint(float2* G, const float2* twr, 
   const int sub = lane / C::RPW;
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
-    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    const int row = stage_row(C::S, rs, wave, lane % C::RPW);
     if (C::RGUARD && row >= C::L) continue;
     float2* R = G + row * C::P;
     float2 y[C::JBR][C::QR];
@@ -511,7 +511,7 @@ __device__ __forceinline__ void row_stage_adjoint_w(float2* G, const float2* twr
   const int sub = lane / C::RPW;
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
-    const int row = (rs * C::NW + wave) * C::RPW + lane % C::RPW;
+    const int row = stage_row(C::S, rs, wave, lane % C::RPW);
     if (C::RGUARD && row >= C::L) continue;
     float2* R = G + row * C::P;
     float2 y[C::JBR][C::QR];

@@ -190,6 +190,7 @@ struct AdjFusedArgs {
   const float4* progw;         // its entry weights, or nullptr
   const int* cell0;            // [SX][NT]
   int prog_len;
+  int wave_rows;               // as FusedArgs::wave_rows
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]

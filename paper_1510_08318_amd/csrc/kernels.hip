@@ -443,7 +443,8 @@ __device__ __forceinline__ void adjoint_item(const AdjFusedArgs& a, float2* lds,
     __syncthreads();
     gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0, e,
                                                                                Wt, G, static_cast<uint32_t>(a.n_ant));
-    __syncthreads();
+    if (a.wave_rows) wave_sync();   // (wave-owned rows: as in the forward kernel)
+    else __syncthreads();
     row_stage_w<N, V, W>(G, twr);
     __syncthreads();
     col_stage_roundtrip<N, V>(G, twc, [&](int cs, int s, int jb, float (&rr)[C::QC]) {

@@ -454,26 +454,34 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     // Lanes take contiguous runs of cells, split greedily by cost.  A segment
     // is a range of cells split over a range of lanes.
     struct Segment {
-      int begin, end, lane0, lanes;
+      std::vector<std::pair<int, int>> runs;   // cell ranges [begin, end), a lane never spans two
+      int lane0, lanes;
     };
     // smallest per-lane load B for which the greedy split of a segment needs
     // no more than its lanes
     auto min_load = [&](const Segment& g) {
       auto lanes_needed = [&](long long B) {
-        int lanes = 1;
-        long long cur = 0;
-        for (int i = g.begin; i < g.end; ++i) {
-          if (cur + cost[i] > B) {
-            ++lanes;
-            cur = 0;
+        int lanes = 0;
+        for (const auto& run : g.runs) {
+          if (run.first >= run.second) continue;
+          ++lanes;
+          long long cur = 0;
+          for (int i = run.first; i < run.second; ++i) {
+            if (cur + cost[i] > B) {
+              ++lanes;
+              cur = 0;
+            }
+            cur += cost[i];
           }
-          cur += cost[i];
         }
         return lanes;
       };
-      if (g.begin >= g.end) return 0LL;
-      long long lo = *std::max_element(cost.begin() + g.begin, cost.begin() + g.end);
-      long long hi = std::accumulate(cost.begin() + g.begin, cost.begin() + g.end, 0LL);
+      long long lo = 0, hi = 0;
+      for (const auto& run : g.runs)
+        for (int i = run.first; i < run.second; ++i) {
+          lo = std::max<long long>(lo, cost[i]);
+          hi += cost[i];
+        }
       while (lo < hi) {
         long long mid = (lo + hi) / 2;
         if (lanes_needed(mid) <= g.lanes) hi = mid;
@@ -481,24 +489,29 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
       }
       return lo;
     };
-    std::vector<Segment> segs{Segment{0, ncell, 0, S.NT}};
+    std::vector<Segment> segs{Segment{{{0, ncell}}, 0, S.NT}};
     long long B = min_load(segs[0]);
-    // Wave-owned rows: when the row stage gives each wave one block of RPW
-    // consecutive folded rows, each wave can grid exactly its own rows; the
+    // Wave-owned rows: when one step of the row stage covers every folded row,
+    // each wave can grid exactly the rows it transforms (stage_row); the
     // kernel then needs no workgroup barrier between the gather and the row
     // stage.  Taken when the per-wave split lengthens the program by at most
-    // 1/16 (the densest wave sets the length).
+    // 1/8 (the densest wave sets the length).
     const int NW = S.NT / 64, RPW = 64 / row_lanes(S);
     V.wave_rows = false;
-    if (NW > 1 && NW * RPW >= L) {
+    if (NW > 1 && NW * RPW == L) {
       std::vector<Segment> ws;
       long long Bw = 0;
       for (int w = 0; w < NW; ++w) {
-        const int r0 = std::min(L, w * RPW), r1 = std::min(L, (w + 1) * RPW);
-        ws.push_back(Segment{r0 * V.NZR, r1 * V.NZR, 64 * w, 64});
-        Bw = std::max(Bw, min_load(ws.back()));
+        Segment g{{}, 64 * w, 64};
+        for (int r = 0; r < RPW; ++r) {
+          const int row = stage_row(S, 0, w, r);
+          if (!g.runs.empty() && g.runs.back().second == row * V.NZR) g.runs.back().second += V.NZR;
+          else g.runs.push_back({row * V.NZR, (row + 1) * V.NZR});
+        }
+        Bw = std::max(Bw, min_load(g));
+        ws.push_back(std::move(g));
       }
-      if (16 * Bw <= 17 * B) {
+      if (8 * Bw <= 9 * B) {
         segs = ws;
         B = Bw;
         V.wave_rows = true;
@@ -512,10 +525,15 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
     for (int w = 0; w < S.SX; ++w) {
      for (const Segment& g : segs) {
       GatherEntry* base = &V.prog[static_cast<size_t>(w) * V.prog_len * S.NT];
-      int lane = g.lane0, k = 0;
+      int lane = g.lane0 - 1, k = 0;
       long long cur = 0;
-      V.cell0[static_cast<size_t>(w) * S.NT + lane] = g.begin;
-      for (int i = g.begin; i < g.end; ++i) {
+      for (const auto& run : g.runs) {
+       if (run.first >= run.second) continue;
+       ++lane;
+       k = 0;
+       cur = 0;
+       V.cell0[static_cast<size_t>(w) * S.NT + lane] = run.first;
+       for (int i = run.first; i < run.second; ++i) {
         if (cur + cost[i] > B) {
           ++lane;
           k = 0;
@@ -541,6 +559,7 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
           ++k;
         }
         base[static_cast<size_t>(k - 1) * S.NT + lane].x |= kStoreBit;
+       }
       }
      }
     }

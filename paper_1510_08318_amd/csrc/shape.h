@@ -19,6 +19,24 @@ struct FrameShape {
 // Lanes per row of the row stage (RPW = 64 / row_lanes rows per wave and step).
 constexpr int row_lanes(const FrameShape& S) { return S.QR < 4 ? S.QR : 4; }
 
+// Row-stage ownership.  When one step of the row stage covers all L = N/2
+// folded rows with more than one wave (NW * RPW == L), the rows are cut into
+// 2 NW half-blocks of RPW/2 consecutive rows and wave w takes half-block w
+// from the upper half of the grid and half-block NW + (w ^ 1) from the lower
+// half, so that every wave's rows mix the aperture's sparse edges with its
+// dense middle (the plan can then give each wave's lanes just its own rows
+// to grid at little cost in balance).  The two half-blocks lie an odd number
+// of half-blocks apart, so they start RPW/2 apart modulo RPW and a 16-lane
+// group still touches 16 distinct banks.  Otherwise step rs of wave w takes
+// rows (rs NW + w) RPW + r.  stage_row gives the row of step-row r < RPW.
+constexpr bool paired_rows(const FrameShape& S) {
+  return S.NT / 64 > 1 && (S.NT / 64) * (64 / row_lanes(S)) == S.N / 2;
+}
+constexpr int stage_row(const FrameShape& S, int rs, int wave, int r) {
+  const int NW = S.NT / 64, RPW = 64 / row_lanes(S), H = RPW / 2;
+  return paired_rows(S) ? (r < H ? wave * H + r : (NW + (wave ^ 1)) * H + (r - H)) : (rs * NW + wave) * RPW + r;
+}
+
 // LDS row pitch of the folded grid (complex elements) for M output columns per
 // workgroup: odd, so that 16 lanes reading 16 different rows at the same column
 // hit 16 different banks.

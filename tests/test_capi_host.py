@@ -213,9 +213,10 @@ def test_host_only_plan_rejects_compute(moff):
 
 def test_wave_owned_rows_hera(moff):
     """On the HERA-shaped layout the 512-thread shape's program gives every wave
-    exactly the 16 folded rows that wave transforms in the row stage (rows
-    16 w .. 16 w + 15 for wave w), which lets the kernel skip the workgroup
-    barrier between the gather and the row stage; every row is covered."""
+    exactly the 16 folded rows that wave transforms in the row stage (wave w:
+    rows 8 w .. 8 w + 7 from the upper half and 8 (8 + (w xor 1)) .. + 7 from
+    the lower half), which lets the kernel skip the workgroup barrier between
+    the gather and the row stage; every row is covered."""
     w = synth.make_config(3, n_time=1, n_chan=1)
     with host_plan(moff, w.geom) as p:
         for cls in range(2):
@@ -228,6 +229,8 @@ def test_wave_owned_rows_hera(moff):
                 dst = y[:, lane][(x[:, lane] >> 31) == 1]
                 rows = set((dst // ZP).tolist())
                 wave = lane // 64
-                assert rows <= set(range(16 * wave, 16 * wave + 16)), (cls, lane)
+                lower = 8 * (8 + (wave ^ 1))
+                own = set(range(8 * wave, 8 * wave + 8)) | set(range(lower, lower + 8))
+                assert rows <= own, (cls, lane)
                 rows_seen |= rows
             assert rows_seen == set(range(128))
