@@ -264,6 +264,7 @@ moff::FusedArgs fused_args(moff_plan p, int variant, const void* E, int64_t n_ti
   a.cell0 = p->d_cell0[variant];
   a.prog_len = V.prog_len;
   a.wave_rows = V.wave_rows ? 1 : 0;
+  a.dst_entries = V.dst_entries ? 1 : 0;
   a.weights = p->d_weights[variant];
   a.n_weights = V.n_weights();
   a.tw = p->d_tw;
@@ -496,6 +497,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.cell0 = p->d_cell0[av];
     a.prog_len = AV.prog_len;
     a.wave_rows = AV.wave_rows ? 1 : 0;
+    a.dst_entries = AV.dst_entries ? 1 : 0;
     a.weights = p->d_weights[av];
     a.n_weights = AV.n_weights();
     a.tw = p->d_tw;

@@ -24,6 +24,7 @@ struct FusedArgs {
   const int* cell0;            // [SX][NT] first folded cell of each lane
   int prog_len;
   int wave_rows;               // each wave grids only the rows it transforms (HostPlan::Variant::wave_rows)
+  int dst_entries;             // program entries carry their cell (HostPlan::Variant::dst_entries)
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]
@@ -191,6 +192,7 @@ struct AdjFusedArgs {
   const int* cell0;            // [SX][NT]
   int prog_len;
   int wave_rows;               // as FusedArgs::wave_rows
+  int dst_entries;             // as FusedArgs::dst_entries
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]

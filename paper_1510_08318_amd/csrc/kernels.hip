@@ -58,19 +58,25 @@ __device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
 // goes to cell cell0 + k.  With real weights (RW) each entry's weight comes
 // with it from the program (progw), which halves the LDS reads -- the
 // gather's limit -- and the multiply-adds; otherwise it is looked up in the
-// LDS weight table W.  The program sits in global memory (L2-resident: it is
+// LDS weight table W.  With destination-carrying entries (DST: real weights,
+// and a grid that leaves room for one workgroup per CU, where no other
+// workgroup hides the per-cell store branch) an entry carries its cell's LDS
+// element and a first-of-cell flag instead, and every entry stores its cell's
+// running sum; the cell's last entry stores the final one.  The program
+// sits in global memory (L2-resident: it is
 // the same for every frame) and is read B entries at a time; entries past the
 // program's end read as padding (the zero sample, no store), so a batch has no
 // trip-count branches.  The samples, weights and grid are disjoint LDS arrays
 // (restrict), and the LDS values of S entries are read before any of their
 // stores: a conditional store starts a new basic block, and reads placed after
 // it would each wait for a full LDS round trip.
-template <int NT, int B, int S, int NZR, int ZP, bool RW>
+template <int NT, int B, int S, int NZR, int ZP, bool RW, bool DST>
 __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, const float4* __restrict__ progw,
                                              int prog_len, int cell0, const float2* __restrict__ e,
                                              const float2* __restrict__ W, float2* __restrict__ G,
                                              uint32_t zero_entry) {
   static_assert(B % 4 == 0 && B % S == 0, "batches hold whole 16-byte loads and LDS sub-batches");
+  static_assert(RW || !DST, "destination-carrying entries come with their weights");
   static_assert((NZR & (NZR - 1)) == 0, "folded rows are a power of two long");
   float2 acc = make_float2(0.f, 0.f);
   uint32_t cell = static_cast<uint32_t>(cell0);   // unsigned: the row split below is a shift
@@ -82,7 +88,12 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
     for (int j = 0; j < B / 4; ++j) {
       const size_t at = static_cast<size_t>(min(k0 + j, len4 - 1)) * NT;
       uint4 q = prog[at];
-      if (k0 + j >= len4) q = make_uint4(zero_entry, zero_entry, zero_entry, zero_entry);
+      if (k0 + j >= len4) {
+        // padding: the zero sample (with destination-carrying entries, into
+        // the unused pad column of row 0)
+        const uint32_t z = DST ? (zero_entry | (static_cast<uint32_t>(ZP - 1) << 12)) : zero_entry;
+        q = make_uint4(z, z, z, z);
+      }
       ent[4 * j] = q.x;
       ent[4 * j + 1] = q.y;
       ent[4 * j + 2] = q.z;
@@ -105,6 +116,14 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
       }
 #pragma unroll
       for (int i = 0; i < S; ++i) {
+        if constexpr (DST) {
+          // every entry stores its cell's running sum: no branch per cell
+          const bool first = ent[s0 + i] & kFirstBit;
+          acc.x = fmaf(ev[i].x, wt[s0 + i], first ? 0.f : acc.x);
+          acc.y = fmaf(ev[i].y, wt[s0 + i], first ? 0.f : acc.y);
+          G[(ent[s0 + i] >> 12) & 0xFFFFu] = acc;
+          continue;
+        }
         if constexpr (RW) {
           acc.x = fmaf(ev[i].x, wt[s0 + i], acc.x);
           acc.y = fmaf(ev[i].y, wt[s0 + i], acc.y);
@@ -122,16 +141,18 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
   }
 }
 
-// The gather with the weight path the plan provides (a uniform branch).
+// The gather in the entry form the plan provides (uniform branches).
 template <int NT, int B, int S, int NZR, int ZP>
 __device__ __forceinline__ void gather_frame_any(const uint4* __restrict__ prog, const float4* __restrict__ progw,
-                                                 int prog_len, int cell0, const float2* __restrict__ e,
-                                                 const float2* __restrict__ W, float2* __restrict__ G,
-                                                 uint32_t zero_entry) {
-  if (progw)
-    gather_frame<NT, B, S, NZR, ZP, true>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+                                                 int prog_len, int cell0, bool dst_entries,
+                                                 const float2* __restrict__ e, const float2* __restrict__ W,
+                                                 float2* __restrict__ G, uint32_t zero_entry) {
+  if (progw && dst_entries)
+    gather_frame<NT, B, S, NZR, ZP, true, true>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+  else if (progw)
+    gather_frame<NT, B, S, NZR, ZP, true, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
   else
-    gather_frame<NT, B, S, NZR, ZP, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+    gather_frame<NT, B, S, NZR, ZP, false, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
 }
 
 // Entries per batch of program reads (B) and per LDS sub-batch (S).  At
@@ -254,8 +275,9 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
       if (tid + k * NT < a.n_ant) take(tid + k * NT, raw[k].value());
     for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
     __syncthreads();
-    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0, e,
-                                                                               Wt, G, static_cast<uint32_t>(a.n_ant));
+    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0,
+                                                                               a.dst_entries, e, Wt, G,
+                                                                               static_cast<uint32_t>(a.n_ant));
     // the next frame's samples load while this frame is transformed (after
     // the gather, so that its program loads do not wait for them)
     if (t + 1 < t1) {
@@ -441,8 +463,9 @@ __device__ __forceinline__ void adjoint_item(const AdjFusedArgs& a, float2* lds,
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
     for (int i = tid; i < a.n_ant; i += NT) e[i] = c_mul(gl[i], load_sample(a.E, base + i, CI4));
     __syncthreads();
-    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0, e,
-                                                                               Wt, G, static_cast<uint32_t>(a.n_ant));
+    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0,
+                                                                               a.dst_entries, e, Wt, G,
+                                                                               static_cast<uint32_t>(a.n_ant));
     if (a.wave_rows) wave_sync();   // (wave-owned rows: as in the forward kernel)
     else __syncthreads();
     row_stage_w<N, V, W>(G, twr);

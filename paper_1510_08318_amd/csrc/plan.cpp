@@ -583,6 +583,29 @@ moff_status build_host_plan(const moff_geometry* g, HostPlan* hp, std::string* w
         V.progw[i] = (x & 0xFFFu) == zero_slot ? 0.f : V.weights[(static_cast<size_t>(w) * V.n_weights() + wi) * 2];
       }
     }
+    // Destination-carrying entries (device form, real weights only): when the
+    // folded grid takes more than half a CU's LDS, one workgroup runs per CU
+    // and nothing hides the gather's per-cell store branch, so each entry
+    // instead carries its cell's LDS element and a "first entry of the cell"
+    // flag, and every entry stores its cell's running sum (the cell's last
+    // entry stores the final one): x = slot | element << 12 | first << 30.
+    // Padding entries (the zero slot) write to the unused pad column of row 0.
+    V.dst_entries = real && sizeof(float) * 2 * static_cast<size_t>(L) * V.ZP > 80u * 1024;
+    if (V.dst_entries) {
+      const uint32_t pad_elem = static_cast<uint32_t>(V.ZP - 1);
+      if (static_cast<size_t>(L) * V.ZP > (1u << 16)) return fail(why, MOFF_ERR_UNSUPPORTED, "grid too large for the entry form");
+      for (int w = 0; w < S.SX; ++w)
+        for (int lane = 0; lane < S.NT; ++lane) {
+          bool first = true;
+          for (int k = 0; k < V.prog_len; ++k) {
+            const GatherEntry& ge = V.prog[(static_cast<size_t>(w) * V.prog_len + k) * S.NT + lane];
+            const bool pad = (ge.x & 0xFFFu) == zero_slot && ge.y == 0 && !(ge.x & kStoreBit);
+            V.prog4[((static_cast<size_t>(w) * K4 + k / 4) * S.NT + lane) * 4 + k % 4] =
+                (ge.x & 0xFFFu) | ((pad ? pad_elem : ge.y) << 12) | ((first && !pad) ? kFirstBit : 0u);
+            first = (ge.x & kStoreBit) != 0;
+          }
+        }
+    }
     build_adjoint_slots(P, S.NT, &V.slots);
     P.variants.push_back(std::move(V));
   }

@@ -17,14 +17,18 @@ namespace moff {
 
 // A gather entry of the fused kernel: 8 bytes, read coalesced by lane.
 //   x bits  0..11 : antenna slot in LDS (n_ant = the all-zero slot)
-//   x bits 12..21 : weight index into the workgroup's complex weight table
+//   x bits 12..22 : weight index into the workgroup's complex weight table
 //   x bit  31     : last entry of its cell -> store the running sum
 //   y             : LDS element iy * ZP + n' of the folded-grid cell (if stored)
+// The device form keeps the x words only (HostPlan::Variant::prog4), or with
+// destination-carrying entries (Variant::dst_entries) slot | element << 12 |
+// first-entry-of-its-cell << 30.
 struct GatherEntry {
   uint32_t x, y;
 };
 
 constexpr uint32_t kStoreBit = 0x80000000u;
+constexpr uint32_t kFirstBit = 0x40000000u;
 
 // Antenna slots of the fused adjoint: each lane degrids up to kAdjSlots whole
 // antennas, two words per slot:
@@ -82,6 +86,8 @@ struct HostPlan {
     // the row stage (one block of 64 / row_lanes rows per wave), so no
     // workgroup barrier is needed between the two.
     bool wave_rows = false;
+    // Device-form entries carry their cell's LDS element (see GatherEntry).
+    bool dst_entries = false;
     std::vector<float> weights;              // [SX][NJ * n_taps] complex: K[tap] * w_SX^(j w)
     int n_weights() const { return NJ * n_taps_; }
     int n_taps_ = 0;
