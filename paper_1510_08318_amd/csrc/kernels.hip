@@ -23,21 +23,6 @@
 #include "ingest.h"
 #include "kernels.h"
 
-#ifndef GATHER_BATCH_256
-#define GATHER_BATCH_256 16
-#endif
-#ifndef GATHER_BATCH_128
-#define GATHER_BATCH_128 24
-#endif
-#ifndef GATHER_SUB_128
-#define GATHER_SUB_128 4
-#endif
-#ifndef GATHER_SUB_256
-#define GATHER_SUB_256 8
-#endif
-#ifndef FUSED_PREFETCH
-#define FUSED_PREFETCH 0
-#endif
 
 namespace moff {
 
@@ -62,38 +47,32 @@ __device__ __forceinline__ float2 quarter_rot(float2 v, int k, int SX) {
 // and a grid that leaves room for one workgroup per CU, where no other
 // workgroup hides the per-cell store branch) an entry carries its cell's LDS
 // element and a first-of-cell flag instead, and every entry stores its cell's
-// running sum; the cell's last entry stores the final one.  The program
-// sits in global memory (L2-resident: it is
-// the same for every frame) and is read B entries at a time; entries past the
-// program's end read as padding (the zero sample, no store), so a batch has no
-// trip-count branches.  The samples, weights and grid are disjoint LDS arrays
+// running sum; the cell's last entry stores the final one.  The program sits
+// in global memory (L2-resident: it is the same for every frame) and is read
+// in whole batches of B entries, then the rest four at a time, so that no
+// entry past the program's end is executed and a batch has no trip-count
+// branches.  The samples, weights and grid are disjoint LDS arrays
 // (restrict), and the LDS values of S entries are read before any of their
 // stores: a conditional store starts a new basic block, and reads placed after
 // it would each wait for a full LDS round trip.
 template <int NT, int B, int S, int NZR, int ZP, bool RW, bool DST>
 __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, const float4* __restrict__ progw,
                                              int prog_len, int cell0, const float2* __restrict__ e,
-                                             const float2* __restrict__ W, float2* __restrict__ G,
-                                             uint32_t zero_entry) {
+                                             const float2* __restrict__ W, float2* __restrict__ G) {
   static_assert(B % 4 == 0 && B % S == 0, "batches hold whole 16-byte loads and LDS sub-batches");
   static_assert(RW || !DST, "destination-carrying entries come with their weights");
   static_assert((NZR & (NZR - 1)) == 0, "folded rows are a power of two long");
   float2 acc = make_float2(0.f, 0.f);
   uint32_t cell = static_cast<uint32_t>(cell0);   // unsigned: the row split below is a shift
-  const int len4 = prog_len / 4;
-  for (int k0 = 0; k0 < len4; k0 += B / 4) {
-    uint32_t ent[B];
-    float wt[RW ? B : 1];
+  // one batch of BB entries from 16-byte word k0 on, in sub-batches of SS
+  auto batch = [&](int k0, auto bc, auto sc) {
+    constexpr int BB = decltype(bc)::value, SS = decltype(sc)::value;
+    uint32_t ent[BB];
+    float wt[RW ? BB : 1];
 #pragma unroll
-    for (int j = 0; j < B / 4; ++j) {
-      const size_t at = static_cast<size_t>(min(k0 + j, len4 - 1)) * NT;
-      uint4 q = prog[at];
-      if (k0 + j >= len4) {
-        // padding: the zero sample (with destination-carrying entries, into
-        // the unused pad column of row 0)
-        const uint32_t z = DST ? (zero_entry | (static_cast<uint32_t>(ZP - 1) << 12)) : zero_entry;
-        q = make_uint4(z, z, z, z);
-      }
+    for (int j = 0; j < BB / 4; ++j) {
+      const size_t at = static_cast<size_t>(k0 + j) * NT;
+      const uint4 q = prog[at];
       ent[4 * j] = q.x;
       ent[4 * j + 1] = q.y;
       ent[4 * j + 2] = q.z;
@@ -107,15 +86,15 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
       }
     }
 #pragma unroll
-    for (int s0 = 0; s0 < B; s0 += S) {
-      float2 ev[S], wv[RW ? 1 : S];
+    for (int s0 = 0; s0 < BB; s0 += SS) {
+      float2 ev[SS], wv[RW ? 1 : SS];
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
+      for (int i = 0; i < SS; ++i) {
         ev[i] = e[ent[s0 + i] & 0xFFFu];
         if constexpr (!RW) wv[i] = W[(ent[s0 + i] >> 12) & 0x7FFu];
       }
 #pragma unroll
-      for (int i = 0; i < S; ++i) {
+      for (int i = 0; i < SS; ++i) {
         if constexpr (DST) {
           // every entry stores its cell's running sum: no branch per cell
           const bool first = ent[s0 + i] & kFirstBit;
@@ -138,7 +117,13 @@ __device__ __forceinline__ void gather_frame(const uint4* __restrict__ prog, con
         }
       }
     }
-  }
+  };
+  // whole batches of B, then the rest (a multiple of 4 entries) four at a time
+  const int len4 = prog_len / 4;
+  int k0 = 0;
+  for (; k0 + B / 4 <= len4; k0 += B / 4)
+    batch(k0, std::integral_constant<int, B>{}, std::integral_constant<int, S>{});
+  for (; k0 < len4; ++k0) batch(k0, std::integral_constant<int, 4>{}, std::integral_constant<int, (S < 4 ? S : 4)>{});
 }
 
 // The gather in the entry form the plan provides (uniform branches).
@@ -146,27 +131,21 @@ template <int NT, int B, int S, int NZR, int ZP>
 __device__ __forceinline__ void gather_frame_any(const uint4* __restrict__ prog, const float4* __restrict__ progw,
                                                  int prog_len, int cell0, bool dst_entries,
                                                  const float2* __restrict__ e, const float2* __restrict__ W,
-                                                 float2* __restrict__ G, uint32_t zero_entry) {
+                                                 float2* __restrict__ G) {
   if (progw && dst_entries)
-    gather_frame<NT, B, S, NZR, ZP, true, true>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+    gather_frame<NT, B, S, NZR, ZP, true, true>(prog, progw, prog_len, cell0, e, W, G);
   else if (progw)
-    gather_frame<NT, B, S, NZR, ZP, true, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+    gather_frame<NT, B, S, NZR, ZP, true, false>(prog, progw, prog_len, cell0, e, W, G);
   else
-    gather_frame<NT, B, S, NZR, ZP, false, false>(prog, progw, prog_len, cell0, e, W, G, zero_entry);
+    gather_frame<NT, B, S, NZR, ZP, false, false>(prog, progw, prog_len, cell0, e, W, G);
 }
 
-// Entries per batch of program reads (B) and per LDS sub-batch (S).  At
-// N = 128 the program (about 20 entries per lane) fits one batch, and the
-// registers it takes are free during the gridding (the transform's
-// temporaries are not live then).
-template <int N, int V = 0>
-constexpr int gather_batch() {
-  return N == 128 ? GATHER_BATCH_128 : N == 256 ? GATHER_BATCH_256 : 8;
-}
-template <int N, int V = 0>
-constexpr int gather_sub() {
-  return N == 128 ? GATHER_SUB_128 : N == 256 ? GATHER_SUB_256 : 4;
-}
+// Entries per batch of program reads (B) and per LDS sub-batch (S): short
+// batches measured fastest at both N = 128 and 256 (8 and 4 against 12–16
+// and 4–8: 2.21 against 2.24 ms at the LWA shape, 23.7 against 24.5 ms at
+// the HERA shape).
+constexpr int kGatherBatch = 8;
+constexpr int kGatherSub = 4;
 
 }  // namespace
 
@@ -181,28 +160,6 @@ template <int N, int V>
 constexpr int fused_waves_per_simd() {
   return (N == 128 && V == 0) ? 4 : 1;
 }
-
-// Samples of the next frame each lane loads ahead (antennas tid + k NT,
-// k < kPrefetch), so that their latency overlaps the current frame's transform.
-constexpr int kPrefetch = FUSED_PREFETCH;
-
-// A raw sample held in registers between its load and its use: the byte of a
-// 4+4-bit sample, or a complex64 value.
-template <bool CI4>
-struct RawSample {
-  float2 v;
-  __device__ __forceinline__ void load(const void* E, size_t idx) { v = reinterpret_cast<const float2*>(E)[idx]; }
-  __device__ __forceinline__ float2 value() const { return v; }
-};
-template <>
-struct RawSample<true> {
-  int b;
-  __device__ __forceinline__ void load(const void* E, size_t idx) { b = reinterpret_cast<const int8_t*>(E)[idx]; }
-  __device__ __forceinline__ float2 value() const {
-    // real part in the high nibble, imaginary part in the low nibble
-    return make_float2(static_cast<float>(b >> 4), static_cast<float>(static_cast<int8_t>(b << 4) >> 4));
-  }
-};
 
 // One work item of the fused kernel: column class W (a compile-time constant,
 // so the row stage's fold factors are constant rotations), channel c and a
@@ -249,15 +206,6 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
   bool flushed = false;
   int in_block = 0;
 
-  // the first frame's samples
-  RawSample<CI4> raw[kPrefetch > 0 ? kPrefetch : 1];
-  {
-    const size_t base = static_cast<size_t>(t0) * frame_stride + static_cast<size_t>(c) * a.n_ant;
-#pragma unroll
-    for (int k = 0; k < kPrefetch; ++k)
-      if (tid + k * NT < a.n_ant && t0 < t1) raw[k].load(a.E, base + tid + k * NT);
-  }
-
   __syncthreads();
   for (int64_t t = t0; t < t1; ++t) {
     // ingest + calibration: e = g * E, and the self power of each antenna type
@@ -270,21 +218,10 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
 #pragma unroll
       for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
     };
-#pragma unroll
-    for (int k = 0; k < kPrefetch; ++k)
-      if (tid + k * NT < a.n_ant) take(tid + k * NT, raw[k].value());
-    for (int i = tid + kPrefetch * NT; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
+    for (int i = tid; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
     __syncthreads();
-    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0,
-                                                                               a.dst_entries, e, Wt, G,
-                                                                               static_cast<uint32_t>(a.n_ant));
-    // the next frame's samples load while this frame is transformed (after
-    // the gather, so that its program loads do not wait for them)
-    if (t + 1 < t1) {
-#pragma unroll
-      for (int k = 0; k < kPrefetch; ++k)
-        if (tid + k * NT < a.n_ant) raw[k].load(a.E, base + frame_stride + tid + k * NT);
-    }
+    gather_frame_any<NT, kGatherBatch, kGatherSub, C::NZR, C::P>(prog, progw, a.prog_len, cell0, a.dst_entries, e,
+                                                                 Wt, G);
     // With wave-owned rows each wave has gridded exactly the rows it
     // transforms next, so its own LDS order suffices (a uniform branch).
     if (a.wave_rows) wave_sync();
@@ -463,9 +400,8 @@ __device__ __forceinline__ void adjoint_item(const AdjFusedArgs& a, float2* lds,
     const size_t base = static_cast<size_t>(t) * frame_stride + static_cast<size_t>(c) * a.n_ant;
     for (int i = tid; i < a.n_ant; i += NT) e[i] = c_mul(gl[i], load_sample(a.E, base + i, CI4));
     __syncthreads();
-    gather_frame_any<NT, gather_batch<N, V>(), gather_sub<N, V>(), C::NZR, C::P>(prog, progw, a.prog_len, cell0,
-                                                                               a.dst_entries, e, Wt, G,
-                                                                               static_cast<uint32_t>(a.n_ant));
+    gather_frame_any<NT, kGatherBatch, kGatherSub, C::NZR, C::P>(prog, progw, a.prog_len, cell0, a.dst_entries, e,
+                                                                 Wt, G);
     if (a.wave_rows) wave_sync();   // (wave-owned rows: as in the forward kernel)
     else __syncthreads();
     row_stage_w<N, V, W>(G, twr);
