@@ -64,6 +64,12 @@ def run_image(torch, moff, w, staged=False):
         return out.cpu().numpy()
 
 
+def _zero_corners(seed, k):
+    K = synth.random_kernel(np.random.default_rng(seed), k).copy()
+    K[0, 0] = K[0, -1] = K[-1, 0] = K[-1, -1] = 0
+    return K
+
+
 CASES = {
     "config1": lambda: synth.make_config(1),
     "config2_sub": lambda: synth.make_config(2, n_time=7, n_chan=3),
@@ -78,6 +84,11 @@ CASES = {
     "hetero_n32_ci4": lambda: synth.random_case(23, 20, 32, 3, 4, [synth.random_kernel(np.random.default_rng(4), 3),
                                                                    synth.random_kernel(np.random.default_rng(5), 4)],
                                                 fmt=synth.IN_CI4, extent_m=20.0, cell_m=1.5),
+    # complex tables with exactly-zero corners at N = 256: the gather leaves the
+    # zero entries out, and the 512-thread shape's program is wave-owned
+    # (each wave grids the rows it transforms) with complex weights
+    "hetero_n256_zero_taps": lambda: synth.random_case(25, 220, 256, 2, 3, [_zero_corners(9, 5), _zero_corners(10, 7)],
+                                                       extent_m=120.0, cell_m=1.0),
     "hetero_n128_4types": lambda: synth.random_case(24, 150, 128, 2, 3,
                                                     [synth.random_kernel(np.random.default_rng(6 + i), k)
                                                      for i, k in enumerate((1, 3, 5, 7))],
@@ -279,7 +290,8 @@ def test_full_config2_sampled_channels(torch, moff):
     assert_image_close(got[chans], ref, pbar, label="config2 full")
 
 
-@pytest.mark.parametrize("case", ["config2_sub", "config3_sub", "config5_sub", "hetero_n128_4types", "config1"])
+@pytest.mark.parametrize("case", ["config2_sub", "config3_sub", "config5_sub", "hetero_n128_4types",
+                                  "hetero_n256_zero_taps", "config1"])
 def test_every_variant_and_slicing(torch, moff, case):
     """Every shape variant of the frame transform and several time slicings agree
     with the oracle (the autotuner may pick any of them)."""
