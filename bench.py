@@ -45,89 +45,89 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # on, so that every candidate launch shape is counted (KiB per dispatch; the
 # commands are in profiles/fused_kernel_hera_n256.md).  Scaled by what the same
 # counters read for one 256 MiB device copy in the same runs (FETCH_SIZE
-# 131,093 KiB, WRITE_SIZE 262,144 KiB).  All entries are from one set of runs on
+# 131,088-131,094 KiB, WRITE_SIZE 262,144 KiB).  All entries are from one set of runs on
 # the current sources.  Keyed by (workload, precision, shape variant,
 # workgroups); valid only for the kernel sources they were measured on,
 # identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "d2398072c85286ee"
+TRAFFIC_SOURCES_SHA = "d7ce12b4a42b8721"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (26244, 58368),
-    (2, "f32", 0, 512): (34429, 51202),
-    (2, "f32", 0, 1024): (19059, 36868),
-    (2, "f32", 0, 2048): (19828, 70953),
-    (2, "f32", 0, 3072): (20556, 105101),
-    (2, "f32", 0, 4096): (21176, 139454),
-    (2, "f32", 0, 8192): (22218, 276421),
-    (2, "f32", 0, 16384): (22515, 551295),
-    (2, "f32", 1, 128): (25495, 57344),
-    (2, "f32", 1, 256): (33171, 49154),
-    (2, "f32", 1, 512): (16843, 32772),
-    (2, "f32", 1, 1024): (16829, 65544),
-    (2, "f32", 1, 1536): (16796, 98316),
-    (2, "f32", 1, 2048): (16801, 131088),
-    (2, "f32", 1, 4096): (16843, 262176),
-    (2, "f32", 1, 8192): (16899, 524352),
-    (3, "f32", 0, 4096): (54335, 262144),
-    (3, "f32", 0, 8192): (49744, 524304),
-    (3, "f32", 0, 16384): (50593, 1048608),
-    (3, "f32", 0, 32768): (52622, 2097216),
-    (3, "f32", 0, 65536): (55795, 4194433),
-    (3, "f32", 0, 131072): (64402, 8388866),
-    (3, "f32", 0, 262144): (74285, 16777732),
-    (3, "f32", 1, 2048): (77735, 304961),
-    (3, "f32", 1, 4096): (68646, 608307),
-    (3, "f32", 1, 8192): (146551, 1220221),
-    (3, "f32", 1, 16384): (319296, 2441249),
-    (3, "f32", 1, 32768): (611450, 4882574),
-    (3, "f32", 1, 65536): (1255847, 9765175),
-    (3, "f32", 1, 131072): (2501776, 19530364),
+    (2, "f32", 0, 256): (25852, 58624),
+    (2, "f32", 0, 512): (33652, 51714),
+    (2, "f32", 0, 1024): (17514, 37892),
+    (2, "f32", 0, 2048): (18036, 75722),
+    (2, "f32", 0, 3072): (18508, 113438),
+    (2, "f32", 0, 4096): (18823, 151171),
+    (2, "f32", 0, 8192): (20148, 302417),
+    (2, "f32", 0, 16384): (20492, 605240),
+    (2, "f32", 1, 128): (25479, 57344),
+    (2, "f32", 1, 256): (33154, 49154),
+    (2, "f32", 1, 512): (16800, 32772),
+    (2, "f32", 1, 1024): (16832, 65544),
+    (2, "f32", 1, 1536): (16778, 98316),
+    (2, "f32", 1, 2048): (16789, 131088),
+    (2, "f32", 1, 4096): (16826, 262176),
+    (2, "f32", 1, 8192): (16866, 524352),
+    (3, "f32", 0, 4096): (53699, 262144),
+    (3, "f32", 0, 8192): (49635, 524304),
+    (3, "f32", 0, 16384): (50336, 1048609),
+    (3, "f32", 0, 32768): (51046, 2097216),
+    (3, "f32", 0, 65536): (53560, 4194433),
+    (3, "f32", 0, 131072): (64318, 8388865),
+    (3, "f32", 0, 262144): (554737, 16777766),
+    (3, "f32", 1, 2048): (72934, 325478),
+    (3, "f32", 1, 4096): (67739, 640737),
+    (3, "f32", 1, 8192): (95682, 1282088),
+    (3, "f32", 1, 16384): (307076, 2605057),
+    (3, "f32", 1, 32768): (585809, 5210250),
+    (3, "f32", 1, 65536): (1191063, 10420538),
+    (3, "f32", 1, 131072): (2353919, 20841086),
     (4, "bf16", 0, 128): (129004, 8192),
     (4, "bf16", 0, 256): (128440, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
     (4, "bf16", 0, 1024): (129079, 65569),
-    (4, "bf16", 0, 2048): (129614, 131136),
-    (4, "bf16", 0, 4096): (129632, 262272),
-    (4, "bf16", 0, 8192): (130022, 524544),
+    (4, "bf16", 0, 2048): (129615, 131136),
+    (4, "bf16", 0, 4096): (129651, 262272),
+    (4, "bf16", 0, 8192): (130111, 524544),
     (4, "f16", 0, 128): (129019, 8192),
     (4, "f16", 0, 256): (128459, 16392),
     (4, "f16", 0, 512): (128672, 32784),
-    (4, "f16", 0, 768): (128885, 49176),
-    (4, "f16", 0, 1024): (129098, 65569),
-    (4, "f16", 0, 2048): (129638, 131136),
-    (4, "f16", 0, 4096): (129659, 262272),
-    (4, "f16", 0, 8192): (130098, 524544),
-    (4, "f32", 0, 256): (138800, 58752),
-    (4, "f32", 0, 512): (147053, 51970),
-    (4, "f32", 0, 1024): (131867, 38404),
-    (4, "f32", 0, 2048): (133183, 74764),
-    (4, "f32", 0, 3072): (134450, 111129),
-    (4, "f32", 0, 4096): (135726, 147615),
-    (4, "f32", 0, 8192): (140808, 293257),
-    (4, "f32", 0, 16384): (151019, 585545),
-    (4, "f32", 1, 128): (137494, 57344),
-    (4, "f32", 1, 256): (145165, 49154),
-    (4, "f32", 1, 512): (128873, 32772),
-    (4, "f32", 1, 1024): (129352, 65544),
-    (4, "f32", 1, 1536): (129921, 98316),
-    (4, "f32", 1, 2048): (130324, 131088),
-    (4, "f32", 1, 4096): (131082, 262176),
-    (4, "f32", 1, 8192): (129210, 524352),
-    (5, "f32", 0, 1024): (158340, 65536),
-    (5, "f32", 0, 2048): (149476, 131080),
-    (5, "f32", 0, 4096): (159609, 262160),
-    (5, "f32", 0, 8192): (145079, 524320),
-    (5, "f32", 0, 16384): (153924, 1048640),
-    (5, "f32", 0, 32768): (171976, 2097280),
-    (5, "f32", 0, 65536): (201104, 4194560),
-    (5, "f32", 1, 512): (152600, 77824),
-    (5, "f32", 1, 1024): (156507, 155657),
-    (5, "f32", 1, 2048): (181819, 311314),
-    (5, "f32", 1, 4096): (232163, 622625),
-    (5, "f32", 1, 8192): (332641, 1245248),
-    (5, "f32", 1, 16384): (533862, 2490496),
-    (5, "f32", 1, 32768): (936295, 4980992),
+    (4, "f16", 0, 768): (128884, 49177),
+    (4, "f16", 0, 1024): (129098, 65568),
+    (4, "f16", 0, 2048): (129628, 131136),
+    (4, "f16", 0, 4096): (129653, 262272),
+    (4, "f16", 0, 8192): (130000, 524544),
+    (4, "f32", 0, 256): (138493, 59008),
+    (4, "f32", 0, 512): (146353, 52482),
+    (4, "f32", 0, 1024): (130378, 39428),
+    (4, "f32", 0, 2048): (131440, 78397),
+    (4, "f32", 0, 3072): (132467, 117366),
+    (4, "f32", 0, 4096): (133490, 156365),
+    (4, "f32", 0, 8192): (137549, 312266),
+    (4, "f32", 0, 16384): (145711, 624456),
+    (4, "f32", 1, 128): (137530, 57344),
+    (4, "f32", 1, 256): (145203, 49154),
+    (4, "f32", 1, 512): (128897, 32772),
+    (4, "f32", 1, 1024): (129427, 65544),
+    (4, "f32", 1, 1536): (130059, 98316),
+    (4, "f32", 1, 2048): (130543, 131088),
+    (4, "f32", 1, 4096): (131418, 262176),
+    (4, "f32", 1, 8192): (129456, 524352),
+    (5, "f32", 0, 1024): (158656, 65536),
+    (5, "f32", 0, 2048): (151104, 131080),
+    (5, "f32", 0, 4096): (161600, 262160),
+    (5, "f32", 0, 8192): (143992, 524320),
+    (5, "f32", 0, 16384): (152538, 1048640),
+    (5, "f32", 0, 32768): (169551, 2097280),
+    (5, "f32", 0, 65536): (200852, 4194560),
+    (5, "f32", 1, 512): (152505, 83456),
+    (5, "f32", 1, 1024): (156781, 166921),
+    (5, "f32", 1, 2048): (182064, 333841),
+    (5, "f32", 1, 4096): (232325, 667678),
+    (5, "f32", 1, 8192): (332018, 1335346),
+    (5, "f32", 1, 16384): (532095, 2670710),
+    (5, "f32", 1, 32768): (941455, 5341441),
 }
 
 
