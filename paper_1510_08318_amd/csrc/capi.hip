@@ -209,7 +209,7 @@ KernelFootprint footprint(moff_plan p, int variant) {
   KernelFootprint f{};
   if (is_mfma(hp)) {
     f.per_slice = hp.n_chan;
-    const bool in_lds = moff::mfma_prog_fits_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len);
+    const bool in_lds = moff::mfma_prog_in_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len);
     f.lds = moff::mfma_lds_bytes(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len, in_lds);
     f.resident = std::max(1, moff::mfma_blocks_per_cu(hp.N, hp.mfma.prec, ci4, f.lds)) * std::max(1, p->cu_count);
     f.threads = moff::mfma_threads(hp.N);
@@ -285,7 +285,7 @@ moff::MfmaArgs mfma_args(moff_plan p, const void* E, int64_t n_time, const float
   a.gains = reinterpret_cast<const float2*>(gains);
   a.prog = p->d_mfma_prog;
   a.prog_len = hp.mfma.prog_len;
-  a.prog_in_lds = moff::mfma_prog_fits_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len) ? 1 : 0;
+  a.prog_in_lds = moff::mfma_prog_in_lds(hp.N, hp.n_taps, hp.n_ant, hp.mfma.prog_len) ? 1 : 0;
   a.ktab = p->d_ktab;
   a.n_taps = hp.n_taps;
   a.dft = p->d_mfma_dft;

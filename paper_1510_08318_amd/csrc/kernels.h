@@ -145,7 +145,7 @@ struct MfmaArgs {
   const float2* gains;         // [C][n_ant] or nullptr
   const GatherEntry* prog;     // [prog_len][gather lanes]
   int prog_len;
-  int prog_in_lds;             // copy the program into LDS (mfma_prog_fits_lds)
+  int prog_in_lds;             // copy the program into LDS (mfma_prog_in_lds)
   const float2* ktab;          // [n_taps] kernel taps, all types back to back
   int n_taps;
   const uint16_t* dft;         // phase-factor operands (HostPlan::Mfma::dft), 16-byte aligned
@@ -162,7 +162,7 @@ struct MfmaArgs {
 };
 
 size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds);
-bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len);
+bool mfma_prog_in_lds(int N, int n_taps, int n_ant, int prog_len);
 int mfma_threads(int N);
 hipError_t launch_mfma(const MfmaArgs& a, int N, int prec, bool ci4, int grid, hipStream_t st);
 int mfma_blocks_per_cu(int N, int prec, bool ci4, size_t lds);

@@ -113,6 +113,11 @@ struct MfmaShape {
 // registers allow no second one); at N = 64 two workgroups share one.
 constexpr size_t mfma_prog_lds_limit(int N) { return N == 128 ? kMfmaLdsMax : kMfmaLdsMax / 2; }
 
+// Program entries per gather lane that the gather waves keep in registers for
+// the whole launch (with their tap values); a longer program is read every
+// frame, from LDS when it fits there.
+constexpr int mfma_prog_regs(int N) { return N == 128 ? 16 : 24; }
+
 }  // namespace
 
 size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_lds) {
@@ -121,8 +126,10 @@ size_t mfma_lds_bytes(int N, int n_taps, int n_ant, int prog_len, bool prog_in_l
   return static_cast<size_t>(m.prog) + prog;
 }
 
-bool mfma_prog_fits_lds(int N, int n_taps, int n_ant, int prog_len) {
-  return mfma_lds_bytes(N, n_taps, n_ant, prog_len, true) <= mfma_prog_lds_limit(N);
+// A program that fits the registers is read from global memory once, so it
+// takes no LDS: at N = 64 three workgroups then share a compute unit.
+bool mfma_prog_in_lds(int N, int n_taps, int n_ant, int prog_len) {
+  return prog_len > mfma_prog_regs(N) && mfma_lds_bytes(N, n_taps, n_ant, prog_len, true) <= mfma_prog_lds_limit(N);
 }
 
 template <int N, class H, bool CI4>
@@ -451,7 +458,7 @@ void mfma_kernel(MfmaArgs a) {
     // The program does not change from frame to frame: when it is short
     // enough, each lane keeps its entries and their tap values in registers,
     // and a frame costs one batch of sample reads from LDS.
-    constexpr int kProgRegs = N == 128 ? 16 : 24;
+    constexpr int kProgRegs = mfma_prog_regs(N);
     const bool prog_in_regs = a.prog_len <= kProgRegs;
     uint32_t r_e[kProgRegs], r_cell[kProgRegs];
     float2 r_k[kProgRegs];
