@@ -245,11 +245,13 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  *
  * moff_plan_autotune times every candidate (variant x slices, including the
  * slice counts that fill whole rounds of resident workgroups) with HIP events
- * on `hip_stream` using the caller's data, keeps the fastest, and synchronises
- * the stream.  It first runs the default shape for about 200 ms so that no
- * candidate is timed on a cold device, then takes each candidate's time as the
- * best of three batches of three back-to-back calls; later results do not depend on the choice beyond float32
- * rounding order.  Unless the plan has a MOFF_MFMA_* flag, it also times the
+ * on `hip_stream` using the caller's data and synchronises the stream.  It
+ * first runs the default shape for about 200 ms so that no candidate is timed
+ * on a cold device, then takes each candidate's time as the best of three
+ * batches of three back-to-back calls, and keeps, of the candidates within 2 %
+ * of the fastest, the one with the fewest time slices (less scratch and fewer
+ * partial images to reduce).  Later results do not depend on the choice
+ * beyond float32 rounding order.  Unless the plan has a MOFF_MFMA_* flag, it also times the
  * fused gain adjoint (moff_gain_vjp) for every shape variant and register
  * budget it is built with (see moff_plan_set_adjoint_waves), on the same
  * samples and gains with the tuned image as the pixel sensitivities, and

@@ -192,6 +192,7 @@ struct LaunchConfig {
 
 constexpr int kTuneReps = 3;    // timed batches per autotuner candidate
 constexpr int kTuneBatch = 3;   // back-to-back calls per timed batch (steady state, as in use)
+constexpr float kTuneSlack = 0.02f;   // calls this much slower than the fastest still count as equal
 
 bool is_mfma(const HostPlan& hp) { return hp.mfma.prec != 0; }
 
@@ -316,6 +317,7 @@ hipError_t launch_fused_kernel(moff_plan p, const LaunchConfig& lc, const void* 
     return moff::launch_mfma(a, hp.N, hp.mfma.prec, ci4, lc.grid, st);
   }
   moff::FusedArgs a = fused_args(p, lc.variant, E, n_time, gains);
+  a.progress_prio = footprint(p, lc.variant).resident > std::max(1, p->cu_count) ? 1 : 0;
   a.slices = lc.slices;
   a.scale = image_scale(hp, n_time);
   a.out = out;
@@ -498,6 +500,7 @@ moff_status gain_vjp(moff_plan p, const void* E, int64_t n_time, const float* ga
     a.prog_len = AV.prog_len;
     a.wave_rows = AV.wave_rows ? 1 : 0;
     a.dst_entries = AV.dst_entries ? 1 : 0;
+    a.progress_prio = resident > std::max(1, p->cu_count) ? 1 : 0;
     a.weights = p->d_weights[av];
     a.n_weights = AV.n_weights();
     a.tw = p->d_tw;
@@ -830,6 +833,12 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
   p->timing = false;
   float best = 1e30f;
   int bv = saved_v, bs = saved_s;
+  // every timed candidate (at most 11 slice counts per shape variant)
+  struct Timed {
+    int v, sl;
+    float ms;
+  } timed[moff::kMaxVariants * 11];
+  int n_timed = 0;
   moff_status result = MOFF_OK;
   {
     // Bring the device to its steady clocks first (about 200 ms of the default
@@ -879,11 +888,27 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
           if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
           if (result == MOFF_OK) ms = std::min(ms, one);
         }
-        if (result == MOFF_OK && ms < best) {
-          best = ms;
-          bv = v;
-          bs = sl;
+        if (result == MOFF_OK) {
+          timed[n_timed++] = {v, sl, ms};
+          best = std::min(best, ms);
         }
+      }
+    }
+  }
+  // Of the candidates within kTuneSlack of the fastest call, the one with the
+  // fewest time slices (then the fastest): fewer per-slice partial images to
+  // write and read back, and less scratch, at the same time per call.
+  {
+    float chosen = 1e30f;
+    int chosen_sl = 1 << 30;
+    for (int i = 0; i < n_timed; ++i) {
+      const Timed& c = timed[i];
+      if (c.ms > best * (1.f + kTuneSlack)) continue;
+      if (c.sl < chosen_sl || (c.sl == chosen_sl && c.ms < chosen)) {
+        chosen = c.ms;
+        chosen_sl = c.sl;
+        bv = c.v;
+        bs = c.sl;
       }
     }
   }

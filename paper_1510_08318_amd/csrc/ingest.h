@@ -21,6 +21,41 @@ __device__ __forceinline__ float2 load_sample(const void* E, size_t idx, bool ci
   return reinterpret_cast<const float2*>(E)[idx];
 }
 
+// Issue priority by progress through a work item's frames [t0, t1), for
+// kernels whose workgroups share a CU: 3 in the first quarter of the frames,
+// down to 0 in the last.  Otherwise a CU's oldest waves issue first, its
+// workgroups advance unevenly, and the first to finish leaves the CU short of
+// waves for the others' remaining frames.  Only the order in which ready
+// waves issue changes, never a result.  frame(t) runs at the top of frame t;
+// every call is wave-uniform.  Compiled out (Enabled false) for shapes that
+// never share a CU.
+template <bool Enabled>
+struct ProgressPrio {
+  bool on;
+  int quarter;
+  int64_t next, step;
+  __device__ ProgressPrio(bool on_, int64_t t0, int64_t t1)
+      : on(Enabled && on_), quarter(0), next(t0 + (t1 - t0) / 4), step((t1 - t0) / 4) {
+    if constexpr (Enabled)
+      if (on) __builtin_amdgcn_s_setprio(3);
+  }
+  __device__ __forceinline__ void frame(int64_t t) {
+    if constexpr (Enabled) {
+      if (on && t == next && quarter < 3) {
+        ++quarter;
+        next += step;
+        if (quarter == 1) __builtin_amdgcn_s_setprio(2);
+        else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
+        else __builtin_amdgcn_s_setprio(0);
+      }
+    }
+  }
+  __device__ __forceinline__ void done() const {
+    if constexpr (Enabled)
+      if (on) __builtin_amdgcn_s_setprio(0);
+  }
+};
+
 // Deterministic block sum of four doubles per thread; result valid in thread 0..3 of `out`.
 template <int NT>
 __device__ __forceinline__ void block_sum4(double v[kMaxTypesDev], double* out) {

@@ -25,6 +25,7 @@ struct FusedArgs {
   int prog_len;
   int wave_rows;               // each wave grids only the rows it transforms (HostPlan::Variant::wave_rows)
   int dst_entries;             // program entries carry their cell (HostPlan::Variant::dst_entries)
+  int progress_prio;           // issue priority by slice progress (several workgroups per CU)
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]
@@ -193,6 +194,7 @@ struct AdjFusedArgs {
   int prog_len;
   int wave_rows;               // as FusedArgs::wave_rows
   int dst_entries;             // as FusedArgs::dst_entries
+  int progress_prio;           // as FusedArgs::progress_prio
   const float2* weights;       // [SX][n_weights]
   int n_weights;
   const float2* tw;            // [N]
