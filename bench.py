@@ -49,85 +49,85 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # the current sources.  Keyed by (workload, precision, shape variant,
 # workgroups); valid only for the kernel sources they were measured on,
 # identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "d7ce12b4a42b8721"
+TRAFFIC_SOURCES_SHA = "c691737985238181"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (25852, 58624),
-    (2, "f32", 0, 512): (33652, 51714),
-    (2, "f32", 0, 1024): (17514, 37892),
-    (2, "f32", 0, 2048): (18036, 75722),
-    (2, "f32", 0, 3072): (18508, 113438),
-    (2, "f32", 0, 4096): (18823, 151171),
-    (2, "f32", 0, 8192): (20148, 302417),
-    (2, "f32", 0, 16384): (20492, 605240),
-    (2, "f32", 1, 128): (25479, 57344),
+    (2, "f32", 0, 256): (26248, 59392),
+    (2, "f32", 0, 512): (34431, 53250),
+    (2, "f32", 0, 1024): (18818, 40964),
+    (2, "f32", 0, 2048): (19892, 80546),
+    (2, "f32", 0, 3072): (20940, 120077),
+    (2, "f32", 0, 4096): (21937, 159497),
+    (2, "f32", 0, 8192): (25833, 317852),
+    (2, "f32", 0, 16384): (31427, 639147),
+    (2, "f32", 1, 128): (25484, 57344),
     (2, "f32", 1, 256): (33154, 49154),
-    (2, "f32", 1, 512): (16800, 32772),
-    (2, "f32", 1, 1024): (16832, 65544),
-    (2, "f32", 1, 1536): (16778, 98316),
-    (2, "f32", 1, 2048): (16789, 131088),
-    (2, "f32", 1, 4096): (16826, 262176),
-    (2, "f32", 1, 8192): (16866, 524352),
-    (3, "f32", 0, 4096): (53699, 262144),
-    (3, "f32", 0, 8192): (49635, 524304),
-    (3, "f32", 0, 16384): (50336, 1048609),
-    (3, "f32", 0, 32768): (51046, 2097216),
-    (3, "f32", 0, 65536): (53560, 4194433),
-    (3, "f32", 0, 131072): (64318, 8388865),
-    (3, "f32", 0, 262144): (554737, 16777766),
-    (3, "f32", 1, 2048): (72934, 325478),
-    (3, "f32", 1, 4096): (67739, 640737),
-    (3, "f32", 1, 8192): (95682, 1282088),
-    (3, "f32", 1, 16384): (307076, 2605057),
-    (3, "f32", 1, 32768): (585809, 5210250),
-    (3, "f32", 1, 65536): (1191063, 10420538),
-    (3, "f32", 1, 131072): (2353919, 20841086),
+    (2, "f32", 1, 512): (16808, 32772),
+    (2, "f32", 1, 1024): (16844, 65544),
+    (2, "f32", 1, 1536): (16813, 98316),
+    (2, "f32", 1, 2048): (16840, 131088),
+    (2, "f32", 1, 4096): (16901, 262176),
+    (2, "f32", 1, 8192): (17141, 524352),
+    (3, "f32", 0, 4096): (54068, 262144),
+    (3, "f32", 0, 8192): (50221, 524304),
+    (3, "f32", 0, 16384): (51036, 1048608),
+    (3, "f32", 0, 32768): (52354, 2097216),
+    (3, "f32", 0, 65536): (59890, 4194432),
+    (3, "f32", 0, 131072): (71578, 8388867),
+    (3, "f32", 0, 262144): (1488600, 16777777),
+    (3, "f32", 1, 2048): (72355, 325460),
+    (3, "f32", 1, 4096): (67180, 640018),
+    (3, "f32", 1, 8192): (90003, 1275743),
+    (3, "f32", 1, 16384): (279704, 2603070),
+    (3, "f32", 1, 32768): (589544, 5210231),
+    (3, "f32", 1, 65536): (1183194, 10420532),
+    (3, "f32", 1, 131072): (2354792, 20841085),
     (4, "bf16", 0, 128): (129004, 8192),
-    (4, "bf16", 0, 256): (128440, 16393),
+    (4, "bf16", 0, 256): (128441, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
     (4, "bf16", 0, 1024): (129079, 65569),
-    (4, "bf16", 0, 2048): (129615, 131136),
-    (4, "bf16", 0, 4096): (129651, 262272),
-    (4, "bf16", 0, 8192): (130111, 524544),
+    (4, "bf16", 0, 2048): (129618, 131136),
+    (4, "bf16", 0, 4096): (129694, 262272),
+    (4, "bf16", 0, 8192): (130973, 524544),
     (4, "f16", 0, 128): (129019, 8192),
     (4, "f16", 0, 256): (128459, 16392),
     (4, "f16", 0, 512): (128672, 32784),
-    (4, "f16", 0, 768): (128884, 49177),
-    (4, "f16", 0, 1024): (129098, 65568),
-    (4, "f16", 0, 2048): (129628, 131136),
-    (4, "f16", 0, 4096): (129653, 262272),
-    (4, "f16", 0, 8192): (130000, 524544),
-    (4, "f32", 0, 256): (138493, 59008),
-    (4, "f32", 0, 512): (146353, 52482),
-    (4, "f32", 0, 1024): (130378, 39428),
-    (4, "f32", 0, 2048): (131440, 78397),
-    (4, "f32", 0, 3072): (132467, 117366),
-    (4, "f32", 0, 4096): (133490, 156365),
-    (4, "f32", 0, 8192): (137549, 312266),
-    (4, "f32", 0, 16384): (145711, 624456),
-    (4, "f32", 1, 128): (137530, 57344),
-    (4, "f32", 1, 256): (145203, 49154),
-    (4, "f32", 1, 512): (128897, 32772),
-    (4, "f32", 1, 1024): (129427, 65544),
-    (4, "f32", 1, 1536): (130059, 98316),
-    (4, "f32", 1, 2048): (130543, 131088),
-    (4, "f32", 1, 4096): (131418, 262176),
-    (4, "f32", 1, 8192): (129456, 524352),
-    (5, "f32", 0, 1024): (158656, 65536),
-    (5, "f32", 0, 2048): (151104, 131080),
-    (5, "f32", 0, 4096): (161600, 262160),
-    (5, "f32", 0, 8192): (143992, 524320),
-    (5, "f32", 0, 16384): (152538, 1048640),
-    (5, "f32", 0, 32768): (169551, 2097280),
-    (5, "f32", 0, 65536): (200852, 4194560),
-    (5, "f32", 1, 512): (152505, 83456),
-    (5, "f32", 1, 1024): (156781, 166921),
-    (5, "f32", 1, 2048): (182064, 333841),
-    (5, "f32", 1, 4096): (232325, 667678),
-    (5, "f32", 1, 8192): (332018, 1335346),
-    (5, "f32", 1, 16384): (532095, 2670710),
-    (5, "f32", 1, 32768): (941455, 5341441),
+    (4, "f16", 0, 768): (128884, 49176),
+    (4, "f16", 0, 1024): (129098, 65569),
+    (4, "f16", 0, 2048): (129637, 131136),
+    (4, "f16", 0, 4096): (129690, 262272),
+    (4, "f16", 0, 8192): (130851, 524545),
+    (4, "f32", 0, 256): (139022, 60032),
+    (4, "f32", 0, 512): (147401, 54530),
+    (4, "f32", 0, 1024): (132428, 43524),
+    (4, "f32", 0, 2048): (134004, 85967),
+    (4, "f32", 0, 3072): (135554, 128597),
+    (4, "f32", 0, 4096): (137106, 171523),
+    (4, "f32", 0, 8192): (143256, 343141),
+    (4, "f32", 0, 16384): (155681, 690130),
+    (4, "f32", 1, 128): (137520, 57344),
+    (4, "f32", 1, 256): (145195, 49154),
+    (4, "f32", 1, 512): (128868, 32772),
+    (4, "f32", 1, 1024): (129318, 65544),
+    (4, "f32", 1, 1536): (129760, 98316),
+    (4, "f32", 1, 2048): (130183, 131088),
+    (4, "f32", 1, 4096): (131591, 262176),
+    (4, "f32", 1, 8192): (131103, 524352),
+    (5, "f32", 0, 1024): (158843, 65536),
+    (5, "f32", 0, 2048): (151056, 131080),
+    (5, "f32", 0, 4096): (160434, 262160),
+    (5, "f32", 0, 8192): (144036, 524320),
+    (5, "f32", 0, 16384): (152646, 1048640),
+    (5, "f32", 0, 32768): (170683, 2097280),
+    (5, "f32", 0, 65536): (201069, 4194560),
+    (5, "f32", 1, 512): (152583, 83456),
+    (5, "f32", 1, 1024): (156838, 166921),
+    (5, "f32", 1, 2048): (182200, 333842),
+    (5, "f32", 1, 4096): (232853, 667681),
+    (5, "f32", 1, 8192): (333782, 1335360),
+    (5, "f32", 1, 16384): (536219, 2670720),
+    (5, "f32", 1, 32768): (941020, 5341446),
 }
 
 

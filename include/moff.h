@@ -248,7 +248,7 @@ moff_status moff_plan_mfma_tables(moff_plan plan, uint32_t* prog, uint16_t* dft,
  * on `hip_stream` using the caller's data and synchronises the stream.  It
  * first runs the default shape for about 200 ms so that no candidate is timed
  * on a cold device, then takes each candidate's time as the best of three
- * batches of three back-to-back calls, and keeps, of the candidates within 2 %
+ * batches of three back-to-back calls, and keeps, of the candidates within 3 %
  * of the fastest, the one with the fewest time slices (less scratch and fewer
  * partial images to reduce).  Later results do not depend on the choice
  * beyond float32 rounding order.  Unless the plan has a MOFF_MFMA_* flag, it also times the

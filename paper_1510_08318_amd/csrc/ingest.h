@@ -22,30 +22,34 @@ __device__ __forceinline__ float2 load_sample(const void* E, size_t idx, bool ci
 }
 
 // Issue priority by progress through a work item's frames [t0, t1), for
-// kernels whose workgroups share a CU: 3 in the first quarter of the frames,
-// down to 0 in the last.  Otherwise a CU's oldest waves issue first, its
-// workgroups advance unevenly, and the first to finish leaves the CU short of
-// waves for the others' remaining frames.  Only the order in which ready
-// waves issue changes, never a result.  frame(t) runs at the top of frame t;
-// every call is wave-uniform.  Compiled out (Enabled false) for shapes that
-// never share a CU.
+// kernels whose workgroups share a CU: 3 in the first half of the frames, 2
+// in the next fourth, 1 in the next eighth and 0 in the last eighth.
+// Otherwise a CU's oldest waves issue first, its workgroups advance unevenly,
+// and the first to finish leaves the CU short of waves for the others'
+// remaining frames.  A workgroup that has fallen behind across a boundary
+// outranks the ones ahead until it catches up, so the spread left at the end
+// is what builds up within the last, shortest segment.  Only the order in
+// which ready waves issue changes, never a result.  frame(t) runs at the top
+// of frame t; every call is wave-uniform.  Compiled out (Enabled false) for
+// shapes that never share a CU.
 template <bool Enabled>
 struct ProgressPrio {
   bool on;
-  int quarter;
+  int level;   // boundaries crossed
   int64_t next, step;
   __device__ ProgressPrio(bool on_, int64_t t0, int64_t t1)
-      : on(Enabled && on_), quarter(0), next(t0 + (t1 - t0) / 4), step((t1 - t0) / 4) {
+      : on(Enabled && on_), level(0), next(t0 + (t1 - t0) / 2), step((t1 - t0) / 4) {
     if constexpr (Enabled)
       if (on) __builtin_amdgcn_s_setprio(3);
   }
   __device__ __forceinline__ void frame(int64_t t) {
     if constexpr (Enabled) {
-      if (on && t == next && quarter < 3) {
-        ++quarter;
+      if (on && t == next && level < 3) {
+        ++level;
         next += step;
-        if (quarter == 1) __builtin_amdgcn_s_setprio(2);
-        else if (quarter == 2) __builtin_amdgcn_s_setprio(1);
+        step /= 2;
+        if (level == 1) __builtin_amdgcn_s_setprio(2);
+        else if (level == 2) __builtin_amdgcn_s_setprio(1);
         else __builtin_amdgcn_s_setprio(0);
       }
     }

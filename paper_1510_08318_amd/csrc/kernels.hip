@@ -210,7 +210,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
   bool flushed = false;
   int in_block = 0;
 
-  // (at the LWA shape with one round of four workgroups per CU: 2.22 ms with
+  // (at the LWA shape with one round of four workgroups per CU: 2.17 ms with
   // the progress priority, 2.42 ms without)
   ProgressPrio<shares_cu(N, V)> prio(a.progress_prio != 0, t0, t1);
   __syncthreads();
