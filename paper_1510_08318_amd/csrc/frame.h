@@ -106,6 +106,7 @@ __device__ __forceinline__ void row_stage(float2* G, const float2* twr, const fl
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::RPW;
+  const float2* twrl = twr + sub;   // twrl[q1 QR + LPR ja] = twr[q1 QR + n2]
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
     const int row = stage_row(C::S, rs, wave, lane % C::RPW);
@@ -121,10 +122,9 @@ __device__ __forceinline__ void row_stage(float2* G, const float2* twr, const fl
       }
 #pragma unroll
     for (int ja = 0; ja < C::JAR; ++ja) {
-      const int n2 = sub + C::LPR * ja;
       dft_pruned<C::PR, C::PRNZ>(x[ja]);
 #pragma unroll
-      for (int q1 = (C::SX > 1 ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twr[q1 * C::QR + n2]);
+      for (int q1 = (C::SX > 1 ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twrl[q1 * C::QR + C::LPR * ja]);
     }
     wave_sync();
 #pragma unroll
@@ -158,6 +158,7 @@ __device__ __forceinline__ void row_stage_w(float2* G, const float2* twr) {
   constexpr bool kFold = C::SX > 1 && W != 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::RPW;
+  const float2* twrl = twr + sub;   // twrl[q1 QR + LPR ja] = twr[q1 QR + n2]
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
     const int row = stage_row(C::S, rs, wave, lane % C::RPW);
@@ -173,10 +174,9 @@ __device__ __forceinline__ void row_stage_w(float2* G, const float2* twr) {
       });
 #pragma unroll
     for (int ja = 0; ja < C::JAR; ++ja) {
-      const int n2 = sub + C::LPR * ja;
       dft_pruned<C::PR, C::PRNZ>(x[ja]);
 #pragma unroll
-      for (int q1 = (kFold ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twr[q1 * C::QR + n2]);
+      for (int q1 = (kFold ? 0 : 1); q1 < C::PR; ++q1) x[ja][q1] = c_mul(x[ja][q1], twrl[q1 * C::QR + C::LPR * ja]);
     }
     wave_sync();
 #pragma unroll
@@ -211,6 +211,7 @@ __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& s
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::CPW;
+  const float2* twl = twc + sub;   // twl[q1 QC + LPC ja] = twc[q1 QC + n2]
 #pragma unroll
   for (int cs = 0; cs < C::CSTEPS; ++cs) {
     const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
@@ -226,7 +227,6 @@ __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& s
       constexpr int s = decltype(sc)::value;
 #pragma unroll
       for (int ja = 0; ja < C::JA; ++ja) {
-        const int n2 = sub + C::LPC * ja;
         float2 u[C::PH];
         static_for<0, C::PH>([&](auto nc) {
           constexpr int n1 = decltype(nc)::value;
@@ -237,7 +237,7 @@ __device__ __forceinline__ void col_stage(float2* G, const float2* twc, Sink&& s
 #pragma unroll
         for (int j = 0; j < C::PH; ++j) {
           const int q1 = 2 * j + s;
-          if (q1 != 0) u[j] = c_mul(u[j], twc[q1 * C::QC + n2]);
+          if (q1 != 0) u[j] = c_mul(u[j], twl[q1 * C::QC + C::LPC * ja]);
           Zc[(C::LPC * ja + j * C::QC) * C::P] = u[j];
         }
       }
@@ -308,6 +308,7 @@ __device__ __forceinline__ void col_stage_adjoint(float2* G, const float2* twc, 
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::CPW;
+  const float2* twb = twc + 2 * sub * C::QC;   // twb[(2 LPC jb + s) QC + n2] = twc[q1 QC + n2]
 #pragma unroll
   for (int cs = 0; cs < C::CSTEPS; ++cs) {
     const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
@@ -333,7 +334,7 @@ __device__ __forceinline__ void col_stage_adjoint(float2* G, const float2* twc, 
         idft<C::QC>(v);
 #pragma unroll
         for (int n2 = 0; n2 < C::QC; ++n2) {
-          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twc[q1 * C::QC + n2]);
+          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twb[(2 * C::LPC * jb + s) * C::QC + n2]);
           Zb[(C::LPC * jb * C::QC + n2) * C::P] = v[n2];
         }
       }
@@ -374,6 +375,8 @@ __device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::CPW;
+  const float2* twb = twc + 2 * sub * C::QC;   // twb[(2 LPC jb + s) QC + n2] = twc[q1 QC + n2]
+  const float2* twl = twc + sub;   // twl[q1 QC + LPC ja] = twc[q1 QC + n2]
 #pragma unroll
   for (int cs = 0; cs < C::CSTEPS; ++cs) {
     const int col = (cs * C::NW + wave) * C::CPW + lane % C::CPW;
@@ -394,7 +397,6 @@ __device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc
       // forward pass A, half-round s
 #pragma unroll
       for (int ja = 0; ja < C::JA; ++ja) {
-        const int n2 = sub + C::LPC * ja;
         float2 u[C::PH];
         static_for<0, C::PH>([&](auto nc) {
           constexpr int n1 = decltype(nc)::value;
@@ -405,7 +407,7 @@ __device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc
 #pragma unroll
         for (int j = 0; j < C::PH; ++j) {
           const int q1 = 2 * j + s;
-          if (q1 != 0) u[j] = c_mul(u[j], twc[q1 * C::QC + n2]);
+          if (q1 != 0) u[j] = c_mul(u[j], twl[q1 * C::QC + C::LPC * ja]);
           Zc[(C::LPC * ja + j * C::QC) * C::P] = u[j];
         }
       }
@@ -426,7 +428,7 @@ __device__ __forceinline__ void col_stage_roundtrip(float2* G, const float2* twc
         idft<C::QC>(v);
 #pragma unroll
         for (int n2 = 0; n2 < C::QC; ++n2) {
-          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twc[q1 * C::QC + n2]);
+          if (q1 != 0) v[n2] = c_mul_conj(v[n2], twb[(2 * C::LPC * jb + s) * C::QC + n2]);
           Zb[(C::LPC * jb * C::QC + n2) * C::P] = v[n2];
         }
       }
@@ -461,6 +463,7 @@ __device__ __forceinline__ void row_stage_adjoint(float2* G, const float2* twr, 
   using C = FT<N, V>;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::RPW;
+  const float2* twrb = twr + sub * C::QR;   // twrb[LPR jb QR + n2] = twr[q1 QR + n2]
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
     const int row = stage_row(C::S, rs, wave, lane % C::RPW);
@@ -478,7 +481,7 @@ __device__ __forceinline__ void row_stage_adjoint(float2* G, const float2* twr, 
       idft<C::QR>(y[jb]);
 #pragma unroll
       for (int n2 = 0; n2 < C::QR; ++n2) {
-        if (C::SX > 1 || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twr[q1 * C::QR + n2]);
+        if (C::SX > 1 || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twrb[C::LPR * jb * C::QR + n2]);
         R[q1 * C::QR + n2] = y[jb][n2];
       }
     }
@@ -509,6 +512,7 @@ __device__ __forceinline__ void row_stage_adjoint_w(float2* G, const float2* twr
   constexpr bool kFold = C::SX > 1 && W != 0;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int sub = lane / C::RPW;
+  const float2* twrb = twr + sub * C::QR;   // twrb[LPR jb QR + n2] = twr[q1 QR + n2]
 #pragma unroll
   for (int rs = 0; rs < C::RSTEPS; ++rs) {
     const int row = stage_row(C::S, rs, wave, lane % C::RPW);
@@ -526,7 +530,7 @@ __device__ __forceinline__ void row_stage_adjoint_w(float2* G, const float2* twr
       idft<C::QR>(y[jb]);
 #pragma unroll
       for (int n2 = 0; n2 < C::QR; ++n2) {
-        if (kFold || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twr[q1 * C::QR + n2]);
+        if (kFold || q1 != 0) y[jb][n2] = c_mul_conj(y[jb][n2], twrb[C::LPR * jb * C::QR + n2]);
         R[q1 * C::QR + n2] = y[jb][n2];
       }
     }
