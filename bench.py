@@ -49,85 +49,85 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # the current sources.  Keyed by (workload, precision, shape variant,
 # workgroups); valid only for the kernel sources they were measured on,
 # identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "c691737985238181"
+TRAFFIC_SOURCES_SHA = "37e9a911adcdaca4"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (26248, 59392),
-    (2, "f32", 0, 512): (34431, 53250),
-    (2, "f32", 0, 1024): (18818, 40964),
-    (2, "f32", 0, 2048): (19892, 80546),
-    (2, "f32", 0, 3072): (20940, 120077),
-    (2, "f32", 0, 4096): (21937, 159497),
-    (2, "f32", 0, 8192): (25833, 317852),
-    (2, "f32", 0, 16384): (31427, 639147),
-    (2, "f32", 1, 128): (25484, 57344),
-    (2, "f32", 1, 256): (33154, 49154),
-    (2, "f32", 1, 512): (16808, 32772),
-    (2, "f32", 1, 1024): (16844, 65544),
-    (2, "f32", 1, 1536): (16813, 98316),
-    (2, "f32", 1, 2048): (16840, 131088),
-    (2, "f32", 1, 4096): (16901, 262176),
-    (2, "f32", 1, 8192): (17141, 524352),
-    (3, "f32", 0, 4096): (54068, 262144),
-    (3, "f32", 0, 8192): (50221, 524304),
-    (3, "f32", 0, 16384): (51036, 1048608),
-    (3, "f32", 0, 32768): (52354, 2097216),
-    (3, "f32", 0, 65536): (59890, 4194432),
-    (3, "f32", 0, 131072): (71578, 8388867),
-    (3, "f32", 0, 262144): (1488600, 16777777),
-    (3, "f32", 1, 2048): (72355, 325460),
-    (3, "f32", 1, 4096): (67180, 640018),
-    (3, "f32", 1, 8192): (90003, 1275743),
-    (3, "f32", 1, 16384): (279704, 2603070),
-    (3, "f32", 1, 32768): (589544, 5210231),
-    (3, "f32", 1, 65536): (1183194, 10420532),
-    (3, "f32", 1, 131072): (2354792, 20841085),
+    (2, "f32", 0, 256): (25800, 58496),
+    (2, "f32", 0, 512): (33538, 51458),
+    (2, "f32", 0, 1024): (17281, 37380),
+    (2, "f32", 0, 2048): (17545, 74760),
+    (2, "f32", 0, 3072): (17800, 112010),
+    (2, "f32", 0, 4096): (18033, 149257),
+    (2, "f32", 0, 8192): (18777, 297926),
+    (2, "f32", 0, 16384): (18359, 597152),
+    (2, "f32", 1, 128): (25502, 57344),
+    (2, "f32", 1, 256): (33177, 49154),
+    (2, "f32", 1, 512): (16835, 32772),
+    (2, "f32", 1, 1024): (16869, 65544),
+    (2, "f32", 1, 1536): (16835, 98316),
+    (2, "f32", 1, 2048): (16863, 131088),
+    (2, "f32", 1, 4096): (16926, 262176),
+    (2, "f32", 1, 8192): (17197, 524352),
+    (3, "f32", 0, 4096): (54500, 262144),
+    (3, "f32", 0, 8192): (50233, 524304),
+    (3, "f32", 0, 16384): (51199, 1048608),
+    (3, "f32", 0, 32768): (52554, 2097216),
+    (3, "f32", 0, 65536): (59860, 4194432),
+    (3, "f32", 0, 131072): (81997, 8388867),
+    (3, "f32", 0, 262144): (1485700, 16777751),
+    (3, "f32", 1, 2048): (76764, 311113),
+    (3, "f32", 1, 4096): (64718, 621267),
+    (3, "f32", 1, 8192): (122818, 1245159),
+    (3, "f32", 1, 16384): (238487, 2490363),
+    (3, "f32", 1, 32768): (462305, 4980797),
+    (3, "f32", 1, 65536): (948862, 9961757),
+    (3, "f32", 1, 131072): (1875706, 19923526),
     (4, "bf16", 0, 128): (129004, 8192),
-    (4, "bf16", 0, 256): (128441, 16393),
+    (4, "bf16", 0, 256): (128440, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
     (4, "bf16", 0, 1024): (129079, 65569),
-    (4, "bf16", 0, 2048): (129618, 131136),
-    (4, "bf16", 0, 4096): (129694, 262272),
-    (4, "bf16", 0, 8192): (130973, 524544),
+    (4, "bf16", 0, 2048): (129616, 131136),
+    (4, "bf16", 0, 4096): (129688, 262272),
+    (4, "bf16", 0, 8192): (130920, 524544),
     (4, "f16", 0, 128): (129019, 8192),
     (4, "f16", 0, 256): (128459, 16392),
     (4, "f16", 0, 512): (128672, 32784),
-    (4, "f16", 0, 768): (128884, 49176),
-    (4, "f16", 0, 1024): (129098, 65569),
-    (4, "f16", 0, 2048): (129637, 131136),
-    (4, "f16", 0, 4096): (129690, 262272),
-    (4, "f16", 0, 8192): (130851, 524545),
-    (4, "f32", 0, 256): (139022, 60032),
-    (4, "f32", 0, 512): (147401, 54530),
-    (4, "f32", 0, 1024): (132428, 43524),
-    (4, "f32", 0, 2048): (134004, 85967),
-    (4, "f32", 0, 3072): (135554, 128597),
-    (4, "f32", 0, 4096): (137106, 171523),
-    (4, "f32", 0, 8192): (143256, 343141),
-    (4, "f32", 0, 16384): (155681, 690130),
-    (4, "f32", 1, 128): (137520, 57344),
-    (4, "f32", 1, 256): (145195, 49154),
-    (4, "f32", 1, 512): (128868, 32772),
-    (4, "f32", 1, 1024): (129318, 65544),
-    (4, "f32", 1, 1536): (129760, 98316),
-    (4, "f32", 1, 2048): (130183, 131088),
-    (4, "f32", 1, 4096): (131591, 262176),
-    (4, "f32", 1, 8192): (131103, 524352),
-    (5, "f32", 0, 1024): (158843, 65536),
-    (5, "f32", 0, 2048): (151056, 131080),
-    (5, "f32", 0, 4096): (160434, 262160),
-    (5, "f32", 0, 8192): (144036, 524320),
-    (5, "f32", 0, 16384): (152646, 1048640),
-    (5, "f32", 0, 32768): (170683, 2097280),
-    (5, "f32", 0, 65536): (201069, 4194560),
-    (5, "f32", 1, 512): (152583, 83456),
-    (5, "f32", 1, 1024): (156838, 166921),
-    (5, "f32", 1, 2048): (182200, 333842),
-    (5, "f32", 1, 4096): (232853, 667681),
-    (5, "f32", 1, 8192): (333782, 1335360),
-    (5, "f32", 1, 16384): (536219, 2670720),
-    (5, "f32", 1, 32768): (941020, 5341446),
+    (4, "f16", 0, 768): (128885, 49176),
+    (4, "f16", 0, 1024): (129098, 65568),
+    (4, "f16", 0, 2048): (129632, 131136),
+    (4, "f16", 0, 4096): (129727, 262272),
+    (4, "f16", 0, 8192): (130895, 524544),
+    (4, "f32", 0, 256): (138445, 58880),
+    (4, "f32", 0, 512): (146250, 52226),
+    (4, "f32", 0, 1024): (130123, 38916),
+    (4, "f32", 0, 2048): (130929, 77415),
+    (4, "f32", 0, 3072): (131710, 115918),
+    (4, "f32", 0, 4096): (132494, 154421),
+    (4, "f32", 0, 8192): (135550, 308585),
+    (4, "f32", 0, 16384): (141657, 620822),
+    (4, "f32", 1, 128): (137537, 57344),
+    (4, "f32", 1, 256): (145215, 49154),
+    (4, "f32", 1, 512): (128910, 32772),
+    (4, "f32", 1, 1024): (129430, 65544),
+    (4, "f32", 1, 1536): (129944, 98316),
+    (4, "f32", 1, 2048): (130434, 131088),
+    (4, "f32", 1, 4096): (131993, 262176),
+    (4, "f32", 1, 8192): (131294, 524352),
+    (5, "f32", 0, 1024): (158948, 65536),
+    (5, "f32", 0, 2048): (151513, 131080),
+    (5, "f32", 0, 4096): (163068, 262160),
+    (5, "f32", 0, 8192): (144393, 524320),
+    (5, "f32", 0, 16384): (153191, 1048640),
+    (5, "f32", 0, 32768): (171328, 2097281),
+    (5, "f32", 0, 65536): (201426, 4194560),
+    (5, "f32", 1, 512): (150421, 79360),
+    (5, "f32", 1, 1024): (152891, 158730),
+    (5, "f32", 1, 2048): (174309, 317458),
+    (5, "f32", 1, 4096): (217027, 634913),
+    (5, "f32", 1, 8192): (301710, 1269824),
+    (5, "f32", 1, 16384): (471695, 2539646),
+    (5, "f32", 1, 32768): (811340, 5079298),
 }
 
 
