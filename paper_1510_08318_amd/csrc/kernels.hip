@@ -167,8 +167,12 @@ constexpr bool shares_cu(int N, int V) { return !(N == 256 && V == 1); }
 
 // One work item of the fused kernel: column class W (a compile-time constant,
 // so the row stage's fold factors are constant rotations), channel c and a
-// slice of time samples.
-template <int N, int V, bool CI4, int W>
+// slice of time samples.  ONE: every lane ingests at most one antenna
+// (n_ant <= NT), so a lane's self power is one float64 sum, given its type
+// after the frame loop, instead of one running sum per antenna type (8 fewer
+// registers held through the loop: at the HERA shape 1 spilled register
+// instead of 24).  The sums are the same either way.
+template <int N, int V, bool CI4, int W, bool ONE>
 __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, double* Atot, int c, int slice,
                                            int item) {
   using C = FT<N, V>;
@@ -203,6 +207,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
 #pragma unroll
   for (int i = 0; i < C::NACC; ++i) acc[i] = 0.f;
   double pw[kMaxTypesDev] = {0.0, 0.0, 0.0, 0.0};
+  double pw1 = 0.0;   // ONE: the lane's antenna's self power
   // float64 running sums of this workgroup's pixels (blocked accumulation),
   // laid out [item][acc index][lane]: a uniform base per accumulator index
   // plus the lane's offset, so no per-lane address stays live in the loop
@@ -222,11 +227,19 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
       const float2 v = c_mul(gl[i], raw_v);
       e[i] = v;
       const double p = static_cast<double>(v.x) * v.x + static_cast<double>(v.y) * v.y;
-      const int tp = ty[i];
+      if constexpr (ONE) {
+        pw1 += p;
+      } else {
+        const int tp = ty[i];
 #pragma unroll
-      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+        for (int q = 0; q < kMaxTypesDev; ++q) pw[q] += (tp == q) ? p : 0.0;
+      }
     };
-    for (int i = tid; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
+    if constexpr (ONE) {
+      if (tid < a.n_ant) take(tid, load_sample(a.E, base + tid, CI4));
+    } else {
+      for (int i = tid; i < a.n_ant; i += NT) take(i, load_sample(a.E, base + i, CI4));
+    }
     __syncthreads();
     gather_frame_any<NT, kGatherBatch, kGatherSub, C::NZR, C::P>(prog, progw, a.prog_len, cell0, a.dst_entries, e,
                                                                  Wt, G);
@@ -263,6 +276,13 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
   }
 
   prio.done();
+  if constexpr (ONE) {
+    if (tid < a.n_ant) {
+      const int tp = ty[tid];
+#pragma unroll
+      for (int q = 0; q < kMaxTypesDev; ++q) pw[q] = (tp == q) ? pw1 : 0.0;
+    }
+  }
   // (its barriers also end every wave's use of the folded grid)
   block_sum4<NT>(pw, Atot);
 
@@ -337,7 +357,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, float2* lds, doub
 // apart: the classes share their samples in that XCD's L2, and neighbouring
 // channels share the 128-byte lines their samples straddle.  The grid pads the
 // (channel, slice) count to a multiple of kXcds.
-template <int N, int V, bool CI4>
+template <int N, int V, bool CI4, bool ONE>
 __global__ __launch_bounds__((FT<N, V>::NT)) __attribute__((amdgpu_waves_per_eu(fused_waves_per_simd<N, V>())))
 void fused_kernel(FusedArgs a) {
   using C = FT<N, V>;
@@ -352,7 +372,7 @@ void fused_kernel(FusedArgs a) {
   const int item = cs * C::SX + w;
   static_for<0, C::SX>([&](auto wc) {
     constexpr int W = decltype(wc)::value;
-    if (w == W) fused_item<N, V, CI4, W>(a, lds, Atot, c, slice, item);
+    if (w == W) fused_item<N, V, CI4, W, ONE>(a, lds, Atot, c, slice, item);
   });
 }
 
@@ -853,22 +873,24 @@ size_t fused_lds_bytes(int N, int V, int n_weights, int n_ant) {
 namespace {
 
 template <int N, int V, bool CI4>
-const void* fused_symbol() {
-  return reinterpret_cast<const void*>(fused_kernel<N, V, CI4>);
+const void* fused_symbol(bool one) {
+  return one ? reinterpret_cast<const void*>(fused_kernel<N, V, CI4, true>)
+             : reinterpret_cast<const void*>(fused_kernel<N, V, CI4, false>);
 }
 
 template <int N, int V>
-const void* fused_symbol_v(bool ci4) {
+const void* fused_symbol_v(bool ci4, bool one) {
   if constexpr (frame_shape(N, V).N == N)
-    return ci4 ? fused_symbol<N, V, true>() : fused_symbol<N, V, false>();
+    return ci4 ? fused_symbol<N, V, true>(one) : fused_symbol<N, V, false>(one);
   else
     return nullptr;
 }
 
-const void* fused_kernel_symbol(int N, int V, bool ci4) {
+// one: the variant for at most one antenna per lane (n_ant <= threads)
+const void* fused_kernel_symbol(int N, int V, bool ci4, bool one) {
   auto pick = [&](auto nc) -> const void* {
     constexpr int NN = decltype(nc)::value;
-    return V == 0 ? fused_symbol_v<NN, 0>(ci4) : V == 1 ? fused_symbol_v<NN, 1>(ci4) : nullptr;
+    return V == 0 ? fused_symbol_v<NN, 0>(ci4, one) : V == 1 ? fused_symbol_v<NN, 1>(ci4, one) : nullptr;
   };
   switch (N) {
     case 8: return pick(std::integral_constant<int, 8>{});
@@ -898,9 +920,9 @@ unsigned blocks_for(size_t n) { return static_cast<unsigned>((n + 255) / 256); }
 }  // namespace
 
 hipError_t launch_fused(const FusedArgs& a, int N, int V, bool ci4, int grid, hipStream_t st) {
-  const void* k = fused_kernel_symbol(N, V, ci4);
-  if (!k) return hipErrorInvalidValue;
   const FrameShape S = frame_shape(N, V);
+  const void* k = fused_kernel_symbol(N, V, ci4, a.n_ant <= S.NT);
+  if (!k) return hipErrorInvalidValue;
   // the kernel's decode assumes SX classes times a whole number of XCD rounds
   // covering every (channel, slice)
   if (grid <= 0 || grid % (S.SX * kXcds) != 0 || static_cast<int64_t>(grid / S.SX) < static_cast<int64_t>(a.n_chan) * a.slices)
@@ -1042,7 +1064,8 @@ hipError_t launch_adjoint_reduce(const double2* Dp, int parts, int n_chan, int n
 }
 
 int fused_blocks_per_cu(int N, int V, bool ci4, size_t lds) {
-  const void* k = fused_kernel_symbol(N, V, ci4);
+  // (both antenna variants are sized for the same waves per SIMD)
+  const void* k = fused_kernel_symbol(N, V, ci4, false);
   if (!k) return 0;
   int blocks = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k, frame_shape(N, V).NT, lds) != hipSuccess) return 0;
