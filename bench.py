@@ -49,85 +49,85 @@ PEAK_MFMA_16BIT_TFLOPS = 2500.0   # MI355X dense fp16 / bf16 matrix peak (spec s
 # the current sources.  Keyed by (workload, precision, shape variant,
 # workgroups); valid only for the kernel sources they were measured on,
 # identified by TRAFFIC_SOURCES_SHA (KERNEL_SOURCES).
-TRAFFIC_SOURCES_SHA = "37e9a911adcdaca4"
+TRAFFIC_SOURCES_SHA = "e4f70da47563606b"
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131093.0, 1.0
 TRAFFIC_KIB = {
-    (2, "f32", 0, 256): (25800, 58496),
-    (2, "f32", 0, 512): (33538, 51458),
-    (2, "f32", 0, 1024): (17281, 37380),
-    (2, "f32", 0, 2048): (17545, 74760),
-    (2, "f32", 0, 3072): (17800, 112010),
-    (2, "f32", 0, 4096): (18033, 149257),
-    (2, "f32", 0, 8192): (18777, 297926),
-    (2, "f32", 0, 16384): (18359, 597152),
-    (2, "f32", 1, 128): (25502, 57344),
-    (2, "f32", 1, 256): (33177, 49154),
-    (2, "f32", 1, 512): (16835, 32772),
-    (2, "f32", 1, 1024): (16869, 65544),
-    (2, "f32", 1, 1536): (16835, 98316),
-    (2, "f32", 1, 2048): (16863, 131088),
-    (2, "f32", 1, 4096): (16926, 262176),
-    (2, "f32", 1, 8192): (17197, 524352),
-    (3, "f32", 0, 4096): (54500, 262144),
-    (3, "f32", 0, 8192): (50233, 524304),
-    (3, "f32", 0, 16384): (51199, 1048608),
-    (3, "f32", 0, 32768): (52554, 2097216),
-    (3, "f32", 0, 65536): (59860, 4194432),
-    (3, "f32", 0, 131072): (81997, 8388867),
-    (3, "f32", 0, 262144): (1485700, 16777751),
-    (3, "f32", 1, 2048): (76764, 311113),
-    (3, "f32", 1, 4096): (64718, 621267),
-    (3, "f32", 1, 8192): (122818, 1245159),
-    (3, "f32", 1, 16384): (238487, 2490363),
-    (3, "f32", 1, 32768): (462305, 4980797),
-    (3, "f32", 1, 65536): (948862, 9961757),
-    (3, "f32", 1, 131072): (1875706, 19923526),
+    (2, "f32", 0, 256): (25802, 57728),
+    (2, "f32", 0, 512): (33537, 49922),
+    (2, "f32", 0, 1024): (17279, 34308),
+    (2, "f32", 0, 2048): (17534, 68562),
+    (2, "f32", 0, 3072): (17787, 102787),
+    (2, "f32", 0, 4096): (17891, 137051),
+    (2, "f32", 0, 8192): (17492, 273957),
+    (2, "f32", 0, 16384): (17334, 548572),
+    (2, "f32", 1, 128): (25488, 57344),
+    (2, "f32", 1, 256): (33167, 49154),
+    (2, "f32", 1, 512): (16802, 32772),
+    (2, "f32", 1, 1024): (16905, 65544),
+    (2, "f32", 1, 1536): (16820, 98316),
+    (2, "f32", 1, 2048): (16871, 131088),
+    (2, "f32", 1, 4096): (16931, 262176),
+    (2, "f32", 1, 8192): (17274, 524352),
+    (3, "f32", 0, 4096): (54035, 262144),
+    (3, "f32", 0, 8192): (50060, 524304),
+    (3, "f32", 0, 16384): (50853, 1048609),
+    (3, "f32", 0, 32768): (52323, 2097217),
+    (3, "f32", 0, 65536): (58021, 4194433),
+    (3, "f32", 0, 131072): (73561, 8388866),
+    (3, "f32", 0, 262144): (1486197, 16777747),
+    (3, "f32", 1, 2048): (70928, 286676),
+    (3, "f32", 1, 4096): (60810, 573356),
+    (3, "f32", 1, 8192): (102210, 1146896),
+    (3, "f32", 1, 16384): (163573, 2293809),
+    (3, "f32", 1, 32768): (319042, 4587654),
+    (3, "f32", 1, 65536): (656732, 9175348),
+    (3, "f32", 1, 131072): (1296538, 18350714),
     (4, "bf16", 0, 128): (129004, 8192),
-    (4, "bf16", 0, 256): (128440, 16393),
+    (4, "bf16", 0, 256): (128441, 16393),
     (4, "bf16", 0, 512): (128653, 32785),
     (4, "bf16", 0, 768): (128866, 49177),
     (4, "bf16", 0, 1024): (129079, 65569),
     (4, "bf16", 0, 2048): (129616, 131136),
-    (4, "bf16", 0, 4096): (129688, 262272),
-    (4, "bf16", 0, 8192): (130920, 524544),
+    (4, "bf16", 0, 4096): (129734, 262272),
+    (4, "bf16", 0, 8192): (130841, 524546),
     (4, "f16", 0, 128): (129019, 8192),
-    (4, "f16", 0, 256): (128459, 16392),
+    (4, "f16", 0, 256): (128460, 16392),
     (4, "f16", 0, 512): (128672, 32784),
-    (4, "f16", 0, 768): (128885, 49176),
-    (4, "f16", 0, 1024): (129098, 65568),
-    (4, "f16", 0, 2048): (129632, 131136),
-    (4, "f16", 0, 4096): (129727, 262272),
-    (4, "f16", 0, 8192): (130895, 524544),
-    (4, "f32", 0, 256): (138445, 58880),
-    (4, "f32", 0, 512): (146250, 52226),
-    (4, "f32", 0, 1024): (130123, 38916),
-    (4, "f32", 0, 2048): (130929, 77415),
-    (4, "f32", 0, 3072): (131710, 115918),
-    (4, "f32", 0, 4096): (132494, 154421),
-    (4, "f32", 0, 8192): (135550, 308585),
-    (4, "f32", 0, 16384): (141657, 620822),
+    (4, "f16", 0, 768): (128885, 49177),
+    (4, "f16", 0, 1024): (129098, 65569),
+    (4, "f16", 0, 2048): (129633, 131137),
+    (4, "f16", 0, 4096): (129757, 262272),
+    (4, "f16", 0, 8192): (130846, 524544),
+    (4, "f32", 0, 256): (137860, 57728),
+    (4, "f32", 0, 512): (145601, 49922),
+    (4, "f32", 0, 1024): (129344, 34308),
+    (4, "f32", 0, 2048): (129634, 68616),
+    (4, "f32", 0, 3072): (129903, 102924),
+    (4, "f32", 0, 4096): (130175, 137232),
+    (4, "f32", 0, 8192): (131174, 274464),
+    (4, "f32", 0, 16384): (133180, 548853),
     (4, "f32", 1, 128): (137537, 57344),
-    (4, "f32", 1, 256): (145215, 49154),
-    (4, "f32", 1, 512): (128910, 32772),
-    (4, "f32", 1, 1024): (129430, 65544),
-    (4, "f32", 1, 1536): (129944, 98316),
-    (4, "f32", 1, 2048): (130434, 131088),
-    (4, "f32", 1, 4096): (131993, 262176),
-    (4, "f32", 1, 8192): (131294, 524352),
-    (5, "f32", 0, 1024): (158948, 65536),
-    (5, "f32", 0, 2048): (151513, 131080),
-    (5, "f32", 0, 4096): (163068, 262160),
-    (5, "f32", 0, 8192): (144393, 524320),
-    (5, "f32", 0, 16384): (153191, 1048640),
-    (5, "f32", 0, 32768): (171328, 2097281),
-    (5, "f32", 0, 65536): (201426, 4194560),
-    (5, "f32", 1, 512): (150421, 79360),
-    (5, "f32", 1, 1024): (152891, 158730),
-    (5, "f32", 1, 2048): (174309, 317458),
-    (5, "f32", 1, 4096): (217027, 634913),
-    (5, "f32", 1, 8192): (301710, 1269824),
-    (5, "f32", 1, 16384): (471695, 2539646),
-    (5, "f32", 1, 32768): (811340, 5079298),
+    (4, "f32", 1, 256): (145210, 49154),
+    (4, "f32", 1, 512): (128915, 32772),
+    (4, "f32", 1, 1024): (129386, 65544),
+    (4, "f32", 1, 1536): (129854, 98316),
+    (4, "f32", 1, 2048): (130301, 131088),
+    (4, "f32", 1, 4096): (131640, 262176),
+    (4, "f32", 1, 8192): (130414, 524352),
+    (5, "f32", 0, 1024): (158456, 65536),
+    (5, "f32", 0, 2048): (150892, 131080),
+    (5, "f32", 0, 4096): (160215, 262160),
+    (5, "f32", 0, 8192): (143492, 524320),
+    (5, "f32", 0, 16384): (151870, 1048640),
+    (5, "f32", 0, 32768): (168397, 2097280),
+    (5, "f32", 0, 65536): (201060, 4194560),
+    (5, "f32", 1, 512): (150456, 79360),
+    (5, "f32", 1, 1024): (152983, 158729),
+    (5, "f32", 1, 2048): (174530, 317458),
+    (5, "f32", 1, 4096): (217594, 634913),
+    (5, "f32", 1, 8192): (303225, 1269824),
+    (5, "f32", 1, 16384): (474974, 2539648),
+    (5, "f32", 1, 32768): (818068, 5079296),
 }
 
 
