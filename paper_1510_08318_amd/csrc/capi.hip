@@ -888,7 +888,7 @@ moff_status moff_plan_autotune(moff_plan p, const void* E, int64_t n_time, const
           if (result == MOFF_OK && hipEventElapsedTime(&one, e0, e1) != hipSuccess) result = MOFF_ERR_HIP;
           if (result == MOFF_OK) ms = std::min(ms, one);
         }
-        if (result == MOFF_OK) {
+        if (result == MOFF_OK && n_timed < static_cast<int>(sizeof(timed) / sizeof(timed[0]))) {
           timed[n_timed++] = {v, sl, ms};
           best = std::min(best, ms);
         }
