@@ -311,6 +311,26 @@ def test_every_variant_and_slicing(torch, moff, case):
                 assert_image_close(got.cpu().numpy(), ref, pbar, label=f"{case} v{v} s{sl}")
 
 
+@pytest.mark.parametrize("n_ant,grid_n", [(128, 64), (129, 64), (256, 128), (257, 128)])
+def test_antennas_per_lane_boundary(torch, moff, n_ant, grid_n):
+    """Up to one antenna per lane (n_ant no larger than the workgroup: 128
+    threads at N = 64, 256 at N = 128) and one more: the two kernel instances
+    keep each antenna type's self power differently (one sum per lane, typed
+    after the frame loop, or one running sum per type), and both images agree
+    with the oracle, for every shape variant, with three table types."""
+    kernels = [synth.random_kernel(np.random.default_rng(30 + i), k) for i, k in enumerate((1, 3, 5))]
+    w = synth.random_case(40 + n_ant, n_ant, grid_n, 2, 3, kernels, extent_m=grid_n * 0.35, cell_m=1.0)
+    ref, pbar = oracle_channels(w, range(w.geom.n_chan))
+    with moff.Plan.from_geometry(w.geom, device=0) as p:
+        E = to_dev(torch, w.E)
+        g = to_dev(torch, w.gains)
+        for v in range(p.config(w.E.shape[0])["n_variants"]):
+            p.set_config(variant=v, slices=1)
+            got = p.image(E, g)
+            torch.cuda.synchronize()
+            assert_image_close(got.cpu().numpy(), ref, pbar, label=f"n_ant {n_ant} v{v}")
+
+
 def test_autotune_and_graph_replay(torch, moff):
     """The autotuned configuration is correct, and the fused call captured in a
     HIP graph reproduces the eager result on every replay."""
